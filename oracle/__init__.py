@@ -1,0 +1,226 @@
+"""FP64 CPU oracle of event-by-event pCT reconstruction.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline may use this package; the product path (the HIP library and its
+binding) never imports, loads or calls it, and shares no code with it.
+
+The arithmetic lives in ``oracle.c`` (plain FP64 C):
+  * ``mlp_path``     -- most-likely path polyline of one history (Sec. 2; the
+                        Bayesian path formalism the paper cites, Schulte 2008);
+  * ``polyline_row`` -- Siddon voxel traversal of a polyline, fully merged;
+  * ``trace``        -- the rows of A for a set of histories (Sec. 2: one row
+                        per proton, path lengths in the voxels it touches);
+  * ``drop``         -- block-iterative row projections (DROP, Sec. 2.1), ART
+                        as block size 1;
+  * ``residual``     -- ||Ax - b||_2.
+``roi_means`` is the ROI analysis of Sec. 3.2 / 4.2 (mean RSP per insert).
+
+Parity pins: see tests/test_oracle_*.py.  The full reconstructed image has no
+closed form; it is pinned only piecewise (path, traversal, solver), so the
+image itself is "parity unpinned" beyond those pins.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+FIELDS = ("phi", "t_in", "v_in", "dt_in", "dv_in", "t_out", "v_out", "dt_out", "dv_out", "wepl")
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_SO):
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", _SO + ".tmp",
+                               os.path.join(_HERE, "oracle.c"), "-lm"])
+        os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+class OrcGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("ox", ctypes.c_double), ("oy", ctypes.c_double), ("oz", ctypes.c_double)]
+
+
+class OrcGeom(ctypes.Structure):
+    _fields_ = [("u_in", ctypes.c_double), ("u_out", ctypes.c_double), ("hull_a", ctypes.c_double),
+                ("hull_b", ctypes.c_double), ("hull_zmin", ctypes.c_double), ("hull_zmax", ctypes.c_double),
+                ("step", ctypes.c_double), ("highland_log", ctypes.c_int32), ("n_poly", ctypes.c_int32),
+                ("poly", ctypes.c_double * 8), ("E0", ctypes.c_double), ("X0", ctypes.c_double)]
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        lib = ctypes.CDLL(_SO)
+        lib.orc_mlp_path.restype = ctypes.c_int
+        lib.orc_mlp_path.argtypes = [ctypes.POINTER(OrcGeom), _dp, ctypes.c_int, _dp, _dp, _dp]
+        lib.orc_polyline_row.restype = ctypes.c_int64
+        lib.orc_polyline_row.argtypes = [ctypes.POINTER(OrcGrid), ctypes.c_int32, _dp, _i32p, _dp, ctypes.c_int64,
+                                         _dp]
+        lib.orc_trace.restype = ctypes.c_int64
+        lib.orc_trace.argtypes = [ctypes.POINTER(OrcGrid), ctypes.POINTER(OrcGeom), ctypes.c_int64,
+                                  ctypes.POINTER(ctypes.POINTER(ctypes.c_float)), _i64p, _i32p, _dp, _dp,
+                                  ctypes.c_int32]
+        lib.orc_residual.restype = ctypes.c_double
+        lib.orc_residual.argtypes = [ctypes.c_int64, _i64p, _i32p, _dp, _dp, _dp]
+        lib.orc_drop.restype = ctypes.c_int
+        lib.orc_drop.argtypes = [ctypes.c_int64, _i64p, _i32p, _dp, _dp, _dp, _i64p, ctypes.c_int64,
+                                 ctypes.c_double, ctypes.POINTER(ctypes.c_uint8), ctypes.c_int64, ctypes.c_int32,
+                                 _dp, _dp, ctypes.c_int32]
+        _lib = lib
+    return _lib
+
+
+def _threads(t):
+    if t:
+        return t
+    n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, min(n, 16))
+
+
+def make_grid(nx, ny, nz, dx, dy, dz, ox, oy, oz) -> OrcGrid:
+    return OrcGrid(nx, ny, nz, dx, dy, dz, ox, oy, oz)
+
+
+def make_geom(u_in, u_out, hull_a, hull_b, hull_zmin, hull_zmax, step, poly, highland_log=True,
+              E0=13.6, X0=360.8) -> OrcGeom:
+    g = OrcGeom()
+    g.u_in, g.u_out = u_in, u_out
+    g.hull_a, g.hull_b, g.hull_zmin, g.hull_zmax = hull_a, hull_b, hull_zmin, hull_zmax
+    g.step = step
+    g.highland_log = 1 if highland_log else 0
+    poly = list(poly)
+    if len(poly) > 8:
+        raise ValueError("at most 8 prior coefficients")
+    g.n_poly = len(poly)
+    for q, c in enumerate(poly):
+        g.poly[q] = float(c)
+    g.E0, g.X0 = E0, X0
+    return g
+
+
+def mlp_path(geom: OrcGeom, hist_row) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """(u, t, v) samples of the most-likely path of one history (10 values)."""
+    lib = _load()
+    h = np.ascontiguousarray(np.asarray(hist_row, dtype=np.float64))
+    cap = 4096
+    while True:
+        u = np.empty(cap)
+        t = np.empty(cap)
+        v = np.empty(cap)
+        n = lib.orc_mlp_path(ctypes.byref(geom), h.ctypes.data_as(_dp), cap, u.ctypes.data_as(_dp),
+                             t.ctypes.data_as(_dp), v.ctypes.data_as(_dp))
+        if n >= 0:
+            return u[:n], t[:n], v[:n]
+        cap = -n
+
+
+def polyline_row(grid: OrcGrid, xyz) -> tuple[np.ndarray, np.ndarray, float]:
+    """(idx ascending, lengths, ||a||^2) of a polyline given in the object frame."""
+    lib = _load()
+    P = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).reshape(-1, 3))
+    cnt = lib.orc_polyline_row(ctypes.byref(grid), P.shape[0], P.ctypes.data_as(_dp), None, None, 0, None)
+    idx = np.empty(max(cnt, 1), dtype=np.int32)
+    ln = np.empty(max(cnt, 1))
+    n2 = ctypes.c_double()
+    lib.orc_polyline_row(ctypes.byref(grid), P.shape[0], P.ctypes.data_as(_dp), idx.ctypes.data_as(_i32p),
+                         ln.ctypes.data_as(_dp), cnt, ctypes.byref(n2))
+    return idx[:cnt], ln[:cnt], n2.value
+
+
+class Rows:
+    """CSR rows of A in FP64: row_ptr [n+1], idx [nnz] ascending per row, len [nnz], norm2 [n]."""
+
+    def __init__(self, row_ptr, idx, length, norm2):
+        self.row_ptr, self.idx, self.len, self.norm2 = row_ptr, idx, length, norm2
+
+    @property
+    def n(self):
+        return len(self.row_ptr) - 1
+
+    def row(self, i):
+        a, b = self.row_ptr[i], self.row_ptr[i + 1]
+        return self.idx[a:b], self.len[a:b]
+
+
+def _hist_ptrs(hist: dict):
+    arrs = [np.ascontiguousarray(hist[k], dtype=np.float32) for k in FIELDS]
+    fp = ctypes.POINTER(ctypes.c_float)
+    arr_t = fp * len(FIELDS)
+    return arrs, arr_t(*[a.ctypes.data_as(fp) for a in arrs])
+
+
+def trace(grid: OrcGrid, geom: OrcGeom, hist: dict, threads: int | None = None) -> Rows:
+    lib = _load()
+    arrs, ptrs = _hist_ptrs(hist)
+    n = len(arrs[0])
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    nnz = lib.orc_trace(ctypes.byref(grid), ctypes.byref(geom), n, ptrs, row_ptr.ctypes.data_as(_i64p), None, None,
+                        None, _threads(threads))
+    idx = np.empty(max(nnz, 1), dtype=np.int32)
+    ln = np.empty(max(nnz, 1))
+    n2 = np.empty(n)
+    lib.orc_trace(ctypes.byref(grid), ctypes.byref(geom), n, ptrs, row_ptr.ctypes.data_as(_i64p),
+                  idx.ctypes.data_as(_i32p), ln.ctypes.data_as(_dp), n2.ctypes.data_as(_dp), _threads(threads))
+    return Rows(row_ptr, idx[:nnz], ln[:nnz], n2)
+
+
+def residual(rows: Rows, b, x) -> float:
+    lib = _load()
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return lib.orc_residual(rows.n, rows.row_ptr.ctypes.data_as(_i64p), rows.idx.ctypes.data_as(_i32p),
+                            rows.len.ctypes.data_as(_dp), b.ctypes.data_as(_dp), x.ctypes.data_as(_dp))
+
+
+def drop(rows: Rows, b, x0, order, block: int, lam: float, sweeps: int, mask=None,
+         threads: int | None = None) -> tuple[np.ndarray, np.ndarray]:
+    """Block-iterative projections (block = 1 is ART).  Returns (x, residual per sweep)."""
+    lib = _load()
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.array(x0, dtype=np.float64, copy=True)
+    order = np.ascontiguousarray(order, dtype=np.int64)
+    if len(order) != rows.n:
+        raise ValueError("order must be a permutation of all rows")
+    res = np.empty(max(sweeps, 1))
+    mptr = None
+    if mask is not None:
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        mptr = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    rc = lib.orc_drop(rows.n, rows.row_ptr.ctypes.data_as(_i64p), rows.idx.ctypes.data_as(_i32p),
+                      rows.len.ctypes.data_as(_dp), rows.norm2.ctypes.data_as(_dp), b.ctypes.data_as(_dp),
+                      order.ctypes.data_as(_i64p), block, lam, mptr, len(x), sweeps, x.ctypes.data_as(_dp),
+                      res.ctypes.data_as(_dp), _threads(threads))
+    if rc != 0:
+        raise ValueError("bad block size")
+    return x, res[:sweeps]
+
+
+def roi_means(x, labels, n_labels: int) -> np.ndarray:
+    """Mean of x over each label 1..n_labels (ROI analysis)."""
+    x = np.asarray(x, dtype=np.float64)
+    sums = np.bincount(labels, weights=x, minlength=n_labels + 1)[1:n_labels + 1]
+    cnts = np.bincount(labels, minlength=n_labels + 1)[1:n_labels + 1]
+    return sums / np.maximum(cnts, 1)
+
+
+def rsp_error(x, labels, true_rsp) -> float:
+    """max_k |ROI mean_k - true_k| / true_k."""
+    m = roi_means(x, labels, len(true_rsp))
+    return float(np.max(np.abs(m - true_rsp) / true_rsp))

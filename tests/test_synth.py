@@ -1,0 +1,99 @@
+"""Checks of the synthetic input generator (input data only)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+
+def _philox(ctr, key):
+    import ctypes
+    lib = synth._load()
+    c = (ctypes.c_uint32 * 4)(*ctr)
+    k = (ctypes.c_uint32 * 2)(*key)
+    o = (ctypes.c_uint32 * 4)()
+    lib.pctgen_philox4x32_10(c, k, o)
+    return list(o)
+
+
+def test_philox_known_answers():
+    # Known-answer vectors of Philox4x32-10 (Salmon et al. 2011, Random123 distribution)
+    assert _philox([0, 0, 0, 0], [0, 0]) == [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
+    assert _philox([0xFFFFFFFF] * 4, [0xFFFFFFFF] * 2) == [0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD]
+    assert _philox([0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344], [0xA4093822, 0x299F31D0]) == \
+        [0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1]
+
+
+def test_deterministic_and_threads():
+    c = synth.config(1)
+    a = synth.generate(c, n=3000, threads=1)
+    b = synth.generate(c, n=3000, threads=4)
+    for k in synth.HIST_FIELDS:
+        assert np.array_equal(a[k], b[k])
+    # a slice equals the same part of a longer run
+    s = synth.generate(c, n=1000, start=1000, threads=2)
+    for k in synth.HIST_FIELDS:
+        assert np.array_equal(s[k], a[k][1000:2000])
+
+
+def test_straight_no_scatter_chord():
+    """No scattering, no noise: exit state is the straight extrapolation and
+    the WEPL is RSP x chord for a homogeneous cylinder."""
+    c = synth.config(1)
+    c.phantom = synth.Phantom(c.phantom.body, [])
+    c.beam.scatter = False
+    c.beam.wepl_sigma = 0.0
+    h = synth.generate(c, n=2000)
+    L = c.beam.u_out - c.beam.u_in
+    assert np.allclose(h["t_out"], h["t_in"] + h["dt_in"] * L, atol=2e-4)
+    assert np.allclose(h["dt_out"], h["dt_in"])
+    R = c.phantom.body.ax[0]
+    for i in range(200):
+        phi, t0, v0, st, sv = (float(h[k][i]) for k in ("phi", "t_in", "v_in", "dt_in", "dv_in"))
+        # chord of the line u -> (t0 + st (u - u_in), v0 + sv (u - u_in)) in the cylinder r=R, |z|<=7
+        T = t0 - st * c.beam.u_in
+        A = 1 + st * st
+        B = 2 * st * T
+        C = T * T - R * R
+        disc = B * B - 4 * A * C
+        ua, ub = (-B - math.sqrt(disc)) / (2 * A), (-B + math.sqrt(disc)) / (2 * A)
+        V = v0 - sv * c.beam.u_in
+        if sv != 0:
+            za, zb = sorted(((-7 - V) / sv, (7 - V) / sv))
+            ua, ub = max(ua, za), min(ub, zb)
+        chord = max(0.0, ub - ua) * math.sqrt(1 + st * st + sv * sv)
+        assert h["wepl"][i] == pytest.approx(chord, abs=2e-4)
+
+
+def test_highland_angle_spread():
+    """Thin water slab (40 mm): the exit-angle variance equals the integral
+    of the Fermi-Eyges scattering power, (13.6 / beta p)^2 / X0 times the
+    Highland logarithmic factor, over the slab (statistical, 3%)."""
+    from scipy.integrate import quad
+    c = synth.config(1)
+    half = 20.0
+    c.phantom = synth.Phantom(synth.Shape(1, (0, 0, 0), (half, 1000.0, 100.0), 0.0, -100.0, 100.0, 1.0), [])
+    c.beam.n_angles = 1
+    c.beam.t_half = 0.5
+    c.beam.v_half = 0.5
+    c.beam.slope_sigma = 1e-12
+    c.beam.u_in, c.beam.u_out = -30.0, 30.0
+    c.beam.wepl_sigma = 0.0
+    n = 40000
+    h = synth.generate(c, n=n)
+    R0 = synth.BK_ALPHA * c.beam.E_kin ** synth.BK_P
+
+    def power(w):
+        E = ((R0 - w) / synth.BK_ALPHA) ** (1.0 / synth.BK_P)
+        bp = (E * E + 2 * E * synth.M_PROTON) / (E + synth.M_PROTON)
+        return (synth.E0_HIGHLAND / bp) ** 2 / synth.X0_WATER
+
+    kappa = (1.0 + 0.038 * math.log(2 * half / synth.X0_WATER)) ** 2
+    expect = kappa * quad(power, 0.0, 2 * half)[0]
+    for k in ("dt_out", "dv_out"):
+        var = np.var(h[k].astype(np.float64))
+        assert var == pytest.approx(expect, rel=0.03)
+    # path length exceeds the slab thickness by the small-angle secant excess only
+    w = h["wepl"].astype(np.float64)
+    assert np.all(w >= 2 * half - 1e-4) and np.mean(w - 2 * half) < 5e-3 and np.max(w) < 2 * half + 0.1
