@@ -1,0 +1,186 @@
+/*
+ * pct.h -- C ABI of the MI355X event-by-event proton CT reconstruction library
+ * (libpct.so).
+ *
+ * The problem (paper Sec. 2): N proton histories, each with an entry position
+ * and direction measured by the upstream tracker pair, an exit position and
+ * direction measured by the downstream pair, and a water-equivalent path
+ * length (WEPL).  The object is a rectangular grid of M voxels whose relative
+ * stopping power (RSP) x is sought.  Each proton's most-likely path (MLP)
+ * through the object gives one row of the sparse matrix A: the path lengths
+ * in the voxels it touches.  The WEPL values form b, and Ax = b is solved by
+ * block-iterative row projections (DROP, Sec. 2.1), ART being the block size
+ * one case.  (The paper writes A as M x N with one column per proton; with b
+ * of length N and x of length M, this library stores A as N x M, one row per
+ * proton.)
+ *
+ * Conventions for every entry point:
+ *   - Pointers documented as "device" are HIP device memory owned by the
+ *     caller; the library never allocates device memory: scratch space comes
+ *     from the caller's `workspace` of pct_workspace_size() bytes.
+ *   - `stream` is a hipStream_t (NULL = the default stream); all device work
+ *     is enqueued on it.  Calls that must read a device value on the host
+ *     (row totals, residuals, device status) synchronise that stream.
+ *   - Argument errors are detected on the host before any launch; then nothing
+ *     is modified and PCT_EINVAL is returned.  Errors found on the device are
+ *     reported by the next call that synchronises.
+ *   - pct_last_error() gives a thread-local message for the last failure.
+ *   - No C++ exception crosses this interface.
+ */
+#ifndef PCT_H
+#define PCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PCT_OK = 0,
+    PCT_EINVAL = -1,      /* bad argument (checked on the host, nothing modified) */
+    PCT_ENOMEM = -2,      /* workspace smaller than pct_workspace_size() */
+    PCT_EDEVICE = -3,     /* a HIP call failed, or a device-side bound was exceeded */
+    PCT_EROWCAP = -4,     /* cached rows do not fit in pct_rows.cap_nnz */
+    PCT_ENONFINITE = -5   /* some histories hold NaN/Inf; their rows were left empty */
+} pct_status;
+
+/* Voxel grid (Sec. 2: a discrete rectangular grid of M voxels, x an
+ * M-element linearised array).  Voxel (i, j, k) covers
+ * [o + i d, o + (i + 1) d) on each axis (half-open); its linear index is
+ * (k * ny + j) * nx + i.  Object frame in mm, isocentre at the origin. */
+typedef struct {
+    int32_t nx, ny, nz;
+    float dx, dy, dz;
+    float ox, oy, oz;
+} pct_grid;
+
+/* Scanner geometry and the scattering prior of the most-likely path.
+ * Beam frame for gantry angle phi: u along (cos phi, sin phi, 0), t along
+ * (-sin phi, cos phi, 0), v along z.  The tracker planes sit at u = u_in and
+ * u = u_out.  The object hull is the elliptic cylinder (x/hull_a)^2 +
+ * (y/hull_b)^2 <= 1, hull_zmin <= z <= hull_zmax; the path is straight
+ * outside it and most-likely inside it, sampled every <= step_mm
+ * (0 < step_mm <= min(dx, dy, dz)).  The prior's 1/(beta p)^2 is the
+ * polynomial sum_n poly[n] s^n (MeV^-2) in depth s (mm) from the hull entry;
+ * highland_log = 1 multiplies each covariance by (1 + 0.038 ln(d / X0_mm))^2
+ * for its interval length d.  E0_MeV scales both covariances alike and does
+ * not change the path; it is kept for completeness.  path_fp32 = 0 computes
+ * path positions in FP64 (coordinates good to ~1e-12 mm); 1 computes them in
+ * FP32 (reduced-precision variant, ~1e-5 mm at 100 mm from the isocentre);
+ * the voxel walk uses the same precision on sub-voxel coordinates. */
+typedef struct {
+    float u_in, u_out;
+    float hull_a, hull_b, hull_zmin, hull_zmax;
+    float step_mm;
+    int32_t highland_log;
+    int32_t n_poly;          /* 1..8 */
+    int32_t path_fp32;       /* 0 or 1 */
+    int32_t reserved;        /* must be 0 */
+    double poly[8];
+    double E0_MeV, X0_mm;
+} pct_geom;
+
+/* Proton histories (Sec. 2: entry and exit positions and directions from the
+ * two tracker pairs, WEPL from the range detector), structure of arrays,
+ * float32, device memory, length n each.  Positions t, v at the tracker
+ * planes (mm), directions as slopes dt/du, dv/du, WEPL in mm (this is b). */
+typedef struct {
+    int64_t n;
+    const float *phi, *t_in, *v_in, *dt_in, *dv_in;
+    const float *t_out, *v_out, *dt_out, *dv_out, *wepl;
+} pct_histories;
+
+/* Cached rows of A (CSR).  Row i belongs to history i.  Entries of a row
+ * follow the path from entry to exit; each voxel appears at most once.
+ * len_dtype 0: float32 lengths (mm); 1: float16 lengths in units of
+ * min(dx, dy, dz).  norm2[i] = sum of squared lengths (mm^2), FP64, computed
+ * from the float32 lengths before any float16 rounding.  All arrays device,
+ * caller-owned: row_ptr [n_rows + 1], idx/len [cap_nnz], norm2 [n_rows].
+ * `nnz` is written by pct_mlp_trace (host field). */
+typedef struct {
+    int64_t n_rows;
+    int64_t cap_nnz;
+    int64_t nnz;
+    int64_t *row_ptr;
+    int32_t *idx;
+    void *len;
+    int32_t len_dtype;
+    double *norm2;
+} pct_rows;
+
+/* Block-iterative solver parameters (Sec. 2.1).  Rows are visited in the
+ * order `order` (device int64 [n], a permutation of 0..n-1; NULL = identity)
+ * in consecutive blocks of block_size rows (the last block may be short).
+ * algo 1 (DROP): for each block, with x fixed at its block-start value,
+ *   r_i = (b_i - a_i.x) / ||a_i||^2, x_j += lambda * sum_i r_i a_ij / s_j,
+ *   s_j = number of rows of the block that touch voxel j.
+ * algo 0 (ART): the same with block_size 1, rows strictly one after another
+ *   (cached rows only).
+ * hull_mask (device uint8 [M], NULL = none): voxels with 0 are held at 0.
+ * n_sweeps: passes over all blocks (Sec. 2.1: a fixed iteration count). */
+typedef struct {
+    int32_t algo;
+    int64_t block_size;
+    float lambda;            /* 0 < lambda < 2 */
+    int32_t n_sweeps;
+    const int64_t *order;
+    const uint8_t *hull_mask;
+} pct_sweep_params;
+
+/* Bytes of scratch that the calls below need for a grid, solver and history
+ * count.  `fused` = 1 when rows are recomputed in every sweep.  The same
+ * workspace may be reused by consecutive calls on one stream. */
+size_t pct_workspace_size(const pct_grid *grid, const pct_geom *geom, const pct_sweep_params *params,
+                          int64_t n_hist, int32_t fused);
+
+/* Rows of A for all histories (Sec. 2: MLP per proton, then the path length
+ * in each voxel it touches).  Two passes: count, then fill.  If rows->idx is
+ * NULL only row_ptr and rows->nnz are produced (a sizing call).  If the total
+ * exceeds rows->cap_nnz, row_ptr and nnz are written, nothing else, and
+ * PCT_EROWCAP is returned.  Histories with NaN/Inf get empty rows and the call
+ * returns PCT_ENONFINITE after finishing the rest.  Synchronises `stream`. */
+pct_status pct_mlp_trace(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist,
+                         pct_rows *rows, void *workspace, size_t ws_bytes, void *stream);
+
+/* One sweep of the block-iterative solver over all histories (Sec. 2.1),
+ * updating x (device float32 [M]) in place.  rows != NULL: cached rows from
+ * pct_mlp_trace; rows == NULL: every row is recomputed from the histories
+ * inside the sweep and never stored.  b is hist->wepl.  resid_out (device
+ * double, or NULL): ||Ax - b||_2 over non-empty rows after the sweep, FP64;
+ * it is set to NaN if the device found an error during the sweep (an order
+ * entry outside [0, n), a cached voxel index outside [0, M), a row bound
+ * exceeded).  params->n_sweeps is ignored (one sweep).  Asynchronous. */
+pct_status pct_project_sweep(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist,
+                             const pct_rows *rows, float *x, const pct_sweep_params *params, double *resid_out,
+                             void *workspace, size_t ws_bytes, void *stream);
+
+/* Whole reconstruction: if rows != NULL, trace into them first (as
+ * pct_mlp_trace), then params->n_sweeps sweeps from x_inout (the initial
+ * guess, Sec. 2.1).  resid_host (host double [n_sweeps], or NULL): residual
+ * after each sweep.  Synchronises `stream`. */
+pct_status pct_reconstruct(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist,
+                           const pct_sweep_params *params, pct_rows *rows, float *x_inout, double *resid_host,
+                           void *workspace, size_t ws_bytes, void *stream);
+
+/* ||Ax - b||_2 over non-empty rows (FP64) into *out (device double).
+ * rows == NULL recomputes the rows.  Asynchronous. */
+pct_status pct_residual(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist,
+                        const pct_rows *rows, const float *x, double *out, void *workspace, size_t ws_bytes,
+                        void *stream);
+
+/* ROI analysis (Sec. 3.2, 4.2): for labels 1..n_labels, sums[l-1] = sum of
+ * x over voxels with label l (FP64), counts[l-1] = their number.  labels
+ * device uint8 [M] (0 = no ROI), sums device double [n_labels], counts
+ * device int64 [n_labels]; n_labels <= 255.  Asynchronous. */
+pct_status pct_roi_stats(const float *x, const uint8_t *labels, int64_t M, int32_t n_labels, double *sums,
+                         int64_t *counts, void *stream);
+
+/* Message for the last failing call on this thread (empty if none). */
+const char *pct_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCT_H */

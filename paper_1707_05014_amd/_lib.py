@@ -1,0 +1,112 @@
+"""ctypes mirror of include/pct.h and the loader of libpct.so.
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+kernels of libpct.so.  If the library is missing this module raises; there
+is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpct.so")
+
+PCT_OK = 0
+PCT_EINVAL = -1
+PCT_ENOMEM = -2
+PCT_EDEVICE = -3
+PCT_EROWCAP = -4
+PCT_ENONFINITE = -5
+STATUS_NAMES = {0: "PCT_OK", -1: "PCT_EINVAL", -2: "PCT_ENOMEM", -3: "PCT_EDEVICE", -4: "PCT_EROWCAP",
+                -5: "PCT_ENONFINITE"}
+
+
+class pct_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_float), ("dy", ctypes.c_float), ("dz", ctypes.c_float),
+                ("ox", ctypes.c_float), ("oy", ctypes.c_float), ("oz", ctypes.c_float)]
+
+
+class pct_geom(ctypes.Structure):
+    _fields_ = [("u_in", ctypes.c_float), ("u_out", ctypes.c_float),
+                ("hull_a", ctypes.c_float), ("hull_b", ctypes.c_float),
+                ("hull_zmin", ctypes.c_float), ("hull_zmax", ctypes.c_float),
+                ("step_mm", ctypes.c_float), ("highland_log", ctypes.c_int32),
+                ("n_poly", ctypes.c_int32), ("path_fp32", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("poly", ctypes.c_double * 8),
+                ("E0_MeV", ctypes.c_double), ("X0_mm", ctypes.c_double)]
+
+
+_fp = ctypes.c_void_p
+
+
+class pct_histories(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("phi", _fp), ("t_in", _fp), ("v_in", _fp), ("dt_in", _fp),
+                ("dv_in", _fp), ("t_out", _fp), ("v_out", _fp), ("dt_out", _fp), ("dv_out", _fp),
+                ("wepl", _fp)]
+
+
+class pct_rows(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("cap_nnz", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", _fp), ("idx", _fp), ("len", _fp), ("len_dtype", ctypes.c_int32),
+                ("norm2", _fp)]
+
+
+class pct_sweep_params(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("block_size", ctypes.c_int64), ("lambda_", ctypes.c_float),
+                ("n_sweeps", ctypes.c_int32), ("order", _fp), ("hull_mask", _fp)]
+
+
+EXPORTS = ("pct_workspace_size", "pct_mlp_trace", "pct_project_sweep", "pct_reconstruct", "pct_residual",
+           "pct_roi_stats", "pct_last_error")
+
+_lib = None
+
+
+class PctError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def load(path: str | None = None):
+    """Load libpct.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} is missing: build it with paper_1707_05014_amd.build.build() "
+                          f"(or __graft_entry__.build())")
+    lib = ctypes.CDLL(p)
+    P = ctypes.POINTER
+    lib.pct_workspace_size.restype = ctypes.c_size_t
+    lib.pct_workspace_size.argtypes = [P(pct_grid), P(pct_geom), P(pct_sweep_params), ctypes.c_int64,
+                                       ctypes.c_int32]
+    lib.pct_mlp_trace.restype = ctypes.c_int
+    lib.pct_mlp_trace.argtypes = [P(pct_grid), P(pct_geom), P(pct_histories), P(pct_rows), _fp, ctypes.c_size_t,
+                                  _fp]
+    lib.pct_project_sweep.restype = ctypes.c_int
+    lib.pct_project_sweep.argtypes = [P(pct_grid), P(pct_geom), P(pct_histories), P(pct_rows), _fp,
+                                      P(pct_sweep_params), _fp, _fp, ctypes.c_size_t, _fp]
+    lib.pct_reconstruct.restype = ctypes.c_int
+    lib.pct_reconstruct.argtypes = [P(pct_grid), P(pct_geom), P(pct_histories), P(pct_sweep_params), P(pct_rows),
+                                    _fp, P(ctypes.c_double), _fp, ctypes.c_size_t, _fp]
+    lib.pct_residual.restype = ctypes.c_int
+    lib.pct_residual.argtypes = [P(pct_grid), P(pct_geom), P(pct_histories), P(pct_rows), _fp, _fp, _fp,
+                                 ctypes.c_size_t, _fp]
+    lib.pct_roi_stats.restype = ctypes.c_int
+    lib.pct_roi_stats.argtypes = [_fp, _fp, ctypes.c_int64, ctypes.c_int32, _fp, _fp, _fp]
+    lib.pct_last_error.restype = ctypes.c_char_p
+    lib.pct_last_error.argtypes = []
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def check(code: int, allow=(PCT_OK,)) -> int:
+    if code not in allow:
+        msg = load().pct_last_error().decode(errors="replace")
+        raise PctError(code, msg)
+    return code

@@ -1,0 +1,409 @@
+// Device-side construction of one proton's row of A by one wavefront:
+// hull entry/exit, most-likely path samples, voxel walk, row assembly in LDS.
+//
+// Paper Sec. 2: each proton's MLP is estimated from the entry and exit
+// positions and angles; its row of A holds the path length in every voxel the
+// path touches.  The MLP is the Bayesian most-likely path the paper cites
+// (Schulte et al. 2008) written in Kalman-gain form, which stays well
+// conditioned at both ends of the path; the covariance integrals use closed
+// forms of the polynomial prior.  The voxel walk is Amanatides-Woo, one path
+// segment per lane, on sub-voxel local coordinates.
+//
+// The template parameter R is the precision of path positions, of the gain
+// and of the voxel walk's crossing parameters: double gives lengths good to
+// ~1e-12 mm except on near-tangent crossings; float is the reduced precision
+// variant (coordinates good to ~1e-5 mm at 100 mm from the isocentre).  The
+// walk runs on coordinates relative to the segment's first voxel.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pct_internal.h"
+
+namespace pct {
+
+__device__ __forceinline__ int wave_lane() { return __lane_id(); }
+
+// exclusive prefix sum over the 64 lanes
+__device__ __forceinline__ int wave_excl_scan(int v) {
+  const int lane = wave_lane();
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    int y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  return x - v;
+}
+
+__device__ __forceinline__ float wave_sum_f32(float v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+template <typename R> __device__ __forceinline__ R rsqrt_(R v);
+template <> __device__ __forceinline__ float rsqrt_(float v) { return sqrtf(v); }
+template <> __device__ __forceinline__ double rsqrt_(double v) { return sqrt(v); }
+template <typename R> __device__ __forceinline__ R rlog_(R v);
+template <> __device__ __forceinline__ float rlog_(float v) { return __logf(v); }
+template <> __device__ __forceinline__ double rlog_(double v) { return log(v); }
+
+template <typename R> struct Tables;
+template <> struct Tables<double> {
+  __device__ static const double (&cI(const PathParams &P))[3][8] { return P.cI_d; }
+  __device__ static const double (&cF(const PathParams &P))[3][8] { return P.cF_d; }
+};
+template <> struct Tables<float> {
+  __device__ static const float (&cI(const PathParams &P))[3][8] { return P.cI_f; }
+  __device__ static const float (&cF(const PathParams &P))[3][8] { return P.cF_f; }
+};
+
+// Interval [lo, hi] of u on which the line t(u) = t_ref + st (u - u_ref),
+// v(u) = v_ref + sv (u - u_ref) lies in the elliptic-cylinder hull.
+template <typename R>
+__device__ __forceinline__ bool hull_interval(const PathParams &P, R c, R s, R u_ref, R t_ref, R v_ref, R st, R sv,
+                                              R &lo, R &hi) {
+  const R ia2 = (R)P.hull_ia2, ib2 = (R)P.hull_ib2;
+  const R T = t_ref - st * u_ref;
+  const R V = v_ref - sv * u_ref;
+  const R px = c - st * s, qx = -T * s;
+  const R py = s + st * c, qy = T * c;
+  const R A = px * px * ia2 + py * py * ib2;
+  const R B = (R)2 * (px * qx * ia2 + py * qy * ib2);
+  const R C = qx * qx * ia2 + qy * qy * ib2 - (R)1;
+  const R disc = B * B - (R)4 * A * C;
+  if (!(disc > (R)0)) return false;
+  const R sq = rsqrt_<R>(disc);
+  const R q = (R)(-0.5) * (B + (B >= (R)0 ? sq : -sq));
+  R r0 = q / A, r1 = (q != (R)0) ? C / q : r0;
+  lo = r0 < r1 ? r0 : r1;
+  hi = r0 < r1 ? r1 : r0;
+  if (sv != (R)0) {
+    R z0 = ((R)P.hull_zmin - V) / sv, z1 = ((R)P.hull_zmax - V) / sv;
+    R zl = z0 < z1 ? z0 : z1, zh = z0 < z1 ? z1 : z0;
+    lo = lo > zl ? lo : zl;
+    hi = hi < zh ? hi : zh;
+  } else if (V < (R)P.hull_zmin || V > (R)P.hull_zmax) {
+    return false;
+  }
+  return hi > lo;
+}
+
+template <typename R>
+struct ProtonPath {
+  bool valid;
+  int K;                 // segments
+  R u0, L, c, s;         // hull entry, path length along u, cos/sin phi
+  R t0, st0, v0, sv0;    // entry state
+  R dtt, dts, dvt, dvs;  // innovations y2 - R(L) y0 per plane
+  R FL[3];               // F_p(L), p = 0, 1, 2 (see mlp_point)
+};
+
+// Horner: d^(M+1) * sum_n c[n] d^n
+template <typename R, int M>
+__device__ __forceinline__ R moment(const R (&c)[8], R d) {
+  R acc = (R)0;
+#pragma unroll
+  for (int q = 7; q >= 0; --q) acc = acc * d + c[q];
+  R dp = d;
+#pragma unroll
+  for (int m = 0; m < M; ++m) dp *= d;
+  return acc * dp;
+}
+
+// Per-proton set-up (wave-uniform values, computed redundantly by all lanes).
+// The hull intersections and end states are found in double for both path
+// precisions: they are per proton, and near-tangent lines are ill-conditioned.
+template <typename R>
+__device__ __forceinline__ void setup_path(const PathParams &P, const float h[10], ProtonPath<R> &pp) {
+  pp.valid = false;
+  pp.K = 0;
+  bool fin = true;
+#pragma unroll
+  for (int q = 0; q < 10; ++q) fin = fin && isfinite(h[q]);
+  if (!fin) return;
+  double c, s;
+  sincos((double)h[0], &s, &c);
+  double a0, b0, a2, b2;
+  const double u_in = P.u_in, u_out = P.u_out;
+  if (!hull_interval<double>(P, c, s, u_in, h[1], h[2], h[3], h[4], a0, b0)) return;
+  if (!hull_interval<double>(P, c, s, u_out, h[5], h[6], h[7], h[8], a2, b2)) return;
+  const double u0 = a0, u2 = b2;
+  const double L = u2 - u0;
+  if (!(L > 0.0)) return;
+  int K = (int)ceil(L * (double)P.inv_step - 1e-9);
+  if (K < 1) K = 1;
+  const double st0 = h[3], sv0 = h[4];
+  const double t0 = (double)h[1] + st0 * (u0 - u_in);
+  const double v0 = (double)h[2] + sv0 * (u0 - u_in);
+  const double t2 = (double)h[5] + (double)h[7] * (u2 - u_out);
+  const double v2 = (double)h[6] + (double)h[8] * (u2 - u_out);
+  pp.K = K;
+  pp.c = (R)c;
+  pp.s = (R)s;
+  pp.u0 = (R)u0;
+  pp.L = (R)L;
+  pp.st0 = (R)st0;
+  pp.sv0 = (R)sv0;
+  pp.t0 = (R)t0;
+  pp.v0 = (R)v0;
+  pp.dtt = (R)(t2 - (t0 + st0 * L));
+  pp.dts = (R)((double)h[7] - st0);
+  pp.dvt = (R)(v2 - (v0 + sv0 * L));
+  pp.dvs = (R)((double)h[8] - sv0);
+  const auto &cF = Tables<R>::cF(P);
+  pp.FL[0] = moment<R, 0>(cF[0], pp.L);
+  pp.FL[1] = moment<R, 1>(cF[1], pp.L);
+  pp.FL[2] = moment<R, 2>(cF[2], pp.L);
+  pp.valid = true;
+}
+
+// MLP lateral offsets (t, v) at depth d1 from the hull entry, 0 < d1 < L.
+//   S1 ~ [I2 I1; I1 I0],  I_m = int_0^d1 f(s) (d1 - s)^m ds
+//   S2 ~ [J2 J1; J1 J0],  J_m = int_d1^L f(s) (L - s)^m ds
+//   J_m from F_p(x) = int_0^x f(s) s^p ds by the binomial expansion of (L - s)^m
+// (the common factor E0^2/X0 cancels in the gain).
+template <typename R>
+__device__ __forceinline__ void mlp_point(const PathParams &P, const ProtonPath<R> &pp, R d1, R &t, R &v) {
+  const auto &cI = Tables<R>::cI(P);
+  const auto &cF = Tables<R>::cF(P);
+  const R L = pp.L;
+  const R d2 = L - d1;
+  R I0 = moment<R, 0>(cI[0], d1);
+  R I1 = moment<R, 1>(cI[1], d1);
+  R I2 = moment<R, 2>(cI[2], d1);
+  const R e0 = pp.FL[0] - moment<R, 0>(cF[0], d1);
+  const R e1 = pp.FL[1] - moment<R, 1>(cF[1], d1);
+  const R e2 = pp.FL[2] - moment<R, 2>(cF[2], d1);
+  R J0 = e0;
+  R J1 = L * e0 - e1;
+  R J2 = L * L * e0 - (R)2 * L * e1 + e2;
+  if (P.highland) {
+    const R ix0 = (R)P.inv_X0;
+    R g1 = (R)1 + (R)0.038 * rlog_<R>(d1 * ix0);
+    R g2 = (R)1 + (R)0.038 * rlog_<R>(d2 * ix0);
+    g1 *= g1;
+    g2 *= g2;
+    I0 *= g1; I1 *= g1; I2 *= g1;
+    J0 *= g2; J1 *= g2; J2 *= g2;
+  }
+  // C = R1 S1 R1^T + S2 with R1 = [1 d2; 0 1]
+  const R C00 = d2 * d2 * I0 + (R)2 * d2 * I1 + I2 + J2;
+  const R C01 = d2 * I0 + I1 + J1;
+  const R C11 = I0 + J0;
+  const R det = C00 * C11 - C01 * C01;
+  // first row of S1 R1^T C^-1
+  const R A0 = d2 * I1 + I2, A1 = I1;
+  const R inv = (R)1 / det;
+  const R G0 = (A0 * C11 - A1 * C01) * inv;
+  const R G1 = (A1 * C00 - A0 * C01) * inv;
+  t = pp.t0 + pp.st0 * d1 + (G0 * pp.dtt + G1 * pp.dts);
+  v = pp.v0 + pp.sv0 * d1 + (G0 * pp.dvt + G1 * pp.dvs);
+}
+
+// Voxel walk of one segment given in local coordinates: (px,py,pz) in [0,1]^3
+// relative to voxel (bx,by,bz), end point (qx,qy,qz) in the same frame,
+// physical length seg.  Emits up to kMaxPieces (voxel, length) pieces;
+// returns the count, or kMaxPieces + 1 on overflow.  W is the precision of
+// the crossing parameters.
+template <typename W>
+__device__ __forceinline__ int walk_segment(const PathParams &P, int bx, int by, int bz, W px, W py, W pz, W qx,
+                                            W qy, W qz, W seg, int vox[kMaxPieces], float len[kMaxPieces]) {
+  const W dx = qx - px, dy = qy - py, dz = qz - pz;
+  int ix = bx, iy = by, iz = bz;
+  const W INF = (W)3.0e38f;
+  int sx = 0, sy = 0, sz = 0;
+  W tx = INF, ty = INF, tz = INF, ddx = INF, ddy = INF, ddz = INF;
+  if (dx > (W)0) { sx = 1; tx = ((W)1 - px) / dx; ddx = (W)1 / dx; }
+  else if (dx < (W)0) { sx = -1; tx = -px / dx; ddx = (W)(-1) / dx; }
+  if (dy > (W)0) { sy = 1; ty = ((W)1 - py) / dy; ddy = (W)1 / dy; }
+  else if (dy < (W)0) { sy = -1; ty = -py / dy; ddy = (W)(-1) / dy; }
+  if (dz > (W)0) { sz = 1; tz = ((W)1 - pz) / dz; ddz = (W)1 / dz; }
+  else if (dz < (W)0) { sz = -1; tz = -pz / dz; ddz = (W)(-1) / dz; }
+  W tc = (W)0;
+  int np = 0;
+  const W eps = (W)P.eps_len;
+  for (int it = 0; it < 3 * kMaxPieces; ++it) {
+    W tn = tx < ty ? tx : ty;
+    tn = tn < tz ? tn : tz;
+    tn = tn < (W)1 ? tn : (W)1;
+    const W l = (tn - tc) * seg;
+    if (l > eps && ix >= 0 && iy >= 0 && iz >= 0 && ix < P.nx && iy < P.ny && iz < P.nz) {
+      if (np == kMaxPieces) return kMaxPieces + 1;
+      const int j = (iz * P.ny + iy) * P.nx + ix;
+#pragma unroll
+      for (int q = 0; q < kMaxPieces; ++q)
+        if (q == np) { vox[q] = j; len[q] = (float)l; }
+      ++np;
+    }
+    if (tn >= (W)1) return np;
+    tc = tn;
+    if (tx <= ty && tx <= tz) { ix += sx; tx += ddx; }
+    else if (ty <= tz) { iy += sy; ty += ddy; }
+    else { iz += sz; tz += ddz; }
+  }
+  return kMaxPieces + 1;
+}
+
+// Build the row of one proton in the wavefront's LDS slice (s_vox, s_len,
+// s_aux of P.emax entries each).  Returns the entry count (wave-uniform);
+// on a bound violation sets `status` bits and returns 0.
+template <typename R>
+__device__ int build_row(const PathParams &P, const float h[10], int *s_vox, float *s_len, int *s_aux,
+                         uint32_t *status) {
+  const int lane = wave_lane();
+  ProtonPath<R> pp;
+  setup_path<R>(P, h, pp);
+  if (!pp.valid) return 0;
+  if (pp.K > P.kmax) {
+    if (lane == 0) atomicOr(status, kStOverflow);
+    return 0;
+  }
+  const int K = pp.K;
+  const R du = pp.L / (R)K;
+  const R gox = (R)P.ox, goy = (R)P.oy, goz = (R)P.oz;
+  const R gix = (R)P.idx, giy = (R)P.idy, giz = (R)P.idz;
+  int count = 0;
+  int carry_vox = -1;
+  for (int base = 0; base < K; base += kSegPerRound) {
+    const int k = base + lane;
+    R wx = 0, wy = 0, wz = 0;
+    if (k <= K) {
+      R t, v, d1;
+      if (k == 0) {
+        t = pp.t0; v = pp.v0; d1 = 0;
+      } else if (k == K) {
+        t = pp.t0 + pp.st0 * pp.L + pp.dtt;
+        v = pp.v0 + pp.sv0 * pp.L + pp.dvt;
+        d1 = pp.L;
+      } else {
+        d1 = (R)k * du;
+        mlp_point<R>(P, pp, d1, t, v);
+      }
+      const R u = pp.u0 + d1;
+      wx = u * pp.c - t * pp.s;
+      wy = u * pp.s + t * pp.c;
+      wz = v;
+    }
+    const R gx = (wx - gox) * gix, gy = (wy - goy) * giy, gz = (wz - goz) * giz;
+    const R ngx = __shfl_down(gx, 1, kWave), ngy = __shfl_down(gy, 1, kWave), ngz = __shfl_down(gz, 1, kWave);
+    const R nwx = __shfl_down(wx, 1, kWave), nwy = __shfl_down(wy, 1, kWave), nwz = __shfl_down(wz, 1, kWave);
+    int vox[kMaxPieces];
+    float len[kMaxPieces];
+    int np = 0;
+    if (lane < kSegPerRound && k < K) {
+      const R ex = nwx - wx, ey = nwy - wy, ez = nwz - wz;
+      const R seg = rsqrt_<R>(ex * ex + ey * ey + ez * ez);
+      const R fx = floor(gx), fy = floor(gy), fz = floor(gz);
+      np = walk_segment<R>(P, (int)fx, (int)fy, (int)fz, gx - fx, gy - fy, gz - fz, ngx - fx, ngy - fy,
+                           ngz - fz, seg, vox, len);
+    }
+    const bool bad = np > kMaxPieces;
+    if (__ballot(bad)) {
+      if (lane == 0) atomicOr(status, kStOverflow);
+      return 0;
+    }
+    int first = -1, last = -1;
+    float first_len = 0.0f;
+#pragma unroll
+    for (int q = 0; q < kMaxPieces; ++q) {
+      if (q == 0 && np > 0) { first = vox[0]; first_len = len[0]; }
+      if (q == np - 1) last = vox[q];
+    }
+    int prev_last = __shfl_up(last, 1, kWave);
+    if (lane == 0) prev_last = carry_vox;
+    const bool merge = np > 0 && prev_last >= 0 && first == prev_last;
+    const int ne = np - (merge ? 1 : 0);
+    const int pos = wave_excl_scan(ne);
+    const int total = __shfl(pos + ne, kWave - 1, kWave);
+    if (count + total > P.emax) {
+      if (lane == 0) atomicOr(status, kStOverflow);
+      return 0;
+    }
+    // new entries
+    const int at = count + pos - (merge ? 1 : 0);
+#pragma unroll
+    for (int q = 0; q < kMaxPieces; ++q) {
+      if (q < np && !(q == 0 && merge)) {
+        s_vox[at + q] = vox[q];
+        s_len[at + q] = len[q];
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // a first piece in the same voxel as the previous piece extends that entry
+    if (merge) atomicAdd(&s_len[count + pos - 1], first_len);
+    count += total;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    carry_vox = count > 0 ? s_vox[count - 1] : -1;
+  }
+  // voxels revisited after a short excursion: fold into the first visit
+  bool any = false;
+  for (int e0 = 0; e0 < count; e0 += kWave) {
+    const int e = e0 + lane;
+    int m = -1;
+    if (e < count) {
+      const int v = s_vox[e];
+      const int lo = e - kDedupWindow > 0 ? e - kDedupWindow : 0;
+      for (int f = lo; f <= e - 2; ++f)
+        if (s_vox[f] == v) { m = f; break; }
+      s_aux[e] = m;
+    }
+    any = any || (__ballot(m >= 0) != 0);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (any) {
+    if (lane == 0) {
+      for (int e = 0; e < count; ++e) {
+        int r = s_aux[e];
+        if (r < 0) continue;
+        while (s_aux[r] >= 0) r = s_aux[r];
+        s_len[r] += s_len[e];
+        s_vox[e] = -1;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    int out = 0;
+    for (int e0 = 0; e0 < count; e0 += kWave) {
+      const int e = e0 + lane;
+      int v = -1;
+      float l = 0.f;
+      if (e < count) { v = s_vox[e]; l = s_len[e]; }
+      const int keep = v >= 0 ? 1 : 0;
+      const int p = wave_excl_scan(keep);
+      const int tot = __shfl(p + keep, kWave - 1, kWave);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (keep) { s_vox[out + p] = v; s_len[out + p] = l; }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      out += tot;
+    }
+    count = out;
+  }
+  return count;
+}
+
+// dispatch on the path precision chosen at run time (uniform per launch)
+__device__ __forceinline__ int build_row_any(const PathParams &P, const float h[10], int *s_vox, float *s_len,
+                                             int *s_aux, uint32_t *status) {
+  if (P.path_fp32) return build_row<float>(P, h, s_vox, s_len, s_aux, status);
+  return build_row<double>(P, h, s_vox, s_len, s_aux, status);
+}
+
+__device__ __forceinline__ void load_history(const HistPtrs &H, int64_t i, float h[10]) {
+  h[0] = H.phi[i]; h[1] = H.t_in[i]; h[2] = H.v_in[i]; h[3] = H.dt_in[i]; h[4] = H.dv_in[i];
+  h[5] = H.t_out[i]; h[6] = H.v_out[i]; h[7] = H.dt_out[i]; h[8] = H.dv_out[i]; h[9] = H.wepl[i];
+}
+
+}  // namespace pct

@@ -1,0 +1,97 @@
+// Internal interface between the C ABI layer (abi.hip) and the kernels
+// (trace.hip, sweep.hip).  Not installed, not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pct.h"
+
+namespace pct {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kSegPerRound = 63;   // path segments a wavefront traces per round (64 points)
+constexpr int kMaxPieces = 6;      // voxel pieces one segment can yield (<= 4 when step <= voxel)
+constexpr int kDedupWindow = 8;    // look-back for voxels revisited after a short excursion
+
+// status word bits (device)
+constexpr uint32_t kStNonFinite = 1u;
+constexpr uint32_t kStOverflow = 2u;
+constexpr uint32_t kStRowMismatch = 4u;
+constexpr uint32_t kStBadIndex = 8u;   // an order entry or a cached voxel index out of range
+
+// Everything a path kernel needs, precomputed on the host and passed by value.
+struct PathParams {
+  // scanner and hull
+  double u_in, u_out;
+  double hull_ia2, hull_ib2, hull_zmin, hull_zmax;
+  float step, inv_step;
+  int32_t highland;
+  float inv_X0;
+  // prior f(s) = sum_n a_n s^n (zero-padded to 8 terms):
+  //   I_m(d) = int_0^d f(s) (d - s)^m ds = d^(m+1) sum_n cI[m][n] d^n, cI = a_n B(n+1, m+1)
+  //   F_p(x) = int_0^x f(s) s^p ds      = x^(p+1) sum_n cF[p][n] x^n, cF = a_n / (n + p + 1)
+  double cI_d[3][8], cF_d[3][8];
+  float cI_f[3][8], cF_f[3][8];
+  int32_t path_fp32;  // 1: path positions in float (reduced-precision variant)
+  // grid
+  int32_t nx, ny, nz;
+  float dx, dy, dz;
+  double idx, idy, idz, ox, oy, oz;
+  float eps_len;      // pieces shorter than this (mm) are dropped
+  // bounds
+  int32_t kmax;       // max path segments
+  int32_t emax;       // max row entries held in LDS per wavefront
+  int32_t waves_per_block;
+};
+
+struct HistPtrs {
+  const float *phi, *t_in, *v_in, *dt_in, *dv_in, *t_out, *v_out, *dt_out, *dv_out, *wepl;
+};
+
+// workspace layout
+struct Workspace {
+  uint32_t *status;      // [4]
+  float *num;            // [M]
+  uint32_t *cnt;         // [M]
+  double *partials;      // [kMaxPartials]
+  int64_t *scan;         // [scan_len]
+};
+constexpr int64_t kMaxPartials = 1 << 16;
+constexpr int64_t kScanChunk = 4096;
+
+size_t workspace_bytes(int64_t M, int64_t n_hist);
+Workspace carve_workspace(void *base, int64_t M, int64_t n_hist);
+
+// launchers (return hipError_t of the launch)
+hipError_t launch_trace(const PathParams &P, const HistPtrs &H, int64_t n, int mode, int64_t *row_ptr,
+                        int32_t *idx, void *len, int32_t len_dtype, double *norm2, uint32_t *status,
+                        hipStream_t s);
+hipError_t launch_scan_rows(int64_t *row_ptr, int64_t n, int64_t *scan_tmp, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+
+hipError_t launch_mask(float *x, const uint8_t *mask, int64_t M, hipStream_t s);
+hipError_t launch_project_cached(const int64_t *row_ptr, const int32_t *idx, const void *len, int32_t len_dtype,
+                                 float len_unit, const double *norm2, const float *b, const int64_t *order,
+                                 int64_t first, int64_t count, int64_t n, int64_t M, const float *x, float *num,
+                                 uint32_t *cnt, uint32_t *status, hipStream_t s);
+hipError_t launch_project_fused(const PathParams &P, const HistPtrs &H, const int64_t *order, int64_t first,
+                                int64_t count, int64_t n, const float *x, float *num, uint32_t *cnt,
+                                uint32_t *status, hipStream_t s);
+hipError_t launch_apply(float *x, float *num, uint32_t *cnt, const uint8_t *mask, int64_t M, float lambda,
+                        hipStream_t s);
+hipError_t launch_art(const int64_t *row_ptr, const int32_t *idx, const void *len, int32_t len_dtype,
+                      float len_unit, const double *norm2, const float *b, const int64_t *order, int64_t n,
+                      int64_t M, float *x, const uint8_t *mask, float lambda, uint32_t *status, hipStream_t s);
+hipError_t launch_residual_cached(const int64_t *row_ptr, const int32_t *idx, const void *len, int32_t len_dtype,
+                                  float len_unit, const float *b, int64_t n, int64_t M, const float *x,
+                                  double *partials, double *out, hipStream_t s);
+hipError_t launch_residual_fused(const PathParams &P, const HistPtrs &H, int64_t n, const float *x,
+                                 double *partials, uint32_t *status, double *out, hipStream_t s);
+// *out = NaN if any status bit is set (asynchronous error report)
+hipError_t launch_poison_on_status(double *out, const uint32_t *status, hipStream_t s);
+hipError_t launch_roi(const float *x, const uint8_t *labels, int64_t M, int32_t n_labels, double *sums,
+                      int64_t *counts, hipStream_t s);
+
+}  // namespace pct

@@ -1,0 +1,366 @@
+// Block-iterative row projections (paper Sec. 2.1, DROP; ART as the block
+// size one case), the residual ||Ax - b|| and the ROI reduction.
+//
+// For one block B with x fixed at its block-start value:
+//   r_i = (b_i - a_i . x) / ||a_i||^2,  num_j = sum_i r_i a_ij,
+//   s_j = #{i in B : a_ij > 0},         x_j += lambda num_j / s_j.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "path_device.h"
+
+namespace pct {
+
+template <int LD>
+__device__ __forceinline__ float load_len(const void *len, int64_t e, float unit) {
+  if constexpr (LD == 0) {
+    return __builtin_nontemporal_load(reinterpret_cast<const float *>(len) + e);
+  } else {
+    return __half2float(reinterpret_cast<const __half *>(len)[e]) * unit;
+  }
+}
+
+// one wavefront per cached row of the block
+template <int LD>
+__global__ void __launch_bounds__(256) k_project_cached(const int64_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ idx, const void *__restrict__ len,
+                                                        float unit, const double *__restrict__ norm2,
+                                                        const float *__restrict__ b, const int64_t *__restrict__ order,
+                                                        int64_t first, int64_t count, int64_t n, int64_t M,
+                                                        const float *__restrict__ x, float *num, uint32_t *cnt,
+                                                        uint32_t *status) {
+  const int lane = wave_lane();
+  const int64_t q = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (q >= count) return;
+  const int64_t i = order ? order[first + q] : first + q;
+  if ((uint64_t)i >= (uint64_t)n) {
+    if (lane == 0) atomicOr(status, kStBadIndex);
+    return;
+  }
+  const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
+  if (e1 == e0) return;
+  float d = 0.0f;
+  bool bad = false;
+  for (int64_t e = e0 + lane; e < e1; e += kWave) {
+    const int j = idx[e];
+    if ((uint32_t)j >= (uint64_t)M) { bad = true; continue; }
+    d = fmaf(load_len<LD>(len, e, unit), x[j], d);
+  }
+  if (__ballot(bad)) {
+    if (lane == 0) atomicOr(status, kStBadIndex);
+    return;
+  }
+  d = wave_sum_f32(d);
+  const float r = (float)(((double)b[i] - (double)d) / norm2[i]);
+  for (int64_t e = e0 + lane; e < e1; e += kWave) {
+    const int j = idx[e];
+    atomicAdd(&num[j], r * load_len<LD>(len, e, unit));
+    atomicAdd(&cnt[j], 1u);
+  }
+}
+
+// one wavefront per proton of the block: the row is rebuilt in LDS
+__global__ void __launch_bounds__(256) k_project_fused(PathParams P, HistPtrs H, const int64_t *__restrict__ order,
+                                                       int64_t first, int64_t count, int64_t n,
+                                                       const float *__restrict__ x, float *num, uint32_t *cnt,
+                                                       uint32_t *status) {
+  extern __shared__ int smem[];
+  const int wid = threadIdx.x / kWave;
+  const int lane = wave_lane();
+  int *s_vox = smem + wid * 3 * P.emax;
+  float *s_len = reinterpret_cast<float *>(s_vox + P.emax);
+  int *s_aux = s_vox + 2 * P.emax;
+  const int64_t stride = (int64_t)gridDim.x * P.waves_per_block;
+  for (int64_t q = (int64_t)blockIdx.x * P.waves_per_block + wid; q < count; q += stride) {
+    const int64_t i = order ? order[first + q] : first + q;
+    if ((uint64_t)i >= (uint64_t)n) {
+      if (lane == 0) atomicOr(status, kStBadIndex);
+      continue;
+    }
+    float h[10];
+    load_history(H, i, h);
+    const int ne = build_row_any(P, h, s_vox, s_len, s_aux, status);
+    if (ne == 0) continue;
+    float d = 0.0f;
+    double n2 = 0.0;
+    for (int e = lane; e < ne; e += kWave) {
+      const float l = s_len[e];
+      d = fmaf(l, x[s_vox[e]], d);
+      n2 += (double)l * (double)l;
+    }
+    d = wave_sum_f32(d);
+    n2 = wave_sum_f64(n2);
+    const float r = (float)(((double)h[9] - (double)d) / n2);
+    for (int e = lane; e < ne; e += kWave) {
+      const int j = s_vox[e];
+      atomicAdd(&num[j], r * s_len[e]);
+      atomicAdd(&cnt[j], 1u);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_apply(float *__restrict__ x, float *__restrict__ num,
+                                               uint32_t *__restrict__ cnt, const uint8_t *__restrict__ mask,
+                                               int64_t M, float lambda) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < M; j += stride) {
+    const uint32_t c = cnt[j];
+    if (c) {
+      const float v = x[j] + lambda * num[j] / (float)c;
+      x[j] = (mask && !mask[j]) ? 0.0f : v;
+      num[j] = 0.0f;
+      cnt[j] = 0u;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_mask(float *__restrict__ x, const uint8_t *__restrict__ mask, int64_t M) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < M; j += stride)
+    if (!mask[j]) x[j] = 0.0f;
+}
+
+// ART: rows strictly in sequence, one wavefront.  x is read with agent-scope
+// loads (past the per-CU cache) and each row's update is made visible before
+// the next row reads.
+template <int LD>
+__global__ void __launch_bounds__(64) k_art(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ idx,
+                                            const void *__restrict__ len, float unit,
+                                            const double *__restrict__ norm2, const float *__restrict__ b,
+                                            const int64_t *__restrict__ order, int64_t n, int64_t M, float *x,
+                                            const uint8_t *__restrict__ mask, float lambda, uint32_t *status) {
+  const int lane = wave_lane();
+  for (int64_t q = 0; q < n; ++q) {
+    const int64_t i = order ? order[q] : q;
+    if ((uint64_t)i >= (uint64_t)n) {
+      if (lane == 0) atomicOr(status, kStBadIndex);
+      continue;
+    }
+    const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
+    if (e1 == e0) continue;
+    float d = 0.0f;
+    bool bad = false;
+    for (int64_t e = e0 + lane; e < e1; e += kWave) {
+      const int j = idx[e];
+      if ((uint32_t)j >= (uint64_t)M) { bad = true; continue; }
+      d = fmaf(load_len<LD>(len, e, unit), __hip_atomic_load(&x[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), d);
+    }
+    if (__ballot(bad)) {
+      if (lane == 0) atomicOr(status, kStBadIndex);
+      continue;
+    }
+    d = wave_sum_f32(d);
+    const float r = (float)(((double)b[i] - (double)d) / norm2[i]);
+    const float lr = lambda * r;
+    for (int64_t e = e0 + lane; e < e1; e += kWave) {
+      const int j = idx[e];
+      if (!mask || mask[j]) atomicAdd(&x[j], lr * load_len<LD>(len, e, unit));
+    }
+    __threadfence();
+  }
+}
+
+// residual: per-workgroup FP64 partial sums, then one ordered final sum
+template <int LD>
+__global__ void __launch_bounds__(256) k_resid_cached(const int64_t *__restrict__ row_ptr,
+                                                      const int32_t *__restrict__ idx, const void *__restrict__ len,
+                                                      float unit, const float *__restrict__ b, int64_t n, int64_t M,
+                                                      const float *__restrict__ x, double *partials) {
+  __shared__ double red[4];
+  const int lane = wave_lane();
+  const int wid = threadIdx.x / kWave;
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + wid; i < n; i += stride) {
+    const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
+    if (e1 == e0) continue;
+    float d = 0.0f;
+    for (int64_t e = e0 + lane; e < e1; e += kWave) {
+      const int j = idx[e];
+      if ((uint32_t)j < (uint64_t)M) d = fmaf(load_len<LD>(len, e, unit), x[j], d);
+    }
+    d = wave_sum_f32(d);
+    const double rr = (double)d - (double)b[i];
+    acc += rr * rr;
+  }
+  if (lane == 0) red[wid] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ void __launch_bounds__(256) k_resid_fused(PathParams P, HistPtrs H, int64_t n,
+                                                     const float *__restrict__ x, double *partials,
+                                                     uint32_t *status) {
+  extern __shared__ int smem[];
+  __shared__ double red[4];
+  const int wid = threadIdx.x / kWave;
+  const int lane = wave_lane();
+  int *s_vox = smem + wid * 3 * P.emax;
+  float *s_len = reinterpret_cast<float *>(s_vox + P.emax);
+  int *s_aux = s_vox + 2 * P.emax;
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * P.waves_per_block;
+  for (int64_t i = (int64_t)blockIdx.x * P.waves_per_block + wid; i < n; i += stride) {
+    float h[10];
+    load_history(H, i, h);
+    const int ne = build_row_any(P, h, s_vox, s_len, s_aux, status);
+    if (ne == 0) continue;
+    float d = 0.0f;
+    for (int e = lane; e < ne; e += kWave) d = fmaf(s_len[e], x[s_vox[e]], d);
+    d = wave_sum_f32(d);
+    const double rr = (double)d - (double)h[9];
+    acc += rr * rr;
+  }
+  if (lane == 0) red[wid] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < P.waves_per_block; ++w) s += red[w];
+    partials[blockIdx.x] = s;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_resid_final(const double *partials, int64_t np, double *out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t k = threadIdx.x; k < np; k += 256) acc += partials[k];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sqrt(red[0]);
+}
+
+__global__ void __launch_bounds__(256) k_roi(const float *__restrict__ x, const uint8_t *__restrict__ labels,
+                                             int64_t M, int32_t n_labels, double *sums,
+                                             unsigned long long *counts) {
+  __shared__ double s_sum[256];
+  __shared__ unsigned int s_cnt[256];
+  for (int l = threadIdx.x; l < 256; l += blockDim.x) { s_sum[l] = 0.0; s_cnt[l] = 0u; }
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < M; j += stride) {
+    const int l = labels[j];
+    if (l > 0 && l <= n_labels) {
+      atomicAdd(&s_sum[l], (double)x[j]);
+      atomicAdd(&s_cnt[l], 1u);
+    }
+  }
+  __syncthreads();
+  for (int l = 1 + threadIdx.x; l <= n_labels; l += blockDim.x) {
+    if (s_cnt[l]) {
+      atomicAdd(&sums[l - 1], s_sum[l]);
+      atomicAdd(&counts[l - 1], (unsigned long long)s_cnt[l]);
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_zero_small(T *p, int64_t n) {
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = T(0);
+}
+
+__global__ void k_poison(double *out, const uint32_t *status) {
+  if (status[0] != 0u) *out = __builtin_nan("");
+}
+
+static inline unsigned grid_for(int64_t n, int per_block, unsigned cap) {
+  int64_t g = (n + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+hipError_t launch_mask(float *x, const uint8_t *mask, int64_t M, hipStream_t s) {
+  if (!mask || M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mask, dim3(grid_for(M, 256, 8192)), dim3(256), 0, s, x, mask, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_cached(const int64_t *row_ptr, const int32_t *idx, const void *len, int32_t len_dtype,
+                                 float len_unit, const double *norm2, const float *b, const int64_t *order,
+                                 int64_t first, int64_t count, int64_t n, int64_t M, const float *x, float *num,
+                                 uint32_t *cnt, uint32_t *status, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const unsigned grid = grid_for(count, 4, 0x7fffffffu);
+  if (len_dtype == 0)
+    hipLaunchKernelGGL(k_project_cached<0>, dim3(grid), dim3(256), 0, s, row_ptr, idx, len, len_unit, norm2, b,
+                       order, first, count, n, M, x, num, cnt, status);
+  else
+    hipLaunchKernelGGL(k_project_cached<1>, dim3(grid), dim3(256), 0, s, row_ptr, idx, len, len_unit, norm2, b,
+                       order, first, count, n, M, x, num, cnt, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_fused(const PathParams &P, const HistPtrs &H, const int64_t *order, int64_t first,
+                                int64_t count, int64_t n, const float *x, float *num, uint32_t *cnt,
+                                uint32_t *status, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const size_t lds = (size_t)P.waves_per_block * 3 * P.emax * sizeof(int);
+  const unsigned grid = grid_for(count, P.waves_per_block, 1u << 20);
+  hipLaunchKernelGGL(k_project_fused, dim3(grid), dim3(P.waves_per_block * kWave), lds, s, P, H, order, first,
+                     count, n, x, num, cnt, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply(float *x, float *num, uint32_t *cnt, const uint8_t *mask, int64_t M, float lambda,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_apply, dim3(grid_for(M, 256, 8192)), dim3(256), 0, s, x, num, cnt, mask, M, lambda);
+  return hipGetLastError();
+}
+
+hipError_t launch_art(const int64_t *row_ptr, const int32_t *idx, const void *len, int32_t len_dtype,
+                      float len_unit, const double *norm2, const float *b, const int64_t *order, int64_t n,
+                      int64_t M, float *x, const uint8_t *mask, float lambda, uint32_t *status, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (len_dtype == 0)
+    hipLaunchKernelGGL(k_art<0>, dim3(1), dim3(64), 0, s, row_ptr, idx, len, len_unit, norm2, b, order, n, M, x,
+                       mask, lambda, status);
+  else
+    hipLaunchKernelGGL(k_art<1>, dim3(1), dim3(64), 0, s, row_ptr, idx, len, len_unit, norm2, b, order, n, M, x,
+                       mask, lambda, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_cached(const int64_t *row_ptr, const int32_t *idx, const void *len, int32_t len_dtype,
+                                  float len_unit, const float *b, int64_t n, int64_t M, const float *x,
+                                  double *partials, double *out, hipStream_t s) {
+  const unsigned grid = grid_for(n, 4, (unsigned)(kMaxPartials - 1));
+  if (len_dtype == 0)
+    hipLaunchKernelGGL(k_resid_cached<0>, dim3(grid), dim3(256), 0, s, row_ptr, idx, len, len_unit, b, n, M, x,
+                       partials);
+  else
+    hipLaunchKernelGGL(k_resid_cached<1>, dim3(grid), dim3(256), 0, s, row_ptr, idx, len, len_unit, b, n, M, x,
+                       partials);
+  hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(256), 0, s, partials, (int64_t)grid, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_fused(const PathParams &P, const HistPtrs &H, int64_t n, const float *x,
+                                 double *partials, uint32_t *status, double *out, hipStream_t s) {
+  const size_t lds = (size_t)P.waves_per_block * 3 * P.emax * sizeof(int);
+  const unsigned grid = grid_for(n, P.waves_per_block, (unsigned)(kMaxPartials - 1));
+  hipLaunchKernelGGL(k_resid_fused, dim3(grid), dim3(P.waves_per_block * kWave), lds, s, P, H, n, x, partials,
+                     status);
+  hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(256), 0, s, partials, (int64_t)grid, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_poison_on_status(double *out, const uint32_t *status, hipStream_t s) {
+  hipLaunchKernelGGL(k_poison, dim3(1), dim3(1), 0, s, out, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_roi(const float *x, const uint8_t *labels, int64_t M, int32_t n_labels, double *sums,
+                      int64_t *counts, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_small<double>, dim3(1), dim3(256), 0, s, sums, (int64_t)n_labels);
+  hipLaunchKernelGGL(k_zero_small<int64_t>, dim3(1), dim3(256), 0, s, counts, (int64_t)n_labels);
+  if (M > 0)
+    hipLaunchKernelGGL(k_roi, dim3(grid_for(M, 256, 1024)), dim3(256), 0, s, x, labels, M, n_labels, sums,
+                       reinterpret_cast<unsigned long long *>(counts));
+  return hipGetLastError();
+}
+
+}  // namespace pct

@@ -1,0 +1,118 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol include/pct.h declares, and rejects bad arguments on the host
+before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1707_05014_amd import _lib, api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pct.h")).read()
+    return sorted(set(re.findall(r"\b(pct_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_matches_exports():
+    names = _declared()
+    assert set(names) == set(_lib.EXPORTS)
+    lib = _lib.load()
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_struct_sizes_match_header():
+    # sizes the C compiler gives the structs (x86-64 SysV): checked against ctypes
+    assert ctypes.sizeof(_lib.pct_grid) == 36
+    assert ctypes.sizeof(_lib.pct_geom) == 48 + 64 + 16
+    assert ctypes.sizeof(_lib.pct_histories) == 8 + 10 * 8
+    assert ctypes.sizeof(_lib.pct_rows) == 3 * 8 + 3 * 8 + 8 + 8
+    assert ctypes.sizeof(_lib.pct_sweep_params) == 4 + 4 + 8 + 4 + 4 + 8 + 8
+
+
+def _grid():
+    return api.make_grid(8, 8, 4, 1, 1, 1, -4, -4, -2)
+
+
+def _geom(**kw):
+    d = dict(u_in=-10, u_out=10, hull_a=3, hull_b=3, hull_zmin=-1, hull_zmax=1, step_mm=1.0, poly=[7.5e-6])
+    d.update(kw)
+    return api.make_geom(**d)
+
+
+def test_workspace_size():
+    lib = _lib.load()
+    g = _grid()
+    a = lib.pct_workspace_size(ctypes.byref(g), None, None, 100, 0)
+    b = lib.pct_workspace_size(ctypes.byref(g), None, None, 10 ** 6, 0)
+    assert 0 < a <= b
+    bad = api.make_grid(0, 8, 4)
+    assert lib.pct_workspace_size(ctypes.byref(bad), None, None, 100, 0) == 0
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(step_mm=2.0), "step_mm"),
+    (dict(step_mm=0.0), "step_mm"),
+    (dict(hull_a=0.0), "hull"),
+    (dict(u_in=10, u_out=-10), "u_out"),
+    (dict(poly=[]), "n_poly"),
+])
+def test_invalid_geometry_rejected(kw, msg):
+    lib = _lib.load()
+    g = _grid()
+    geo = _geom(**kw)
+    hs = _lib.pct_histories()
+    hs.n = 0
+    rs = _lib.pct_rows()
+    rs.n_rows = 0
+    rs.row_ptr = 1  # never dereferenced: the call fails validation first
+    ws = ctypes.create_string_buffer(1)
+    code = lib.pct_mlp_trace(ctypes.byref(g), ctypes.byref(geo), ctypes.byref(hs), ctypes.byref(rs), ws, 1, None)
+    assert code == _lib.PCT_EINVAL
+    assert msg in lib.pct_last_error().decode()
+
+
+def test_small_workspace_rejected():
+    lib = _lib.load()
+    g = _grid()
+    geo = _geom()
+    hs = _lib.pct_histories()
+    hs.n = 0
+    rs = _lib.pct_rows()
+    rs.n_rows = 0
+    rs.row_ptr = 1
+    ws = ctypes.create_string_buffer(16)
+    code = lib.pct_mlp_trace(ctypes.byref(g), ctypes.byref(geo), ctypes.byref(hs), ctypes.byref(rs), ws, 16, None)
+    assert code == _lib.PCT_ENOMEM
+
+
+def test_bad_params_rejected():
+    lib = _lib.load()
+    g = _grid()
+    geo = _geom()
+    hs = _lib.pct_histories()
+    hs.n = 0
+    need = lib.pct_workspace_size(ctypes.byref(g), None, None, 0, 0)
+    ws = ctypes.create_string_buffer(need)
+    x = ctypes.create_string_buffer(4 * 256)
+    for p in (api.sweep_params("drop", 0, 0.5), api.sweep_params("drop", 10, 2.5),
+              api.sweep_params("drop", 10, 0.0)):
+        code = lib.pct_project_sweep(ctypes.byref(g), ctypes.byref(geo), ctypes.byref(hs), None, x,
+                                     ctypes.byref(p.struct), None, ws, need, None)
+        assert code == _lib.PCT_EINVAL
+    # ART needs cached rows
+    p = api.sweep_params("art", 1, 0.5)
+    code = lib.pct_project_sweep(ctypes.byref(g), ctypes.byref(geo), ctypes.byref(hs), None, x, ctypes.byref(p.struct),
+                                 None, ws, need, None)
+    assert code == _lib.PCT_EINVAL
+    assert "ART" in lib.pct_last_error().decode()
+
+
+def test_roi_args_rejected():
+    lib = _lib.load()
+    assert lib.pct_roi_stats(None, None, 10, 3, None, None, None) == _lib.PCT_EINVAL
+    assert lib.pct_roi_stats(None, None, 0, 0, None, None, None) == _lib.PCT_EINVAL

@@ -1,0 +1,247 @@
+"""GPU (HIP) path against the FP64 oracle, through the C ABI.
+
+Bars (stated for the hot path): row index sets identical on >= 99.99% of
+protons, with the voxels that differ carrying only slivers; path lengths
+within 1e-4 mm (1e-4 of the 1 mm voxel) on identical rows; ||a_i||^2 within
+1e-4 relative; images within 1e-3 relative L2 after a fixed number of sweeps.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+from helpers import compare_rows, merge_rows, oracle_geom, oracle_grid, pct_args  # noqa: E402
+from paper_1707_05014_amd import _lib, api  # noqa: E402
+
+LEN_TOL = 1e-4      # mm, on 1 mm voxels
+SLIVER = 1e-3       # mm: most a voxel present on one side only may carry
+IMG_TOL = 1e-3      # relative L2
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    cfg = synth.config(1)
+    h = synth.generate(cfg)
+    R = oracle.trace(oracle_grid(cfg), oracle_geom(cfg), h)
+    return cfg, h, R
+
+
+def _gpu_rows(cfg, h, len_dtype=0):
+    grid, geom = pct_args(cfg)
+    H = api.Histories.from_numpy(h)
+    rows = api.mlp_trace(grid, geom, H, len_dtype=len_dtype)
+    torch.cuda.synchronize()
+    return grid, geom, H, rows
+
+
+def _host_rows(rows, unit=1.0):
+    rp = rows.row_ptr.cpu().numpy()
+    idx = rows.idx[: rows.nnz].cpu().numpy()
+    ln = rows.len[: rows.nnz].float().cpu().numpy().astype(np.float64) * unit
+    n2 = rows.norm2.cpu().numpy()
+    return rp, idx, ln, n2
+
+
+def test_trace_parity_config1(cfg1):
+    cfg, h, R = cfg1
+    _say(f"trace parity: config 1, n={cfg.n}")
+    grid, geom, H, rows = _gpu_rows(cfg, h)
+    rp, idx, ln, n2 = _host_rows(rows)
+    mp, mi, ml, dups = merge_rows(rp, idx, ln)
+    assert dups == 0, "GPU rows must hold each voxel once"
+    cmp = compare_rows(R.row_ptr, R.idx, R.len, mp, mi, ml)
+    _say(f"  identical rows {cmp['frac_identical']:.6f}, max dlen {cmp['max_dlen']:.2e}, "
+         f"max one-sided len {cmp['max_only_len']:.2e}, bad rows {cmp['bad_rows'][:10]}")
+    assert cmp["frac_identical"] >= 0.9999
+    assert cmp["max_dlen"] <= LEN_TOL
+    assert cmp["max_only_len"] <= SLIVER
+    assert cmp["max_dlen_all"] <= SLIVER + LEN_TOL
+    ok = R.norm2 > 0
+    assert np.array_equal(ok, n2 > 0)
+    assert np.max(np.abs(n2[ok] - R.norm2[ok]) / R.norm2[ok]) <= 1e-4
+    # path length per proton
+    so = np.add.reduceat(R.len, R.row_ptr[:-1][ok]) if ok.any() else 0
+    sg = np.add.reduceat(ml, mp[:-1][ok])
+    assert np.max(np.abs(so - sg) / so) <= 1e-4
+
+
+def test_trace_fp32_path_variant(cfg1):
+    """Reduced-precision variant (FP32 path positions): its error against the
+    oracle is reported; the bar is the per-proton path length (1e-4 relative)
+    and that index differences stay slivers."""
+    cfg, h, R = cfg1
+    grid, geom = pct_args(cfg)
+    geom.path_fp32 = 1
+    H = api.Histories.from_numpy(h)
+    rows = api.mlp_trace(grid, geom, H)
+    rp, idx, ln, n2 = _host_rows(rows)
+    mp, mi, ml, dups = merge_rows(rp, idx, ln)
+    cmp = compare_rows(R.row_ptr, R.idx, R.len, mp, mi, ml)
+    _say(f"FP32 path variant: identical rows {cmp['frac_identical']:.6f}, max dlen (identical rows) "
+         f"{cmp['max_dlen']:.2e}, max dlen (all) {cmp['max_dlen_all']:.2e}, one-sided {cmp['max_only_len']:.2e}, "
+         f"dups {dups}")
+    ok = R.norm2 > 0
+    so = np.add.reduceat(R.len, R.row_ptr[:-1][ok])
+    sg = np.add.reduceat(ml, mp[:-1][ok])
+    rel = np.abs(so - sg) / so
+    _say(f"  rel path-length error: max {rel.max():.2e}, 99.9% {np.quantile(rel, 0.999):.2e}; "
+         f"abs max {np.max(np.abs(so - sg)):.2e} mm")
+    assert np.quantile(rel, 0.999) <= 1e-4
+    assert np.max(np.abs(so - sg)) <= 1e-2
+    assert cmp["frac_identical"] >= 0.99
+
+
+def test_trace_f16_rows(cfg1):
+    cfg, h, R = cfg1
+    _say("trace f16 rows: config 1")
+    grid, geom, H, rows32 = _gpu_rows(cfg, h, 0)
+    rows16 = api.mlp_trace(grid, geom, H, len_dtype=1)
+    torch.cuda.synchronize()
+    assert rows16.nnz == rows32.nnz
+    assert torch.equal(rows16.row_ptr, rows32.row_ptr)
+    assert torch.equal(rows16.idx[: rows16.nnz], rows32.idx[: rows32.nnz])
+    l32 = rows32.len[: rows32.nnz].double()
+    l16 = rows16.len[: rows16.nnz].double()   # unit = 1 mm here
+    # float16 rounding: half an ulp, 2^-11 relative for normal values and
+    # 2^-25 absolute in the subnormal range below 2^-14
+    bound = torch.clamp(l32 * 2.0 ** -11, min=2.0 ** -25) * (1 + 1e-6)
+    assert torch.all(torch.abs(l16 - l32) <= bound)
+    assert torch.equal(rows16.norm2, rows32.norm2)
+
+
+def _run_oracle(cfg, h, R, algo, block, sweeps):
+    order = synth.block_order(cfg.n, cfg.perm_seed)
+    mask = synth.hull_mask(cfg)
+    x, res = oracle.drop(R, h["wepl"], mask.astype(np.float64), order, block, cfg.lam, sweeps, mask=mask)
+    return x, res, order, mask
+
+
+def _run_gpu(cfg, h, algo, block, sweeps, order, mask, fused=False, len_dtype=0):
+    grid, geom = pct_args(cfg)
+    H = api.Histories.from_numpy(h)
+    x = torch.from_numpy(mask.astype(np.float32)).cuda()
+    params = api.sweep_params(algo, block, cfg.lam, sweeps, order=torch.from_numpy(order).cuda(),
+                              hull_mask=torch.from_numpy(mask).cuda())
+    rows = None if fused else api.mlp_trace(grid, geom, H, len_dtype=len_dtype)
+    res = api.reconstruct(grid, geom, H, params, x, rows=rows)
+    torch.cuda.synchronize()
+    return x.cpu().numpy().astype(np.float64), np.array(res)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_art_parity_config1(cfg1):
+    """Config 1 as specified: hull start + 10 ART sweeps."""
+    cfg, h, R = cfg1
+    _say("ART parity: config 1, 10 sweeps")
+    xo, ro, order, mask = _run_oracle(cfg, h, R, "art", 1, cfg.sweeps)
+    xg, rg = _run_gpu(cfg, h, "art", 1, cfg.sweeps, order, mask)
+    rel = _rel(xg, xo)
+    _say(f"  image rel-L2 {rel:.2e}; residual oracle {ro[-1]:.4f} gpu {rg[-1]:.4f}")
+    assert rel <= IMG_TOL
+    assert np.allclose(rg, ro, rtol=1e-3)
+
+
+@pytest.mark.parametrize("fused", [False, True], ids=["cached", "fused"])
+def test_drop_parity_config1(cfg1, fused):
+    cfg, h, R = cfg1
+    _say(f"DROP parity: config 1, blocks of 5000, 6 sweeps, fused={fused}")
+    xo, ro, order, mask = _run_oracle(cfg, h, R, "drop", 5000, 6)
+    xg, rg = _run_gpu(cfg, h, "drop", 5000, 6, order, mask, fused=fused)
+    rel = _rel(xg, xo)
+    _say(f"  image rel-L2 {rel:.2e}; residuals oracle {ro[-1]:.4f} gpu {rg[-1]:.4f}")
+    assert rel <= IMG_TOL
+    assert np.allclose(rg, ro, rtol=1e-3)
+
+
+def test_drop_ragged_blocks(cfg1):
+    """Block size that leaves a short last block, several workgroups per block."""
+    cfg, h, R = cfg1
+    _say("DROP ragged blocks: 7777")
+    xo, ro, order, mask = _run_oracle(cfg, h, R, "drop", 7777, 2)
+    xg, rg = _run_gpu(cfg, h, "drop", 7777, 2, order, mask)
+    assert _rel(xg, xo) <= IMG_TOL
+
+
+def test_residual_at_known_image(cfg1):
+    cfg, h, R = cfg1
+    _say("residual at the truth image")
+    truth = synth.truth_image(cfg)
+    ro = oracle.residual(R, h["wepl"], truth.astype(np.float64))
+    grid, geom, H, rows = _gpu_rows(cfg, h)
+    xt = torch.from_numpy(truth).cuda()
+    rc = api.residual(grid, geom, H, rows, xt)
+    rf = api.residual(grid, geom, H, None, xt)
+    assert rc == pytest.approx(ro, rel=1e-4)
+    assert rf == pytest.approx(ro, rel=1e-4)
+
+
+def test_roi_stats():
+    _say("ROI stats")
+    rng = np.random.default_rng(0)
+    M = 100_003
+    x = rng.normal(size=M).astype(np.float32)
+    lab = rng.integers(0, 6, M).astype(np.uint8)
+    s, c = api.roi_stats(torch.from_numpy(x).cuda(), torch.from_numpy(lab).cuda(), 5)
+    means = (s.cpu().numpy() / c.cpu().numpy())
+    assert np.allclose(means, oracle.roi_means(x, lab, 5), rtol=1e-9, atol=1e-12)
+    assert np.array_equal(c.cpu().numpy(), np.bincount(lab, minlength=6)[1:])
+
+
+def test_edge_cases():
+    _say("edge cases: empty input, hull misses, NaN, row capacity")
+    cfg = synth.config(1, n=2000)
+    h = synth.generate(cfg)
+    grid, geom = pct_args(cfg)
+    # empty history set
+    H0 = api.Histories({k: torch.empty(0, dtype=torch.float32, device="cuda") for k in api.FIELDS})
+    r0 = api.mlp_trace(grid, geom, H0)
+    assert r0.nnz == 0 and r0.row_ptr.cpu().tolist() == [0]
+    # histories that miss the hull, and non-finite ones
+    hb = {k: v.copy() for k, v in h.items()}
+    hb["t_in"][:10] = 500.0
+    hb["t_out"][:10] = 500.0
+    hb["wepl"][10:13] = np.nan
+    Hb = api.Histories.from_numpy(hb)
+    with pytest.raises(_lib.PctError) as ei:
+        api.mlp_trace(grid, geom, Hb)
+    assert ei.value.code == _lib.PCT_ENONFINITE
+    rows = api.mlp_trace(grid, geom, Hb, allow_nonfinite=True)
+    cnt = np.diff(rows.row_ptr.cpu().numpy())
+    assert np.all(cnt[:13] == 0) and np.mean(cnt[13:] > 0) > 0.99
+    # capacity overflow: nothing but row_ptr written
+    H = api.Histories.from_numpy(h)
+    full = api.mlp_trace(grid, geom, H)
+    small = api.Rows(torch.empty(cfg.n + 1, dtype=torch.int64, device="cuda"),
+                     torch.full((10,), -7, dtype=torch.int32, device="cuda"),
+                     torch.zeros(10, dtype=torch.float32, device="cuda"),
+                     torch.zeros(cfg.n, dtype=torch.float64, device="cuda"), 0)
+    with pytest.raises(_lib.PctError) as ei:
+        api.mlp_trace(grid, geom, H, rows=small)
+    assert ei.value.code == _lib.PCT_EROWCAP
+    assert torch.all(small.idx == -7)
+    assert torch.equal(small.row_ptr, full.row_ptr)
+
+
+def test_fused_equals_cached_single_block(cfg1):
+    """The fused sweep and the cached sweep see the same rows: one DROP block
+    over every proton gives the same update up to atomic summation order."""
+    cfg, h, R = cfg1
+    _say("fused vs cached, one block")
+    order = np.arange(cfg.n, dtype=np.int64)
+    mask = synth.hull_mask(cfg)
+    xa, _ = _run_gpu(cfg, h, "drop", cfg.n, 1, order, mask, fused=False)
+    xb, _ = _run_gpu(cfg, h, "drop", cfg.n, 1, order, mask, fused=True)
+    assert _rel(xa, xb) <= 1e-6
