@@ -177,6 +177,26 @@ pct_status pct_residual(const pct_grid *grid, const pct_geom *geom, const pct_hi
 pct_status pct_roi_stats(const float *x, const uint8_t *labels, int64_t M, int32_t n_labels, double *sums,
                          int64_t *counts, void *stream);
 
+/* Kernel timing with HIP events, for benchmarking (off by default).
+ * pct_profile_enable(1) clears the counters and records an event pair on the
+ * launching stream around every kernel the calls above launch;
+ * pct_profile_enable(0) stops recording.  pct_profile_read waits for the
+ * recorded events and returns, per kernel class, the number of launches and
+ * their summed device time in ms (arrays of PCT_K_COUNT, host memory).
+ * Recording adds host work per launch; leave it off outside measurements. */
+enum {
+    PCT_K_TRACE_COUNT = 0,   /* row sizing pass */
+    PCT_K_TRACE_FILL = 1,    /* row fill pass */
+    PCT_K_PROJECT = 2,       /* block projection + scatter (cached or fused) */
+    PCT_K_APPLY = 3,         /* block update of x */
+    PCT_K_RESIDUAL = 4,      /* ||Ax - b|| */
+    PCT_K_ART = 5,           /* sequential ART */
+    PCT_K_OTHER = 6,         /* fills, scans, masks */
+    PCT_K_COUNT = 7
+};
+pct_status pct_profile_enable(int32_t on);
+pct_status pct_profile_read(int64_t *launches, double *ms);
+
 /* Message for the last failing call on this thread (empty if none). */
 const char *pct_last_error(void);
 

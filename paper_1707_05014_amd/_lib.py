@@ -59,7 +59,8 @@ class pct_sweep_params(ctypes.Structure):
 
 
 EXPORTS = ("pct_workspace_size", "pct_mlp_trace", "pct_project_sweep", "pct_reconstruct", "pct_residual",
-           "pct_roi_stats", "pct_last_error")
+           "pct_roi_stats", "pct_profile_enable", "pct_profile_read", "pct_last_error")
+KERNEL_CLASSES = ("trace_count", "trace_fill", "project", "apply", "residual", "art", "other")
 
 _lib = None
 
@@ -98,6 +99,10 @@ def load(path: str | None = None):
                                  ctypes.c_size_t, _fp]
     lib.pct_roi_stats.restype = ctypes.c_int
     lib.pct_roi_stats.argtypes = [_fp, _fp, ctypes.c_int64, ctypes.c_int32, _fp, _fp, _fp]
+    lib.pct_profile_enable.restype = ctypes.c_int
+    lib.pct_profile_enable.argtypes = [ctypes.c_int32]
+    lib.pct_profile_read.restype = ctypes.c_int
+    lib.pct_profile_read.argtypes = [P(ctypes.c_int64), P(ctypes.c_double)]
     lib.pct_last_error.restype = ctypes.c_char_p
     lib.pct_last_error.argtypes = []
     if path is None:

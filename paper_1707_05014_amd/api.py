@@ -235,3 +235,16 @@ def roi_stats(x: torch.Tensor, labels: torch.Tensor, n_labels: int, stream=None)
     check(lib.pct_roi_stats(x.data_ptr(), labels.data_ptr(), x.numel(), int(n_labels), sums.data_ptr(),
                             counts.data_ptr(), _stream_ptr(stream)))
     return sums, counts
+
+
+def profile_enable(on: bool = True) -> None:
+    check(_lib.load().pct_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """{kernel class: (launches, total ms)} recorded since profile_enable(True)."""
+    n = len(_lib.KERNEL_CLASSES)
+    launches = (ctypes.c_int64 * n)()
+    ms = (ctypes.c_double * n)()
+    check(_lib.load().pct_profile_read(launches, ms))
+    return {k: (int(launches[i]), float(ms[i])) for i, k in enumerate(_lib.KERNEL_CLASSES)}

@@ -8,13 +8,66 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "pct_internal.h"
 
 namespace {
 
 thread_local std::string g_err;
+
+// ---- optional kernel timing (pct_profile_enable / pct_profile_read)
+struct ProfRec {
+  int kind;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_prof_pool;
+
+hipEvent_t prof_event() {
+  if (!g_prof_pool.empty()) {
+    hipEvent_t e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// brackets one launch: records a start event now and a stop event at stop()
+struct ProfScope {
+  int kind;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(int k, hipStream_t st) : kind(k), s(st) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (!g_prof_on) return;
+    a = prof_event();
+    if (a) hipEventRecord(a, s);
+  }
+  void stop() {
+    if (!a) return;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    hipEvent_t b = prof_event();
+    if (!b) return;
+    hipEventRecord(b, s);
+    g_prof.push_back({kind, a, b});
+    a = nullptr;
+  }
+};
+
+#define PROF(kind, expr)                  \
+  do {                                    \
+    ProfScope ps_((kind), c.s);           \
+    hipError_t pe_ = (expr);              \
+    ps_.stop();                           \
+    HIPCHECK(pe_);                        \
+  } while (0)
 
 pct_status fail(pct_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 pct_status fail(pct_status st, const char *fmt, ...) {
@@ -170,7 +223,8 @@ pct_status status_to_code(uint32_t st) {
 
 pct_status do_trace(Ctx &c, pct_rows *rows) {
   HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
-  HIPCHECK(pct::launch_trace(c.P, c.H, c.n, 0, rows->row_ptr, nullptr, nullptr, 0, nullptr, c.W.status, c.s));
+  PROF(PCT_K_TRACE_COUNT,
+       pct::launch_trace(c.P, c.H, c.n, 0, rows->row_ptr, nullptr, nullptr, 0, nullptr, c.W.status, c.s));
   HIPCHECK(pct::launch_scan_rows(rows->row_ptr, c.n, c.W.scan, c.s));
   int64_t total = 0;
   HIPCHECK(hipMemcpyAsync(&total, rows->row_ptr + c.n, sizeof total, hipMemcpyDeviceToHost, c.s));
@@ -183,8 +237,8 @@ pct_status do_trace(Ctx &c, pct_rows *rows) {
   if (total > rows->cap_nnz)
     return fail(PCT_EROWCAP, "rows need %lld entries, capacity is %lld", (long long)total,
                 (long long)rows->cap_nnz);
-  HIPCHECK(pct::launch_trace(c.P, c.H, c.n, 1, rows->row_ptr, rows->idx, rows->len, rows->len_dtype, rows->norm2,
-                             c.W.status, c.s));
+  PROF(PCT_K_TRACE_FILL, pct::launch_trace(c.P, c.H, c.n, 1, rows->row_ptr, rows->idx, rows->len, rows->len_dtype,
+                                            rows->norm2, c.W.status, c.s));
   r = read_status(c, &st);
   if (r != PCT_OK) return r;
   return status_to_code(st);
@@ -196,8 +250,8 @@ pct_status do_sweep(Ctx &c, const pct_grid *g, const pct_rows *rows, float *x, c
   HIPCHECK(pct::launch_mask(x, p->hull_mask, c.M, c.s));
   const float unit = len_unit(g);
   if (p->algo == 0) {
-    HIPCHECK(pct::launch_art(rows->row_ptr, rows->idx, rows->len, rows->len_dtype, unit, rows->norm2, c.H.wepl,
-                             p->order, c.n, c.M, x, p->hull_mask, p->lambda, c.W.status, c.s));
+    PROF(PCT_K_ART, pct::launch_art(rows->row_ptr, rows->idx, rows->len, rows->len_dtype, unit, rows->norm2,
+                                    c.H.wepl, p->order, c.n, c.M, x, p->hull_mask, p->lambda, c.W.status, c.s));
     return PCT_OK;
   }
   HIPCHECK(pct::launch_fill_f32(c.W.num, c.M, 0.f, c.s));
@@ -205,23 +259,23 @@ pct_status do_sweep(Ctx &c, const pct_grid *g, const pct_rows *rows, float *x, c
   for (int64_t first = 0; first < c.n; first += p->block_size) {
     const int64_t count = std::min<int64_t>(p->block_size, c.n - first);
     if (rows)
-      HIPCHECK(pct::launch_project_cached(rows->row_ptr, rows->idx, rows->len, rows->len_dtype, unit, rows->norm2,
-                                          c.H.wepl, p->order, first, count, c.n, c.M, x, c.W.num, c.W.cnt,
-                                          c.W.status, c.s));
+      PROF(PCT_K_PROJECT, pct::launch_project_cached(rows->row_ptr, rows->idx, rows->len, rows->len_dtype, unit,
+                                                     rows->norm2, c.H.wepl, p->order, first, count, c.n, c.M, x,
+                                                     c.W.num, c.W.cnt, c.W.status, c.s));
     else
-      HIPCHECK(pct::launch_project_fused(c.P, c.H, p->order, first, count, c.n, x, c.W.num, c.W.cnt, c.W.status,
-                                         c.s));
-    HIPCHECK(pct::launch_apply(x, c.W.num, c.W.cnt, p->hull_mask, c.M, p->lambda, c.s));
+      PROF(PCT_K_PROJECT, pct::launch_project_fused(c.P, c.H, p->order, first, count, c.n, x, c.W.num, c.W.cnt,
+                                                    c.W.status, c.s));
+    PROF(PCT_K_APPLY, pct::launch_apply(x, c.W.num, c.W.cnt, p->hull_mask, c.M, p->lambda, c.s));
   }
   return PCT_OK;
 }
 
 pct_status do_residual(Ctx &c, const pct_grid *g, const pct_rows *rows, const float *x, double *out) {
   if (rows)
-    HIPCHECK(pct::launch_residual_cached(rows->row_ptr, rows->idx, rows->len, rows->len_dtype, len_unit(g),
-                                         c.H.wepl, c.n, c.M, x, c.W.partials, out, c.s));
+    PROF(PCT_K_RESIDUAL, pct::launch_residual_cached(rows->row_ptr, rows->idx, rows->len, rows->len_dtype,
+                                                     len_unit(g), c.H.wepl, c.n, c.M, x, c.W.partials, out, c.s));
   else
-    HIPCHECK(pct::launch_residual_fused(c.P, c.H, c.n, x, c.W.partials, c.W.status, out, c.s));
+    PROF(PCT_K_RESIDUAL, pct::launch_residual_fused(c.P, c.H, c.n, x, c.W.partials, c.W.status, out, c.s));
   return PCT_OK;
 }
 
@@ -363,6 +417,39 @@ pct_status pct_roi_stats(const float *x, const uint8_t *labels, int64_t M, int32
   if (M < 0 || n_labels < 1 || n_labels > 255) return fail(PCT_EINVAL, "need M >= 0 and 1 <= n_labels <= 255");
   if ((M > 0 && (!x || !labels)) || !sums || !counts) return fail(PCT_EINVAL, "NULL array");
   HIPCHECK(pct::launch_roi(x, labels, M, n_labels, sums, counts, reinterpret_cast<hipStream_t>(stream)));
+  return PCT_OK;
+}
+
+pct_status pct_profile_enable(int32_t on) {
+  g_err.clear();
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  if (on) {
+    for (auto &r : g_prof) {
+      hipEventSynchronize(r.b);
+      g_prof_pool.push_back(r.a);
+      g_prof_pool.push_back(r.b);
+    }
+    g_prof.clear();
+  }
+  g_prof_on = on != 0;
+  return PCT_OK;
+}
+
+pct_status pct_profile_read(int64_t *launches, double *ms) {
+  g_err.clear();
+  if (!launches || !ms) return fail(PCT_EINVAL, "NULL output array");
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  for (int k = 0; k < PCT_K_COUNT; ++k) {
+    launches[k] = 0;
+    ms[k] = 0.0;
+  }
+  for (auto &r : g_prof) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return fail(PCT_EDEVICE, "event synchronisation failed");
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return fail(PCT_EDEVICE, "event timing failed");
+    launches[r.kind] += 1;
+    ms[r.kind] += t;
+  }
   return PCT_OK;
 }
 

@@ -39,7 +39,8 @@ def build(force: bool = True) -> str:
 class _Shape(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("c", ctypes.c_double * 3), ("ax", ctypes.c_double * 3),
                 ("yaw", ctypes.c_double), ("z0", ctypes.c_double), ("z1", ctypes.c_double),
-                ("delta_rsp", ctypes.c_double), ("bound_r", ctypes.c_double)]
+                ("delta_rsp", ctypes.c_double), ("bound_r", ctypes.c_double), ("cy", ctypes.c_double),
+                ("sy", ctypes.c_double)]
 
 
 class _Params(ctypes.Structure):
@@ -272,12 +273,12 @@ def config(key: int, n: int | None = None) -> Config:
     elif key in (2, 4):
         g = Grid(200, 200, 40, 1.0, 1.0, 1.0, -100.0, -100.0, -20.0)
         c = Config(key, "head-1e7" if key == 2 else "head-1e7-f16", g, _phantom_head(2),
-                   Beam(180, 125.0, 25.0, 5e-3, -150.0, 150.0), 10_000_000, seed=2, perm_seed=202,
+                   Beam(180, 125.0, 25.0, 5e-3, -150.0, 150.0, step=2.0), 10_000_000, seed=2, perm_seed=202,
                    algo="drop", sweeps=6, block=200_000, lam=0.5, rows="f32" if key == 2 else "f16")
     elif key in (3, 5):
         g = Grid(200, 200, 40, 1.0, 1.0, 1.0, -100.0, -100.0, -20.0)
         c = Config(key, "head-2e8" if key == 3 else "head-2e8-warm", g, _phantom_head(3),
-                   Beam(180, 125.0, 25.0, 5e-3, -150.0, 150.0), 200_000_000, seed=3, perm_seed=303,
+                   Beam(180, 125.0, 25.0, 5e-3, -150.0, 150.0, step=2.0), 200_000_000, seed=3, perm_seed=303,
                    algo="drop", sweeps=8, block=200_000, lam=0.5, rows="fused")
     else:
         raise ValueError(key)

@@ -109,6 +109,7 @@ typedef struct {
     double z0, z1;
     double delta_rsp;
     double bound_r;     /* radius of a bounding sphere about c (for culling) */
+    double cy, sy;      /* cos/sin of yaw, filled in by the generator */
 } pctgen_shape;
 
 typedef struct {
@@ -131,7 +132,7 @@ typedef struct {
 /* interval of s in [0,1] for which P + s*D lies inside shape; returns length fraction */
 static int shape_interval(const pctgen_shape *sh, const double P[3], const double D[3],
                           double *s0, double *s1) {
-    double cs = cos(sh->yaw), sn = sin(sh->yaw);
+    double cs = sh->cy, sn = sh->sy;
     double px = P[0] - sh->c[0], py = P[1] - sh->c[1], pz = P[2] - sh->c[2];
     double lx = cs * px + sn * py, ly = -sn * px + cs * py;
     double dx = cs * D[0] + sn * D[1], dy = -sn * D[0] + cs * D[1], dz = D[2];
@@ -216,7 +217,17 @@ static double beta_p(double E, double m) {
  * float32, length n.  Returns the number of histories that needed more than
  * 1000 attempts (they are written as NaN), normally 0.
  */
-int64_t pctgen_histories(const pctgen_params *p, const pctgen_shape *shapes, int32_t n_shapes,
+static pctgen_shape *with_trig(const pctgen_shape *in, int32_t n) {
+    pctgen_shape *o = (pctgen_shape *)malloc((size_t)(n > 0 ? n : 1) * sizeof(pctgen_shape));
+    for (int32_t s = 0; s < n; ++s) {
+        o[s] = in[s];
+        o[s].cy = cos(in[s].yaw);
+        o[s].sy = sin(in[s].yaw);
+    }
+    return o;
+}
+
+static int64_t histories_impl(const pctgen_params *p, const pctgen_shape *shapes, int32_t n_shapes,
                          uint64_t seed, int64_t i0, int64_t n,
                          float *phi_o, float *t_in_o, float *v_in_o, float *dt_in_o, float *dv_in_o,
                          float *t_out_o, float *v_out_o, float *dt_out_o, float *dv_out_o,
@@ -346,17 +357,41 @@ int64_t pctgen_histories(const pctgen_params *p, const pctgen_shape *shapes, int
     return failures;
 }
 
+int64_t pctgen_histories(const pctgen_params *p, const pctgen_shape *shapes, int32_t n_shapes,
+                         uint64_t seed, int64_t i0, int64_t n,
+                         float *phi_o, float *t_in_o, float *v_in_o, float *dt_in_o, float *dv_in_o,
+                         float *t_out_o, float *v_out_o, float *dt_out_o, float *dv_out_o,
+                         float *wepl_o, int32_t nthreads) {
+    pctgen_shape *sh = with_trig(shapes, n_shapes);
+    int64_t r = histories_impl(p, sh, n_shapes, seed, i0, n, phi_o, t_in_o, v_in_o, dt_in_o, dv_in_o, t_out_o,
+                               v_out_o, dt_out_o, dv_out_o, wepl_o, nthreads);
+    free(sh);
+    return r;
+}
+
 /* Exact RSP line integral of the analytic phantom along a segment (test hook). */
 double pctgen_segment_wepl(const pctgen_shape *shapes, int32_t n_shapes, const double P[3], const double Q[3]) {
-    return segment_wepl(shapes, n_shapes, P, Q);
+    pctgen_shape *sh = with_trig(shapes, n_shapes);
+    double r = segment_wepl(sh, n_shapes, P, Q);
+    free(sh);
+    return r;
 }
+
+static double point_rsp(const pctgen_shape *shapes, int32_t n_shapes, const double X[3]);
 
 /* Point RSP of the analytic phantom. */
 double pctgen_point_rsp(const pctgen_shape *shapes, int32_t n_shapes, const double X[3]) {
+    pctgen_shape *sh = with_trig(shapes, n_shapes);
+    double r = point_rsp(sh, n_shapes, X);
+    free(sh);
+    return r;
+}
+
+static double point_rsp(const pctgen_shape *shapes, int32_t n_shapes, const double X[3]) {
     double acc = 0.0;
     for (int s = 0; s < n_shapes; ++s) {
         const pctgen_shape *sh = &shapes[s];
-        double cs = cos(sh->yaw), sn = sin(sh->yaw);
+        double cs = sh->cy, sn = sh->sy;
         double px = X[0] - sh->c[0], py = X[1] - sh->c[1];
         double lx = cs * px + sn * py, ly = -sn * px + cs * py;
         double q;
@@ -377,6 +412,7 @@ double pctgen_point_rsp(const pctgen_shape *shapes, int32_t n_shapes, const doub
 void pctgen_truth_image(const pctgen_shape *shapes, int32_t n_shapes, int32_t nx, int32_t ny, int32_t nz,
                         double dx, double dy, double dz, double ox, double oy, double oz, int32_t ss,
                         float *out, int32_t nthreads) {
+    pctgen_shape *sh = with_trig(shapes, n_shapes);
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(static)
@@ -389,10 +425,11 @@ void pctgen_truth_image(const pctgen_shape *shapes, int32_t n_shapes, int32_t nx
                 for (int c = 0; c < ss; ++c) {
                     double X[3] = {ox + (i + (a + 0.5) / ss) * dx, oy + (jj + (b + 0.5) / ss) * dy,
                                    oz + (k + (c + 0.5) / ss) * dz};
-                    acc += pctgen_point_rsp(shapes, n_shapes, X);
+                    acc += point_rsp(sh, n_shapes, X);
                 }
         out[j] = (float)(acc / ((double)ss * ss * ss));
     }
+    free(sh);
 }
 
 /* splitmix64 (Steele, Lea, Flood 2014) */
