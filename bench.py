@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--config", type=int, default=2, help="workload: 2 (FP32 rows) or 4 (FP16 rows)")
     ap.add_argument("--n", type=int, default=None, help="override the history count")
     ap.add_argument("--fused", action="store_true", help="recompute rows in every sweep (no row cache)")
+    ap.add_argument("--no-plan", action="store_true", help="cached rows swept with atomics (no tiled plan)")
     ap.add_argument("--path-fp32", action="store_true", help="FP32 path positions (reduced precision)")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-accuracy", action="store_true")
@@ -100,15 +101,22 @@ def main():
     params = api.sweep_params("drop", cfg.block, cfg.lam, S, order=order, hull_mask=mask)
 
     rows = None
+    plan = None
     if not args.fused:
         rows = api.mlp_trace(grid, geom, H, len_dtype=len_dtype)  # sizing + allocation
         torch.cuda.synchronize()
         log(f"rows: nnz {rows.nnz} ({rows.nnz / N:.1f} per history), "
             f"{(rows.idx.numel() * 4 + rows.len.numel() * rows.len.element_size()) / 1e9:.2f} GB")
+        if not args.no_plan:
+            plan = api.plan_build(grid, H, rows, params)  # sizing + allocation
+            torch.cuda.synchronize()
+            ps = plan.struct
+            log(f"plan: {ps.entries} entries, {ps.chunks} chunks, {ps.refs} reference slots, "
+                f"{ps.bytes / 1e9:.2f} GB")
 
     def step():
         x.copy_(x0)
-        return api.reconstruct(grid, geom, H, params, x, rows=rows, want_residuals=True)
+        return api.reconstruct(grid, geom, H, params, x, rows=rows, plan=plan, want_residuals=True)
 
     for _ in range(args.warmup):
         step()
@@ -134,6 +142,14 @@ def main():
     n_blocks = (N + cfg.block - 1) // cfg.block
     lb = 4 if len_dtype == 0 else 2
     kernels = {}
+    if plan is not None:
+        ps = plan.struct
+        # one pass over the block's rows: packed entry + length, per-row b, ||a||^2, ref bookkeeping;
+        # x read once and written once per block
+        lbp = 4 if ps.len_dtype == 0 else 2
+        per_block_rows = ((4 + lbp) * nnz + (4 + 8 + 12) * N) / n_blocks
+        kernels["plan_scatter"] = per_block_rows + 8 * M
+        kernels["plan_dot"] = per_block_rows + 4 * M
     if rows is not None:
         # algorithmic HBM bytes per launch (stated in the design doc)
         proj_bytes = ((4 + lb) * nnz + (16 + 8 + 8 + 4) * N) / n_blocks + 20 * M
@@ -151,7 +167,8 @@ def main():
         roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                     "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(kernels[dom])}
-    sweep_ms = (prof["project"][1] + prof["apply"][1]) / S
+    sweep_ms = (prof["project"][1] + prof["apply"][1] + prof["plan_dot"][1] + prof["plan_rows"][1]
+                + prof["plan_scatter"][1]) / S
     trace_ms = prof["trace_count"][1] + prof["trace_fill"][1]
 
     # time to <= 1% RSP error (plain sweeps from the hull start)
@@ -159,10 +176,15 @@ def main():
     if not args.skip_accuracy:
         x.copy_(x0)
         p1 = api.sweep_params("drop", cfg.block, cfg.lam, 1, order=order, hull_mask=mask)
+        if plan is not None:
+            p1 = api.sweep_params("drop", cfg.block, cfg.lam, 1, order=params.order, hull_mask=mask)
         errs = []
         hit = None
         for s in range(1, args.max_sweeps_acc + 1):
-            api.project_sweep(grid, geom, H, rows, x, p1)
+            if plan is not None:
+                api.plan_sweep(grid, plan, x, p1)
+            else:
+                api.project_sweep(grid, geom, H, rows, x, p1)
             sums, cnts = api.roi_stats(x, labels, len(true_rsp))
             means = (sums / cnts.clamp(min=1)).cpu().numpy()
             err = float(np.max(np.abs(means - true_rsp) / true_rsp))
@@ -196,7 +218,8 @@ def main():
         "config": {
             "workload": f"config {cfg.key}: {N} histories, {g.nx}x{g.ny}x{g.nz} voxels of {g.dx} mm, "
                         f"{cfg.beam.n_angles} angles, {S} DROP sweeps, blocks of {cfg.block}, lambda {cfg.lam}, "
-                        + ("rows recomputed every sweep" if args.fused else f"rows cached ({cfg.rows})"),
+                        + ("rows recomputed every sweep" if args.fused else f"rows cached ({cfg.rows})")
+                        + ("" if (args.fused or args.no_plan) else ", tiled sweep plan"),
             "histories": N, "voxels": M, "sweeps": S, "block": cfg.block,
             "rows": "fused" if args.fused else cfg.rows, "path_positions": "f32" if args.path_fp32 else "f64",
             "nnz_per_history": round(nnz / N, 2) if nnz else None,

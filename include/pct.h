@@ -129,9 +129,27 @@ typedef struct {
     const uint8_t *hull_mask;
 } pct_sweep_params;
 
+/* A sweep plan: cached rows regrouped, block by block, into lists per spatial
+ * tile of 16 x 16 x 8 voxels, so that a DROP block runs without global
+ * atomics (the block's row counts s_j and updates are formed in on-chip
+ * memory, tile by tile).  It describes the same matrix A as the rows it was
+ * built from, for one block order and block size, and holds b and ||a_i||^2
+ * in block order.  `mem` is caller-owned device memory of `bytes` bytes; the
+ * other fields are written by pct_plan_build and describe the layout.  A plan
+ * is used by one stream at a time. */
+typedef struct {
+    void *mem;
+    size_t bytes;
+    int64_t n, block_size, n_blocks, n_tiles;
+    int64_t entries, chunks, refs, max_chunks, max_ends;
+    int32_t len_dtype, nx, ny, nz;
+    const void *order, *rows_idx;
+    int32_t ready, reserved;
+} pct_plan;
+
 /* Bytes of scratch that the calls below need for a grid, solver and history
- * count.  `fused` = 1 when rows are recomputed in every sweep.  The same
- * workspace may be reused by consecutive calls on one stream. */
+ * count.  `fused` = 1 when rows are recomputed in every sweep (no plan).  The
+ * same workspace may be reused by consecutive calls on one stream. */
 size_t pct_workspace_size(const pct_grid *grid, const pct_geom *geom, const pct_sweep_params *params,
                           int64_t n_hist, int32_t fused);
 
@@ -156,13 +174,34 @@ pct_status pct_project_sweep(const pct_grid *grid, const pct_geom *geom, const p
                              const pct_rows *rows, float *x, const pct_sweep_params *params, double *resid_out,
                              void *workspace, size_t ws_bytes, void *stream);
 
+/* Build the sweep plan of cached rows for params (DROP, block_size <= 2^18;
+ * b from hist->wepl).  With plan->mem == NULL this is a sizing call: it sets
+ * plan->bytes and returns PCT_OK.  Otherwise plan->bytes must be at least the
+ * size a sizing call reports (else PCT_ENOMEM, with the size in plan->bytes).
+ * Synchronises `stream`. */
+pct_status pct_plan_build(const pct_grid *grid, const pct_histories *hist, const pct_rows *rows,
+                          const pct_sweep_params *params, pct_plan *plan, void *workspace, size_t ws_bytes,
+                          void *stream);
+
+/* One DROP sweep over all blocks with a plan (same result as
+ * pct_project_sweep on the rows the plan was built from, up to the order of
+ * floating-point additions).  params must match the plan's order and
+ * block_size.  resid_out as in pct_project_sweep.  Asynchronous. */
+pct_status pct_plan_sweep(const pct_grid *grid, const pct_plan *plan, float *x, const pct_sweep_params *params,
+                          double *resid_out, void *workspace, size_t ws_bytes, void *stream);
+
+/* ||Ax - b||_2 (FP64) with a plan, into *out (device double).  Asynchronous. */
+pct_status pct_plan_residual(const pct_grid *grid, const pct_plan *plan, const float *x, double *out,
+                             void *workspace, size_t ws_bytes, void *stream);
+
 /* Whole reconstruction: if rows != NULL, trace into them first (as
- * pct_mlp_trace), then params->n_sweeps sweeps from x_inout (the initial
+ * pct_mlp_trace); if plan != NULL too, build the plan (as pct_plan_build) and
+ * sweep with it; then params->n_sweeps sweeps from x_inout (the initial
  * guess, Sec. 2.1).  resid_host (host double [n_sweeps], or NULL): residual
  * after each sweep.  Synchronises `stream`. */
 pct_status pct_reconstruct(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist,
-                           const pct_sweep_params *params, pct_rows *rows, float *x_inout, double *resid_host,
-                           void *workspace, size_t ws_bytes, void *stream);
+                           const pct_sweep_params *params, pct_rows *rows, pct_plan *plan, float *x_inout,
+                           double *resid_host, void *workspace, size_t ws_bytes, void *stream);
 
 /* ||Ax - b||_2 over non-empty rows (FP64) into *out (device double).
  * rows == NULL recomputes the rows.  Asynchronous. */
@@ -192,7 +231,11 @@ enum {
     PCT_K_RESIDUAL = 4,      /* ||Ax - b|| */
     PCT_K_ART = 5,           /* sequential ART */
     PCT_K_OTHER = 6,         /* fills, scans, masks */
-    PCT_K_COUNT = 7
+    PCT_K_PLAN_DOT = 7,      /* plan: partial dot products per piece */
+    PCT_K_PLAN_ROWS = 8,     /* plan: r_i per row */
+    PCT_K_PLAN_SCATTER = 9,  /* plan: per-tile accumulation + block update */
+    PCT_K_PLAN_BUILD = 10,   /* plan construction */
+    PCT_K_COUNT = 11
 };
 pct_status pct_profile_enable(int32_t on);
 pct_status pct_profile_read(int64_t *launches, double *ms);

@@ -53,14 +53,25 @@ class pct_rows(ctypes.Structure):
                 ("norm2", _fp)]
 
 
+class pct_plan(ctypes.Structure):
+    _fields_ = [("mem", _fp), ("bytes", ctypes.c_size_t), ("n", ctypes.c_int64), ("block_size", ctypes.c_int64),
+                ("n_blocks", ctypes.c_int64), ("n_tiles", ctypes.c_int64), ("entries", ctypes.c_int64),
+                ("chunks", ctypes.c_int64), ("refs", ctypes.c_int64), ("max_chunks", ctypes.c_int64),
+                ("max_ends", ctypes.c_int64), ("len_dtype", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("order", _fp), ("rows_idx", _fp),
+                ("ready", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class pct_sweep_params(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("block_size", ctypes.c_int64), ("lambda_", ctypes.c_float),
                 ("n_sweeps", ctypes.c_int32), ("order", _fp), ("hull_mask", _fp)]
 
 
-EXPORTS = ("pct_workspace_size", "pct_mlp_trace", "pct_project_sweep", "pct_reconstruct", "pct_residual",
-           "pct_roi_stats", "pct_profile_enable", "pct_profile_read", "pct_last_error")
-KERNEL_CLASSES = ("trace_count", "trace_fill", "project", "apply", "residual", "art", "other")
+EXPORTS = ("pct_workspace_size", "pct_mlp_trace", "pct_project_sweep", "pct_plan_build", "pct_plan_sweep",
+           "pct_plan_residual", "pct_reconstruct", "pct_residual", "pct_roi_stats", "pct_profile_enable",
+           "pct_profile_read", "pct_last_error")
+KERNEL_CLASSES = ("trace_count", "trace_fill", "project", "apply", "residual", "art", "other", "plan_dot",
+                  "plan_rows", "plan_scatter", "plan_build")
 
 _lib = None
 
@@ -91,9 +102,17 @@ def load(path: str | None = None):
     lib.pct_project_sweep.restype = ctypes.c_int
     lib.pct_project_sweep.argtypes = [P(pct_grid), P(pct_geom), P(pct_histories), P(pct_rows), _fp,
                                       P(pct_sweep_params), _fp, _fp, ctypes.c_size_t, _fp]
+    lib.pct_plan_build.restype = ctypes.c_int
+    lib.pct_plan_build.argtypes = [P(pct_grid), P(pct_histories), P(pct_rows), P(pct_sweep_params), P(pct_plan),
+                                   _fp, ctypes.c_size_t, _fp]
+    lib.pct_plan_sweep.restype = ctypes.c_int
+    lib.pct_plan_sweep.argtypes = [P(pct_grid), P(pct_plan), _fp, P(pct_sweep_params), _fp, _fp, ctypes.c_size_t,
+                                   _fp]
+    lib.pct_plan_residual.restype = ctypes.c_int
+    lib.pct_plan_residual.argtypes = [P(pct_grid), P(pct_plan), _fp, _fp, _fp, ctypes.c_size_t, _fp]
     lib.pct_reconstruct.restype = ctypes.c_int
     lib.pct_reconstruct.argtypes = [P(pct_grid), P(pct_geom), P(pct_histories), P(pct_sweep_params), P(pct_rows),
-                                    _fp, P(ctypes.c_double), _fp, ctypes.c_size_t, _fp]
+                                    P(pct_plan), _fp, P(ctypes.c_double), _fp, ctypes.c_size_t, _fp]
     lib.pct_residual.restype = ctypes.c_int
     lib.pct_residual.argtypes = [P(pct_grid), P(pct_geom), P(pct_histories), P(pct_rows), _fp, _fp, _fp,
                                  ctypes.c_size_t, _fp]

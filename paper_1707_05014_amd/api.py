@@ -13,7 +13,7 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import check, pct_geom, pct_grid, pct_histories, pct_rows, pct_sweep_params
+from ._lib import check, pct_geom, pct_grid, pct_histories, pct_plan, pct_rows, pct_sweep_params
 
 FIELDS = ("phi", "t_in", "v_in", "dt_in", "dv_in", "t_out", "v_out", "dt_out", "dv_out", "wepl")
 
@@ -137,16 +137,16 @@ def sweep_params(algo="drop", block_size=200_000, lam=0.5, n_sweeps=1, order=Non
 _ws_cache: dict = {}
 
 
-def workspace(grid: pct_grid, n_hist: int, device=None) -> torch.Tensor:
+def workspace(grid: pct_grid, n_hist: int, device=None, params: "SweepParams | None" = None) -> torch.Tensor:
     lib = _lib.load()
-    nbytes = lib.pct_workspace_size(ctypes.byref(grid), None, None, int(n_hist), 0)
+    nbytes = lib.pct_workspace_size(ctypes.byref(grid), None, ctypes.byref(params.struct) if params else None,
+                                    int(n_hist), 0)
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-    key = (dev, nbytes)
-    ws = _ws_cache.get(key)
-    if ws is None:
-        _ws_cache.clear()
+    ws = _ws_cache.get(dev)
+    if ws is None or ws.numel() < nbytes:
+        _ws_cache.pop(dev, None)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-        _ws_cache[key] = ws
+        _ws_cache[dev] = ws
     return ws
 
 
@@ -197,22 +197,80 @@ def project_sweep(grid, geom, hist: Histories, rows: Rows | None, x: torch.Tenso
                                 _ptr(resid_out), ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
 
 
+class Plan:
+    """A sweep plan (pct_plan) with its device memory."""
+
+    def __init__(self):
+        self.struct = pct_plan()
+        self.mem = None
+
+    @property
+    def ready(self) -> bool:
+        return bool(self.struct.ready)
+
+
+def plan_build(grid, hist: Histories, rows: Rows, params: SweepParams, plan: Plan | None = None,
+               stream=None) -> Plan:
+    """pct_plan_build: sizing call, allocation (if needed), build."""
+    lib = _lib.load()
+    dev = hist.t["phi"].device
+    ws = workspace(grid, hist.n, dev, params)
+    hs = hist.struct()
+    rs = rows.struct()
+    plan = plan or Plan()
+    if plan.mem is None:
+        plan.struct.mem = None
+        check(lib.pct_plan_build(ctypes.byref(grid), ctypes.byref(hs), ctypes.byref(rs), ctypes.byref(params.struct),
+                                 ctypes.byref(plan.struct), ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+        plan.mem = torch.empty(int(plan.struct.bytes), dtype=torch.uint8, device=dev)
+        plan.struct.mem = plan.mem.data_ptr()
+        plan.struct.bytes = plan.mem.numel()
+    check(lib.pct_plan_build(ctypes.byref(grid), ctypes.byref(hs), ctypes.byref(rs), ctypes.byref(params.struct),
+                             ctypes.byref(plan.struct), ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+    plan.struct.mem = plan.mem.data_ptr()
+    plan.struct.bytes = plan.mem.numel()
+    plan.params = params
+    return plan
+
+
+def plan_sweep(grid, plan: Plan, x: torch.Tensor, params: SweepParams, resid_out: torch.Tensor | None = None,
+               stream=None):
+    lib = _lib.load()
+    ws = workspace(grid, int(plan.struct.n), x.device)
+    check(lib.pct_plan_sweep(ctypes.byref(grid), ctypes.byref(plan.struct), x.data_ptr(), ctypes.byref(params.struct),
+                             _ptr(resid_out), ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+
+
+def plan_residual(grid, plan: Plan, x: torch.Tensor, stream=None) -> float:
+    lib = _lib.load()
+    ws = workspace(grid, int(plan.struct.n), x.device)
+    out = torch.empty(1, dtype=torch.float64, device=x.device)
+    check(lib.pct_plan_residual(ctypes.byref(grid), ctypes.byref(plan.struct), x.data_ptr(), out.data_ptr(),
+                                ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+    return float(out.item())
+
+
 def reconstruct(grid, geom, hist: Histories, params: SweepParams, x: torch.Tensor, rows: Rows | None = None,
-                want_residuals: bool = True, stream=None, allow_nonfinite: bool = False):
-    """pct_reconstruct: x is updated in place; returns the residual per sweep (host list)."""
+                plan: Plan | None = None, want_residuals: bool = True, stream=None, allow_nonfinite: bool = False):
+    """pct_reconstruct: x is updated in place; returns the residual per sweep (host list).
+    With a plan, its memory must already be allocated (plan_build sizes it)."""
     lib = _lib.load()
     _check_lengths(grid, hist, x, params)
-    ws = workspace(grid, hist.n, x.device)
+    ws = workspace(grid, hist.n, x.device, params)
     hs = hist.struct()
     rs = rows.struct() if rows is not None else None
     res = (ctypes.c_double * max(params.n_sweeps, 1))()
     allow = (_lib.PCT_OK, _lib.PCT_ENONFINITE) if allow_nonfinite else (_lib.PCT_OK,)
     check(lib.pct_reconstruct(ctypes.byref(grid), ctypes.byref(geom), ctypes.byref(hs), ctypes.byref(params.struct),
-                              ctypes.byref(rs) if rs is not None else None, x.data_ptr(),
+                              ctypes.byref(rs) if rs is not None else None,
+                              ctypes.byref(plan.struct) if plan is not None else None, x.data_ptr(),
                               res if want_residuals else None, ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
           allow)
     if rows is not None:
         rows.nnz = int(rs.nnz)
+    if plan is not None:
+        plan.struct.mem = plan.mem.data_ptr()
+        plan.struct.bytes = plan.mem.numel()
     return [res[k] for k in range(params.n_sweeps)] if want_residuals else []
 
 

@@ -200,8 +200,8 @@ struct Ctx {
   hipStream_t s;
 };
 
-pct_status check_ws(void *ws, size_t ws_bytes, int64_t M, int64_t n) {
-  const size_t need = pct::workspace_bytes(M, n);
+pct_status check_ws(void *ws, size_t ws_bytes, int64_t M, int64_t n, int64_t plan_bt = 0) {
+  const size_t need = pct::workspace_bytes(M, n, plan_bt);
   if (!ws || ws_bytes < need)
     return fail(PCT_ENOMEM, "workspace of %zu bytes given, %zu needed", ws ? ws_bytes : (size_t)0, need);
   return PCT_OK;
@@ -289,8 +289,235 @@ pct_status setup(Ctx &c, const pct_grid *grid, const pct_geom *geom, const pct_h
   c.n = hist->n;
   if ((r = check_ws(ws, ws_bytes, c.M, c.n)) != PCT_OK) return r;
   c.H = hist_ptrs(hist);
-  c.W = pct::carve_workspace(ws, c.M, c.n);
+  c.W = pct::carve_workspace(ws, c.M, c.n, 0);
   c.s = reinterpret_cast<hipStream_t>(stream);
+  return PCT_OK;
+}
+
+// ------------------------------------------------------------------ plans
+struct PlanDims {
+  int64_t n, B, nb, T;
+  int32_t ntx, nty, ntz;
+};
+
+PlanDims plan_dims(const pct_grid *g, int64_t n, int64_t B) {
+  PlanDims d;
+  d.n = n;
+  d.B = B;
+  d.nb = n > 0 ? (n + B - 1) / B : 0;
+  d.ntx = (g->nx + pct::kTX - 1) / pct::kTX;
+  d.nty = (g->ny + pct::kTY - 1) / pct::kTY;
+  d.ntz = (g->nz + pct::kTZ - 1) / pct::kTZ;
+  d.T = (int64_t)d.ntx * d.nty * d.ntz;
+  return d;
+}
+
+int64_t plan_scratch_len(const PlanDims &d) { return d.nb * d.T + d.nb + 8; }
+
+enum {
+  L_REFBASE, L_BT_OFF, L_BT_CUR, L_CTILE, L_EMASK, L_CFE, L_PACKED, L_LEN, L_REFCNT, L_REFS, L_BPERM, L_N2PERM,
+  L_PARTIAL, L_RVALS, L_RESPART, L_BLKRES, L_SCANTMP, L_ENDSLOT, L_COUNT
+};
+
+size_t plan_layout(const pct_plan *p, size_t off[L_COUNT]) {
+  const int64_t nbT = p->n_blocks * p->n_tiles;
+  const int64_t G = (p->block_size + 255) / 256;
+  const size_t lb = p->len_dtype == 0 ? 4 : 2;
+  const size_t sz[L_COUNT] = {(size_t)(p->n + 1) * 8,   (size_t)(nbT + 1) * 8,   (size_t)nbT * 8,
+                              (size_t)p->chunks * 4,   (size_t)p->chunks * 8,   (size_t)(p->chunks + 1) * 8,
+                              (size_t)p->entries * 4,  (size_t)p->entries * lb, (size_t)p->n * 4,
+                              (size_t)p->refs * 4,     (size_t)p->n * 4,         (size_t)p->n * 8,
+                              (size_t)p->max_ends * 4, (size_t)p->block_size * 4, (size_t)G * 8,
+                              (size_t)p->n_blocks * 8,
+                              (size_t)((p->chunks + pct::kScanChunk - 1) / pct::kScanChunk + 2) * 8,
+                              (size_t)p->refs * 4};
+  size_t o = 0;
+  for (int k = 0; k < L_COUNT; ++k) {
+    off[k] = o;
+    o += align_up(sz[k] > 0 ? sz[k] : 8);
+  }
+  return o;
+}
+
+pct::PlanView plan_view(const pct_plan *p, float len_unit) {
+  size_t off[L_COUNT];
+  plan_layout(p, off);
+  char *m = static_cast<char *>(p->mem);
+  pct::PlanView V;
+  std::memset(&V, 0, sizeof V);
+  V.n = p->n;
+  V.B = p->block_size;
+  V.nb = p->n_blocks;
+  V.T = p->n_tiles;
+  V.E = p->entries;
+  V.C = p->chunks;
+  V.R = p->refs;
+  V.P = p->max_ends;
+  V.maxc = p->max_chunks;
+  V.nx = p->nx;
+  V.ny = p->ny;
+  V.nz = p->nz;
+  V.ntx = (p->nx + pct::kTX - 1) / pct::kTX;
+  V.nty = (p->ny + pct::kTY - 1) / pct::kTY;
+  V.ntz = (p->nz + pct::kTZ - 1) / pct::kTZ;
+  V.len_dtype = p->len_dtype;
+  V.len_unit = len_unit;
+  if (!m) return V;
+  V.bt_off = reinterpret_cast<int64_t *>(m + off[L_BT_OFF]);
+  V.bt_cur = reinterpret_cast<unsigned long long *>(m + off[L_BT_CUR]);
+  V.chunk_tile = reinterpret_cast<int32_t *>(m + off[L_CTILE]);
+  V.end_mask = reinterpret_cast<uint64_t *>(m + off[L_EMASK]);
+  V.chunk_first_end = reinterpret_cast<int64_t *>(m + off[L_CFE]);
+  V.packed = reinterpret_cast<uint32_t *>(m + off[L_PACKED]);
+  V.len = m + off[L_LEN];
+  V.ref_base = reinterpret_cast<int64_t *>(m + off[L_REFBASE]);
+  V.ref_cnt = reinterpret_cast<int32_t *>(m + off[L_REFCNT]);
+  V.refs = reinterpret_cast<uint32_t *>(m + off[L_REFS]);
+  V.b_perm = reinterpret_cast<float *>(m + off[L_BPERM]);
+  V.n2_perm = reinterpret_cast<double *>(m + off[L_N2PERM]);
+  V.partial = reinterpret_cast<float *>(m + off[L_PARTIAL]);
+  V.rvals = reinterpret_cast<float *>(m + off[L_RVALS]);
+  V.res_part = reinterpret_cast<double *>(m + off[L_RESPART]);
+  V.blk_res = reinterpret_cast<double *>(m + off[L_BLKRES]);
+  V.end_slot = reinterpret_cast<uint32_t *>(m + off[L_ENDSLOT]);
+  return V;
+}
+
+int64_t *plan_scan_tmp(const pct_plan *p) {
+  size_t off[L_COUNT];
+  plan_layout(p, off);
+  return reinterpret_cast<int64_t *>(static_cast<char *>(p->mem) + off[L_SCANTMP]);
+}
+
+pct_status check_plan_params(const pct_sweep_params *p, int64_t n) {
+  if (!p) return fail(PCT_EINVAL, "params are NULL");
+  if (p->algo != 1) return fail(PCT_EINVAL, "plans serve DROP (algo 1)");
+  if (p->block_size < 1 || p->block_size > pct::kMaxPlanBlock)
+    return fail(PCT_EINVAL, "plans need 1 <= block_size <= %lld", (long long)pct::kMaxPlanBlock);
+  if (!(p->lambda > 0.f && p->lambda < 2.f)) return fail(PCT_EINVAL, "lambda must be in (0, 2)");
+  (void)n;
+  return PCT_OK;
+}
+
+// sizing pass + (when plan->mem is set) construction
+pct_status do_plan_build(Ctx &c, const pct_grid *g, const pct_rows *rows, const pct_sweep_params *params,
+                         pct_plan *plan, void *ws, size_t ws_bytes) {
+  const PlanDims d = plan_dims(g, c.n, params->block_size);
+  const int64_t scr = plan_scratch_len(d);
+  pct_status r = check_ws(ws, ws_bytes, c.M, c.n, scr);
+  if (r != PCT_OK) return r;
+  c.W = pct::carve_workspace(ws, c.M, c.n, scr);
+  const float unit = len_unit(g);
+  pct_plan tmp = *plan;
+  tmp.n = d.n;
+  tmp.block_size = d.B;
+  tmp.n_blocks = d.nb;
+  tmp.n_tiles = d.T;
+  tmp.nx = g->nx;
+  tmp.ny = g->ny;
+  tmp.nz = g->nz;
+  tmp.len_dtype = rows->len_dtype;
+  tmp.ready = 0;
+  pct::PlanView V = plan_view(&tmp, unit);  // dims only (no memory yet)
+  int64_t *bt_cnt = c.W.plan_scratch;
+  int64_t *blk_cap = bt_cnt + d.nb * d.T;
+  HIPCHECK(pct::launch_fill_u32(reinterpret_cast<uint32_t *>(c.W.plan_scratch), 2 * scr, 0u, c.s));
+  HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
+  // the per-row capacities go straight into the plan's ref_base (first region)
+  // when the plan memory is there and large enough to hold it
+  int64_t *row_cap = nullptr;
+  if (plan->mem && plan->bytes >= (size_t)(c.n + 1) * 8) row_cap = static_cast<int64_t *>(plan->mem);
+  PROF(PCT_K_PLAN_BUILD, pct::launch_plan_count(rows->row_ptr, rows->idx, params->order, c.n, d.B, c.M, V, bt_cnt,
+                                                row_cap, blk_cap, c.W.status, c.s));
+  std::vector<int64_t> host((size_t)scr);
+  HIPCHECK(hipMemcpyAsync(host.data(), c.W.plan_scratch, (size_t)scr * 8, hipMemcpyDeviceToHost, c.s));
+  uint32_t st = 0;
+  if ((r = read_status(c, &st)) != PCT_OK) return r;
+  if (st) return status_to_code(st);
+  std::vector<int64_t> bt_off((size_t)(d.nb * d.T + 1), 0);
+  int64_t E = 0, maxc = 0, P = 1, Rtot = 0;
+  for (int64_t b = 0; b < d.nb; ++b) {
+    int64_t eb = 0;
+    for (int64_t t = 0; t < d.T; ++t) {
+      const int64_t k = b * d.T + t;
+      const int64_t pad = (host[k] + 63) / 64 * 64;
+      bt_off[k] = E;
+      E += pad;
+      eb += pad;
+    }
+    maxc = std::max(maxc, eb / 64);
+    P = std::max(P, host[d.nb * d.T + b]);
+    Rtot += host[d.nb * d.T + b];
+  }
+  bt_off[d.nb * d.T] = E;
+  tmp.entries = E;
+  tmp.chunks = E / 64;
+  tmp.refs = Rtot;
+  tmp.max_chunks = std::max<int64_t>(maxc, 1);
+  tmp.max_ends = P;
+  size_t off[L_COUNT];
+  const size_t need = plan_layout(&tmp, off);
+  if (E >= (int64_t(1) << 32)) return fail(PCT_EINVAL, "plan has more than 2^32 entries");
+  if (!plan->mem) {
+    tmp.bytes = need;
+    tmp.mem = nullptr;
+    *plan = tmp;
+    return PCT_OK;
+  }
+  if (plan->bytes < need) {
+    plan->bytes = need;
+    return fail(PCT_ENOMEM, "plan needs %zu bytes", need);
+  }
+  tmp.order = params->order;
+  tmp.rows_idx = rows->idx;
+  V = plan_view(&tmp, unit);
+  HIPCHECK(hipMemcpyAsync(V.bt_off, bt_off.data(), bt_off.size() * 8, hipMemcpyHostToDevice, c.s));
+  HIPCHECK(pct::launch_copy_i64_to_u64(V.bt_cur, V.bt_off, d.nb * d.T, c.s));
+  if (row_cap != V.ref_base) return fail(PCT_EDEVICE, "plan layout: ref_base is not the first region");
+  HIPCHECK(pct::launch_scan_rows(V.ref_base, c.n, c.W.scan, c.s));
+  HIPCHECK(pct::launch_fill_u32(V.packed, E, 0u, c.s));
+  PROF(PCT_K_PLAN_BUILD, pct::launch_plan_fill(rows->row_ptr, rows->idx, rows->len, rows->len_dtype, params->order,
+                                               c.H.wepl, rows->norm2, c.M, V, c.W.status, c.s));
+  PROF(PCT_K_PLAN_BUILD, pct::launch_plan_chunks(V, c.s));
+  HIPCHECK(pct::launch_scan_rows(V.chunk_first_end, tmp.chunks, plan_scan_tmp(&tmp), c.s));
+  PROF(PCT_K_PLAN_BUILD, pct::launch_plan_ref_ordinals(V, c.s));
+  int64_t refs_total = 0;
+  HIPCHECK(hipMemcpyAsync(&refs_total, V.ref_base + c.n, 8, hipMemcpyDeviceToHost, c.s));
+  if ((r = read_status(c, &st)) != PCT_OK) return r;
+  if (st) return status_to_code(st);
+  if (refs_total != tmp.refs) return fail(PCT_EDEVICE, "plan reference count changed between passes");
+  tmp.ready = 1;
+  *plan = tmp;
+  return PCT_OK;
+}
+
+pct_status check_plan(const pct_plan *plan, const pct_grid *g) {
+  if (!plan || !plan->mem || !plan->ready) return fail(PCT_EINVAL, "plan is not built");
+  if (plan->nx != g->nx || plan->ny != g->ny || plan->nz != g->nz) return fail(PCT_EINVAL, "plan grid differs");
+  size_t off[L_COUNT];
+  if (plan->bytes < plan_layout(plan, off)) return fail(PCT_EINVAL, "plan bytes smaller than its layout");
+  return PCT_OK;
+}
+
+pct_status do_plan_sweep(Ctx &c, const pct_plan *plan, const pct::PlanView &V, float *x,
+                         const pct_sweep_params *p) {
+  HIPCHECK(pct::launch_mask(x, p->hull_mask, c.M, c.s));
+  for (int64_t b = 0; b < plan->n_blocks; ++b) {
+    PROF(PCT_K_PLAN_DOT, pct::launch_plan_dot(V, b, x, c.s));
+    PROF(PCT_K_PLAN_ROWS, pct::launch_plan_rows(V, b, c.s));
+    PROF(PCT_K_PLAN_SCATTER, pct::launch_plan_scatter(V, b, x, p->hull_mask, p->lambda, c.s));
+  }
+  return PCT_OK;
+}
+
+pct_status do_plan_residual(Ctx &c, const pct_plan *plan, const pct::PlanView &V, const float *x, double *out) {
+  const int64_t G = (plan->block_size + 255) / 256;
+  for (int64_t b = 0; b < plan->n_blocks; ++b) {
+    PROF(PCT_K_RESIDUAL, pct::launch_plan_dot(V, b, x, c.s));
+    PROF(PCT_K_RESIDUAL, pct::launch_plan_resid_rows(V, b, V.res_part, c.s));
+    PROF(PCT_K_RESIDUAL, pct::launch_sum_partials(V.res_part, G, V.blk_res + b, 0, c.s));
+  }
+  PROF(PCT_K_RESIDUAL, pct::launch_sum_partials(V.blk_res, plan->n_blocks, out, 1, c.s));
   return PCT_OK;
 }
 
@@ -298,8 +525,9 @@ pct_status setup(Ctx &c, const pct_grid *grid, const pct_geom *geom, const pct_h
 
 namespace pct {
 
-size_t workspace_bytes(int64_t M, int64_t n_hist) {
-  size_t b = align_up(4 * sizeof(uint32_t));
+size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt) {
+  size_t b = align_up((size_t)(plan_bt > 0 ? plan_bt : 0) * sizeof(int64_t));
+  b += align_up(4 * sizeof(uint32_t));
   b += align_up((size_t)M * sizeof(float));
   b += align_up((size_t)M * sizeof(uint32_t));
   b += align_up((size_t)kMaxPartials * sizeof(double));
@@ -307,9 +535,11 @@ size_t workspace_bytes(int64_t M, int64_t n_hist) {
   return b;
 }
 
-Workspace carve_workspace(void *base, int64_t M, int64_t n_hist) {
+Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt) {
   char *p = static_cast<char *>(base);
   Workspace w;
+  w.plan_scratch = reinterpret_cast<int64_t *>(p);
+  p += align_up((size_t)(plan_bt > 0 ? plan_bt : 0) * sizeof(int64_t));
   w.status = reinterpret_cast<uint32_t *>(p);
   p += align_up(4 * sizeof(uint32_t));
   w.num = reinterpret_cast<float *>(p);
@@ -330,10 +560,11 @@ extern "C" {
 size_t pct_workspace_size(const pct_grid *grid, const pct_geom *geom, const pct_sweep_params *params,
                           int64_t n_hist, int32_t fused) {
   (void)geom;
-  (void)params;
-  (void)fused;
   if (!grid || grid->nx <= 0 || grid->ny <= 0 || grid->nz <= 0 || n_hist < 0) return 0;
-  return pct::workspace_bytes(grid_voxels(grid), n_hist);
+  int64_t plan_bt = 0;
+  if (params && !fused && params->algo == 1 && params->block_size >= 1)
+    plan_bt = plan_scratch_len(plan_dims(grid, n_hist, params->block_size));
+  return pct::workspace_bytes(grid_voxels(grid), n_hist, plan_bt);
 }
 
 pct_status pct_mlp_trace(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist, pct_rows *rows,
@@ -366,15 +597,79 @@ pct_status pct_project_sweep(const pct_grid *grid, const pct_geom *geom, const p
   return PCT_OK;
 }
 
+pct_status pct_plan_build(const pct_grid *grid, const pct_histories *hist, const pct_rows *rows,
+                          const pct_sweep_params *params, pct_plan *plan, void *workspace, size_t ws_bytes,
+                          void *stream) {
+  g_err.clear();
+  Ctx c;
+  pct_status r;
+  if ((r = check_grid(grid)) != PCT_OK) return r;
+  if ((r = check_hist(hist)) != PCT_OK) return r;
+  if ((r = check_rows(rows, hist->n, true)) != PCT_OK) return r;
+  if ((r = check_plan_params(params, hist->n)) != PCT_OK) return r;
+  if (!plan) return fail(PCT_EINVAL, "plan is NULL");
+  c.M = grid_voxels(grid);
+  c.n = hist->n;
+  c.H = hist_ptrs(hist);
+  c.s = reinterpret_cast<hipStream_t>(stream);
+  return do_plan_build(c, grid, rows, params, plan, workspace, ws_bytes);
+}
+
+pct_status pct_plan_sweep(const pct_grid *grid, const pct_plan *plan, float *x, const pct_sweep_params *params,
+                          double *resid_out, void *workspace, size_t ws_bytes, void *stream) {
+  g_err.clear();
+  pct_status r;
+  if ((r = check_grid(grid)) != PCT_OK) return r;
+  if ((r = check_plan(plan, grid)) != PCT_OK) return r;
+  if ((r = check_plan_params(params, plan->n)) != PCT_OK) return r;
+  if (params->block_size != plan->block_size || params->order != plan->order)
+    return fail(PCT_EINVAL, "params (order, block_size) differ from those the plan was built for");
+  if (!x) return fail(PCT_EINVAL, "x is NULL");
+  Ctx c;
+  c.M = grid_voxels(grid);
+  c.n = plan->n;
+  if ((r = check_ws(workspace, ws_bytes, c.M, c.n)) != PCT_OK) return r;
+  c.W = pct::carve_workspace(workspace, c.M, c.n, 0);
+  c.s = reinterpret_cast<hipStream_t>(stream);
+  const pct::PlanView V = plan_view(plan, len_unit(grid));
+  HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
+  if ((r = do_plan_sweep(c, plan, V, x, params)) != PCT_OK) return r;
+  if (resid_out) {
+    if ((r = do_plan_residual(c, plan, V, x, resid_out)) != PCT_OK) return r;
+    HIPCHECK(pct::launch_poison_on_status(resid_out, c.W.status, c.s));
+  }
+  return PCT_OK;
+}
+
+pct_status pct_plan_residual(const pct_grid *grid, const pct_plan *plan, const float *x, double *out,
+                             void *workspace, size_t ws_bytes, void *stream) {
+  g_err.clear();
+  pct_status r;
+  if ((r = check_grid(grid)) != PCT_OK) return r;
+  if ((r = check_plan(plan, grid)) != PCT_OK) return r;
+  if (!x || !out) return fail(PCT_EINVAL, "x / out is NULL");
+  Ctx c;
+  c.M = grid_voxels(grid);
+  c.n = plan->n;
+  (void)workspace;
+  (void)ws_bytes;
+  c.s = reinterpret_cast<hipStream_t>(stream);
+  const pct::PlanView V = plan_view(plan, len_unit(grid));
+  return do_plan_residual(c, plan, V, x, out);
+}
+
 pct_status pct_reconstruct(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist,
-                           const pct_sweep_params *params, pct_rows *rows, float *x_inout, double *resid_host,
-                           void *workspace, size_t ws_bytes, void *stream) {
+                           const pct_sweep_params *params, pct_rows *rows, pct_plan *plan, float *x_inout,
+                           double *resid_host, void *workspace, size_t ws_bytes, void *stream) {
   g_err.clear();
   Ctx c;
   pct_status r = setup(c, grid, geom, hist, workspace, ws_bytes, stream);
   if (r != PCT_OK) return r;
   if (rows && (r = check_rows(rows, c.n, true)) != PCT_OK) return r;
   if ((r = check_params(params, rows != nullptr)) != PCT_OK) return r;
+  if (plan && !rows) return fail(PCT_EINVAL, "a plan needs cached rows");
+  if (plan && (r = check_plan_params(params, c.n)) != PCT_OK) return r;
+  if (plan && !plan->mem) return fail(PCT_EINVAL, "plan memory is NULL (size it with pct_plan_build first)");
   if (!x_inout) return fail(PCT_EINVAL, "x is NULL");
   pct_status trace_st = PCT_OK;
   if (rows) {
@@ -383,12 +678,27 @@ pct_status pct_reconstruct(const pct_grid *grid, const pct_geom *geom, const pct
   } else {
     HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
   }
+  pct::PlanView V;
+  if (plan) {
+    Ctx cp = c;
+    if ((r = do_plan_build(cp, grid, rows, params, plan, workspace, ws_bytes)) != PCT_OK) return r;
+    V = plan_view(plan, len_unit(grid));
+    HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
+  }
   double *dres = c.W.partials + (pct::kMaxPartials - 1);
   for (int32_t sw = 0; sw < params->n_sweeps; ++sw) {
-    if ((r = do_sweep(c, grid, rows, x_inout, params)) != PCT_OK) return r;
+    if (plan) {
+      if ((r = do_plan_sweep(c, plan, V, x_inout, params)) != PCT_OK) return r;
+    } else if ((r = do_sweep(c, grid, rows, x_inout, params)) != PCT_OK) {
+      return r;
+    }
     if (resid_host) {
       // partial sums use the front of the array; the result sits in its last slot
-      if ((r = do_residual(c, grid, rows, x_inout, dres)) != PCT_OK) return r;
+      if (plan)
+        r = do_plan_residual(c, plan, V, x_inout, dres);
+      else
+        r = do_residual(c, grid, rows, x_inout, dres);
+      if (r != PCT_OK) return r;
       HIPCHECK(hipMemcpyAsync(&resid_host[sw], dres, sizeof(double), hipMemcpyDeviceToHost, c.s));
     }
   }

@@ -50,6 +50,7 @@ struct HistPtrs {
 
 // workspace layout
 struct Workspace {
+  int64_t *plan_scratch; // [plan_bt]: per (block, tile) and per block counters of a plan sizing pass
   uint32_t *status;      // [4]
   float *num;            // [M]
   uint32_t *cnt;         // [M]
@@ -59,8 +60,59 @@ struct Workspace {
 constexpr int64_t kMaxPartials = 1 << 16;
 constexpr int64_t kScanChunk = 4096;
 
-size_t workspace_bytes(int64_t M, int64_t n_hist);
-Workspace carve_workspace(void *base, int64_t M, int64_t n_hist);
+size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt);
+Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt);
+
+// ---- tiled sweep plan (cached rows regrouped by block and spatial tile)
+constexpr int kTX = 16, kTY = 16, kTZ = 8;           // tile of 2048 voxels
+constexpr int kTileVox = kTX * kTY * kTZ;
+constexpr int kRowBits = 18;                          // row-in-block index bits
+constexpr int64_t kMaxPlanBlock = int64_t(1) << kRowBits;
+// packed entry: bit 0 valid, bit 1 last entry of a piece, bits 2..12 voxel in
+// tile, bits 13..30 row in block
+__host__ __device__ inline uint32_t pack_entry(uint32_t last, uint32_t vox, uint32_t row) {
+  return 1u | (last << 1) | (vox << 2) | (row << 13);
+}
+
+struct PlanView {
+  int64_t n, B, nb, T, E, C, R, P, maxc;
+  int32_t ntx, nty, ntz, nx, ny, nz;
+  int32_t len_dtype;
+  float len_unit;
+  int64_t *bt_off;          // [nb*T + 1] entry offsets of each (block, tile) list (multiples of 64)
+  unsigned long long *bt_cur;  // [nb*T] fill cursors
+  int32_t *chunk_tile;      // [C] linear index of the first voxel of the chunk's tile
+  uint64_t *end_mask;       // [C] lanes that close a piece (or a chunk)
+  int64_t *chunk_first_end; // [C + 1]
+  uint32_t *packed;         // [E]
+  void *len;                // [E] float or half
+  int64_t *ref_base;        // [n + 1]
+  int32_t *ref_cnt;         // [n]
+  uint32_t *refs;           // [R] per row, entry positions that close its pieces
+  uint32_t *end_slot;       // [R] per piece end (chunk order): its row-ordered slot in the block
+  float *b_perm;            // [n] b in block order
+  double *n2_perm;          // [n] ||a||^2 in block order
+  float *partial;           // [P] per-piece partial dot products of one block, in row order
+  float *rvals;             // [B] r_i of one block
+  double *res_part;         // [ceil(B/256)] residual partial sums of one block
+  double *blk_res;          // [nb] squared residual per block
+};
+
+hipError_t launch_plan_count(const int64_t *row_ptr, const int32_t *idx, const int64_t *order, int64_t n, int64_t B,
+                             int64_t M, const PlanView &V, int64_t *bt_cnt, int64_t *row_cap, int64_t *blk_cap,
+                             uint32_t *status, hipStream_t s);
+hipError_t launch_plan_fill(const int64_t *row_ptr, const int32_t *idx, const void *len_in, int32_t len_in_dtype,
+                            const int64_t *order, const float *wepl, const double *norm2, int64_t M,
+                            const PlanView &V, uint32_t *status, hipStream_t s);
+hipError_t launch_plan_pad_counts(int64_t *cnt, int64_t k, hipStream_t s);
+hipError_t launch_plan_chunks(const PlanView &V, hipStream_t s);
+hipError_t launch_plan_ref_ordinals(const PlanView &V, hipStream_t s);
+hipError_t launch_copy_i64_to_u64(unsigned long long *dst, const int64_t *src, int64_t k, hipStream_t s);
+hipError_t launch_plan_dot(const PlanView &V, int64_t b, const float *x, hipStream_t s);
+hipError_t launch_plan_rows(const PlanView &V, int64_t b, hipStream_t s);
+hipError_t launch_plan_scatter(const PlanView &V, int64_t b, float *x, const uint8_t *mask, float lambda, hipStream_t s);
+hipError_t launch_plan_resid_rows(const PlanView &V, int64_t b, double *partials, hipStream_t s);
+hipError_t launch_sum_partials(const double *partials, int64_t np, double *out, int sqrt_it, hipStream_t s);
 
 // launchers (return hipError_t of the launch)
 hipError_t launch_trace(const PathParams &P, const HistPtrs &H, int64_t n, int mode, int64_t *row_ptr,

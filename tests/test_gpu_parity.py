@@ -245,3 +245,86 @@ def test_fused_equals_cached_single_block(cfg1):
     xa, _ = _run_gpu(cfg, h, "drop", cfg.n, 1, order, mask, fused=False)
     xb, _ = _run_gpu(cfg, h, "drop", cfg.n, 1, order, mask, fused=True)
     assert _rel(xa, xb) <= 1e-6
+
+
+# ------------------------------------------------------------- tiled plan
+def _plan_run(cfg, h, block, sweeps, order, mask, len_dtype=0, via_reconstruct=True):
+    grid, geom = pct_args(cfg)
+    H = api.Histories.from_numpy(h)
+    x = torch.from_numpy(mask.astype(np.float32)).cuda()
+    params = api.sweep_params("drop", block, cfg.lam, sweeps, order=torch.from_numpy(order).cuda(),
+                              hull_mask=torch.from_numpy(mask).cuda())
+    rows = api.mlp_trace(grid, geom, H, len_dtype=len_dtype)
+    plan = api.plan_build(grid, H, rows, params)
+    if via_reconstruct:
+        res = api.reconstruct(grid, geom, H, params, x, rows=rows, plan=plan)
+    else:
+        p1 = api.sweep_params("drop", block, cfg.lam, 1, order=params.order, hull_mask=params.hull_mask)
+        res = []
+        for _ in range(sweeps):
+            api.plan_sweep(grid, plan, x, p1)
+            res.append(api.plan_residual(grid, plan, x))
+    torch.cuda.synchronize()
+    return x.cpu().numpy().astype(np.float64), np.array(res), plan, rows
+
+
+@pytest.mark.parametrize("via", [True, False], ids=["reconstruct", "sweeps"])
+def test_plan_drop_parity_config1(cfg1, via):
+    cfg, h, R = cfg1
+    _say(f"plan DROP parity: config 1, blocks of 5000, 6 sweeps, via_reconstruct={via}")
+    xo, ro, order, mask = _run_oracle(cfg, h, R, "drop", 5000, 6)
+    xg, rg, plan, _ = _plan_run(cfg, h, 5000, 6, order, mask, via_reconstruct=via)
+    s = plan.struct
+    _say(f"  plan: entries {s.entries} chunks {s.chunks} refs {s.refs} max_chunks {s.max_chunks} "
+         f"max_ends {s.max_ends} bytes {s.bytes}")
+    rel = _rel(xg, xo)
+    _say(f"  image rel-L2 {rel:.2e}; residual oracle {ro[-1]:.4f} gpu {rg[-1]:.4f}")
+    assert rel <= IMG_TOL
+    assert np.allclose(rg, ro, rtol=1e-3)
+
+
+def test_plan_ragged_grid_and_blocks():
+    """Grid dimensions that are not multiples of the 16 x 16 x 8 tile, and a
+    block size that leaves a short last block."""
+    cfg = synth.config(1, n=60000)
+    cfg.grid = synth.Grid(60, 62, 14, 1.0, 1.0, 1.0, -30.0, -31.0, -7.0)
+    h = synth.generate(cfg)
+    _say("plan ragged: grid 60x62x14, blocks of 7777")
+    R = oracle.trace(oracle_grid(cfg), oracle_geom(cfg), h)
+    order = synth.block_order(cfg.n, cfg.perm_seed)
+    mask = synth.hull_mask(cfg)
+    xo, ro = oracle.drop(R, h["wepl"], mask.astype(np.float64), order, 7777, cfg.lam, 3, mask=mask)
+    xg, rg, plan, _ = _plan_run(cfg, h, 7777, 3, order, mask)
+    assert _rel(xg, xo) <= IMG_TOL
+    assert np.allclose(rg, ro, rtol=1e-3)
+
+
+def test_plan_f16_rows_match_csr(cfg1):
+    """FP16-length plan against the FP16-length CSR path (same matrix)."""
+    cfg, h, R = cfg1
+    _say("plan with FP16 rows vs CSR path with FP16 rows")
+    order = synth.block_order(cfg.n, cfg.perm_seed)
+    mask = synth.hull_mask(cfg)
+    xa, _ = _run_gpu(cfg, h, "drop", 5000, 3, order, mask, len_dtype=1)
+    xb, _, _, _ = _plan_run(cfg, h, 5000, 3, order, mask, len_dtype=1)
+    assert _rel(xb, xa) <= 1e-5
+    # and the FP16 form against the FP64 oracle: stated, bounded loosely
+    xo, _, _, _ = _run_oracle(cfg, h, R, "drop", 5000, 3)
+    _say(f"  FP16 rows vs oracle: rel-L2 {_rel(xb, xo):.2e}")
+    assert _rel(xb, xo) <= 1e-2
+
+
+def test_plan_rejects_mismatched_params(cfg1):
+    cfg, h, R = cfg1
+    grid, geom = pct_args(cfg)
+    H = api.Histories.from_numpy(h)
+    order = torch.from_numpy(synth.block_order(cfg.n, cfg.perm_seed)).cuda()
+    params = api.sweep_params("drop", 5000, 0.5, 1, order=order)
+    rows = api.mlp_trace(grid, geom, H)
+    plan = api.plan_build(grid, H, rows, params)
+    x = torch.zeros(cfg.grid.M, dtype=torch.float32, device="cuda")
+    with pytest.raises(_lib.PctError) as ei:
+        api.plan_sweep(grid, plan, x, api.sweep_params("drop", 4000, 0.5, 1, order=order))
+    assert ei.value.code == _lib.PCT_EINVAL
+    with pytest.raises(_lib.PctError):
+        api.plan_build(grid, H, rows, api.sweep_params("drop", 300_000, 0.5, 1, order=order))
