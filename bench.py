@@ -28,7 +28,14 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6    # MI355X vector FP64
+# FP64 operations per most-likely-path sample in the path kernel: covariance
+# moments (2 x 3 Horner polynomials of 8 terms), Kalman gain, positions, world
+# and grid coordinates, and the voxel walk of the segment that starts there
+PATH_FLOPS_PER_POINT = 220
+CALIB_BYTES = 1 << 30      # plain copy used to scale the FETCH/WRITE counters
+KERNEL_SOURCES = ("path_device.h", "trace.hip", "sweep.hip", "plan.hip", "abi.hip", "pct_internal.h")
 
 
 def log(msg):
@@ -49,11 +56,101 @@ def parse():
     ap.add_argument("--skip-accuracy", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--max-sweeps-acc", type=int, default=30)
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this benchmark and exit")
     return ap.parse_args()
+
+
+def source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1707_05014_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_summary(fetch_dir, write_dir, out_json):
+    """Per-kernel FETCH_SIZE / WRITE_SIZE (KiB per dispatch) from rocprofv3
+    counter CSVs, with the scale factor read off the 1 GiB calibration copy."""
+    import collections
+    import csv
+    import glob
+
+    def load(d, counter):
+        path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        agg = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                agg[r["Kernel_Name"].split("(")[0].replace("void ", "")].append(float(r["Counter_Value"]))
+        return agg
+
+    fetch = load(fetch_dir, "FETCH_SIZE")
+    write = load(write_dir, "WRITE_SIZE")
+    # the calibration is a 1 GiB device-to-device torch copy, which the runtime
+    # runs as its blit kernel: the largest copyBuffer dispatch of the run
+    copy = [k for k in fetch if "copyBuffer" in k]
+    calib_kib = CALIB_BYTES / 1024
+    f_cal = max(v for k in copy for v in fetch[k])
+    w_cal = max(v for k in copy for v in write.get(k, [0.0]))
+    out = {"source_hash": source_hash(), "fetch_scale": f_cal / calib_kib, "write_scale": w_cal / calib_kib,
+           "kernels": {}}
+    for k in fetch:
+        if not k.startswith("pct::"):
+            continue
+        fv, wv = fetch[k], write.get(k, [])
+        out["kernels"][k] = {"dispatches": len(fv), "fetch_kib_per_dispatch": sum(fv) / len(fv),
+                             "write_kib_per_dispatch": (sum(wv) / len(wv)) if wv else None}
+    with open(out_json, "w") as fh:
+        json.dump(out, fh, indent=1, sort_keys=True)
+    print(json.dumps(out, indent=1))
+
+
+def path_points(h, cfg) -> int:
+    """Number of most-likely-path samples over all histories (sum of K + 1 over
+    histories whose entry and exit lines meet the hull): the work count of
+    the path kernel, from the hull geometry alone (float64, host)."""
+    import numpy as np
+    b = cfg.phantom.body
+    a2, b2 = b.ax[0] ** 2, b.ax[1] ** 2
+    phi = h["phi"].astype(np.float64)
+    c, s = np.cos(phi), np.sin(phi)
+
+    def interval(u_ref, t, v, st, sv):
+        T = t - st * u_ref
+        V = v - sv * u_ref
+        px, qx = c - st * s, -T * s
+        py, qy = s + st * c, T * c
+        A = px * px / a2 + py * py / b2
+        B = 2 * (px * qx / a2 + py * qy / b2)
+        C = qx * qx / a2 + qy * qy / b2 - 1
+        disc = B * B - 4 * A * C
+        ok = disc > 0
+        sq = np.sqrt(np.where(ok, disc, 0))
+        lo, hi = (-B - sq) / (2 * A), (-B + sq) / (2 * A)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            z0 = np.where(sv != 0, (b.z0 - V) / sv, -np.inf)
+            z1 = np.where(sv != 0, (b.z1 - V) / sv, np.inf)
+        lo = np.maximum(lo, np.minimum(z0, z1))
+        hi = np.minimum(hi, np.maximum(z0, z1))
+        ok &= (sv != 0) | ((V >= b.z0) & (V <= b.z1))
+        return lo, hi, ok & (hi > lo)
+
+    f64 = lambda k: h[k].astype(np.float64)  # noqa: E731
+    lo0, _, ok0 = interval(cfg.beam.u_in, f64("t_in"), f64("v_in"), f64("dt_in"), f64("dv_in"))
+    _, hi2, ok2 = interval(cfg.beam.u_out, f64("t_out"), f64("v_out"), f64("dt_out"), f64("dv_out"))
+    L = hi2 - lo0
+    ok = ok0 & ok2 & (L > 0)
+    step = min(cfg.grid.dx, cfg.grid.dy, cfg.grid.dz)
+    K = np.maximum(1, np.ceil(L[ok] / step - 1e-9))
+    return int(np.sum(K + 1))
 
 
 def main():
     args = parse()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built",
               file=sys.stderr)
@@ -80,6 +177,7 @@ def main():
     h = synth.generate(cfg)
     gen_s = time.time() - t0
     log(f"generated {N} histories in {gen_s:.1f} s")
+    points = path_points(h, cfg)
     order_np = synth.block_order(N, cfg.perm_seed)
     mask_np = synth.hull_mask(cfg)
     labels_np = synth.roi_labels(cfg)
@@ -118,6 +216,13 @@ def main():
         x.copy_(x0)
         return api.reconstruct(grid, geom, H, params, x, rows=rows, plan=plan, want_residuals=True)
 
+    # a plain copy of known size: the reference for the FETCH/WRITE counters
+    src = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -141,35 +246,42 @@ def main():
     nnz = rows.nnz if rows is not None else None
     n_blocks = (N + cfg.block - 1) // cfg.block
     lb = 4 if len_dtype == 0 else 2
-    kernels = {}
+    # work models per launch (stated in the design doc): HBM bytes or FP64 flops
+    models = {"trace": ("alu", PATH_FLOPS_PER_POINT * points, FP64_PEAK_TFLOPS, "TFLOP/s", "pct::k_trace")}
     if plan is not None:
         ps = plan.struct
-        # one pass over the block's rows: packed entry + length, per-row b, ||a||^2, ref bookkeeping;
-        # x read once and written once per block
         lbp = 4 if ps.len_dtype == 0 else 2
         per_block_rows = ((4 + lbp) * nnz + (4 + 8 + 12) * N) / n_blocks
-        kernels["plan_scatter"] = per_block_rows + 8 * M
-        kernels["plan_dot"] = per_block_rows + 4 * M
+        models["plan_scatter"] = ("hbm", per_block_rows + 8 * M, HBM_PEAK_GBS, "GB/s", "pct::k_plan_scatter<0>")
+        models["plan_dot"] = ("hbm", per_block_rows + 4 * M, HBM_PEAK_GBS, "GB/s", "pct::k_plan_dot<0>")
     if rows is not None:
-        # algorithmic HBM bytes per launch (stated in the design doc)
-        proj_bytes = ((4 + lb) * nnz + (16 + 8 + 8 + 4) * N) / n_blocks + 20 * M
-        kernels["project"] = proj_bytes
-        fill_bytes = 40 * N + (4 + lb) * nnz + 16 * N
-        kernels["trace_fill"] = fill_bytes
-        kernels["residual"] = (4 + lb) * nnz + 20 * N + 4 * M
-    kernels["apply"] = 8 * M + 8 * M + 8 * M + 1 * M   # x, num, cnt read+write, mask read
-    dom = max(prof, key=lambda k: prof[k][1])
-    launches, tot_ms = prof[dom]
-    roofline = None
-    if dom in kernels and launches:
-        avg_ms = tot_ms / launches
-        achieved = kernels[dom] / (avg_ms / 1e3) / 1e9
-        roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                    "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(kernels[dom])}
+        models["project"] = ("hbm", ((4 + lb) * nnz + (16 + 8 + 8 + 4) * N) / n_blocks + 20 * M, HBM_PEAK_GBS,
+                             "GB/s", "pct::k_project_cached<0>")
+    timing = dict(prof)
+    timing["trace"] = (prof["trace_count"][0] + prof["trace_fill"][0], prof["trace_count"][1] + prof["trace_fill"][1])
+    dom = max((k for k in models if timing.get(k, (0, 0.0))[0]), key=lambda k: timing[k][1])
+    launches, tot_ms = timing[dom]
+    bound, work, peak, unit, kname = models[dom]
+    avg_ms = tot_ms / launches
+    achieved = work / (avg_ms / 1e3) / (1e9 if unit == "GB/s" else 1e12)
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic_config2.json")
+    if os.path.exists(tpath):
+        tj = json.load(open(tpath))
+        kk = tj.get("kernels", {}).get(kname)
+        if tj.get("source_hash") == source_hash() and kk and kk.get("write_kib_per_dispatch") is not None:
+            traffic = round((kk["fetch_kib_per_dispatch"] / tj["fetch_scale"]
+                             + kk["write_kib_per_dispatch"] / tj["write_scale"]) * 1024)
+    roofline = {"kernel": kname, "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 4), "traffic": traffic, "avg_launch_ms": round(avg_ms, 4),
+                "work_per_launch": int(work), "work_unit": "bytes" if unit == "GB/s" else "FP64 flops"}
     sweep_ms = (prof["project"][1] + prof["apply"][1] + prof["plan_dot"][1] + prof["plan_rows"][1]
                 + prof["plan_scatter"][1]) / S
     trace_ms = prof["trace_count"][1] + prof["trace_fill"][1]
+    others = {k: {"achieved": round(models[k][1] / (timing[k][1] / timing[k][0] / 1e3)
+                                    / (1e9 if models[k][3] == "GB/s" else 1e12), 3),
+                  "unit": models[k][3], "avg_launch_ms": round(timing[k][1] / timing[k][0], 4)}
+              for k in models if timing.get(k, (0, 0.0))[0]}
 
     # time to <= 1% RSP error (plain sweeps from the hull start)
     acc = None
@@ -226,6 +338,7 @@ def main():
             "trace_ms": round(trace_ms, 3), "sweep_ms": round(sweep_ms, 3),
             "residual_ms": round(prof["residual"][1] / max(S, 1), 3),
             "kernel_ms": {k: [v[0], round(v[1], 3)] for k, v in prof.items()},
+            "kernel_rates": others, "path_points": points,
             "accuracy": acc, "gen_s": round(gen_s, 1),
             "paper_context": "2e9 histories in under 10 min on the authors' earlier cluster (Sec. 1); "
                              "Table 1: 2.107e9 histories in 3:32 on 120 x (CPU core + Tesla GPU)",

@@ -96,7 +96,15 @@ struct PlanView {
   float *rvals;             // [B] r_i of one block
   double *res_part;         // [ceil(B/256)] residual partial sums of one block
   double *blk_res;          // [nb] squared residual per block
+  // voxel-major copy for the scatter: per (block, tile, group of 64 tile-local
+  // voxels) the entries sorted by voxel; packed: bit 0 valid, bit 1 last entry
+  // of its voxel, bits 2..7 voxel in group, bits 13..30 row in block
+  int64_t EB;               // entries (= nnz of the rows)
+  int64_t *grp_off;         // [nb*T*kGroups + 1]
+  uint32_t *packedB;        // [EB]
+  void *lenB;               // [EB]
 };
+constexpr int kGroups = kTileVox / 64;  // 64-voxel groups per tile
 
 hipError_t launch_plan_count(const int64_t *row_ptr, const int32_t *idx, const int64_t *order, int64_t n, int64_t B,
                              int64_t M, const PlanView &V, int64_t *bt_cnt, int64_t *row_cap, int64_t *blk_cap,
@@ -111,6 +119,7 @@ hipError_t launch_copy_i64_to_u64(unsigned long long *dst, const int64_t *src, i
 hipError_t launch_plan_dot(const PlanView &V, int64_t b, const float *x, hipStream_t s);
 hipError_t launch_plan_rows(const PlanView &V, int64_t b, hipStream_t s);
 hipError_t launch_plan_scatter(const PlanView &V, int64_t b, float *x, const uint8_t *mask, float lambda, hipStream_t s);
+hipError_t launch_plan_build_voxel_major(const PlanView &V, hipStream_t s);
 hipError_t launch_plan_resid_rows(const PlanView &V, int64_t b, double *partials, hipStream_t s);
 hipError_t launch_sum_partials(const double *partials, int64_t np, double *out, int sqrt_it, hipStream_t s);
 

@@ -387,57 +387,141 @@ __global__ void __launch_bounds__(256) k_plan_resid_rows(PlanView V, int64_t b, 
   if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
-// per-tile LDS accumulation of the block's update, then the update of the tile
-template <int LD>
-__global__ void __launch_bounds__(1024) k_plan_scatter(PlanView V, int64_t b, float *__restrict__ x,
-                                                      const uint8_t *__restrict__ mask, float lambda) {
-  __shared__ float s_num[kTileVox];
+// Voxel-major copy of one (block, tile) list: counting sort by tile-local
+// voxel in LDS (one workgroup per list).  Group offsets go to grp_off; the
+// last entry of each voxel's run is flagged.
+__global__ void __launch_bounds__(256) k_plan_voxel_major(PlanView V) {
   __shared__ uint32_t s_cnt[kTileVox];
-  const int t = blockIdx.x;
-  const int64_t bt = b * V.T + t;
-  const int64_t c0 = V.bt_off[bt] / kWave, c1 = V.bt_off[bt + 1] / kWave;
-  if (c0 == c1) return;
-  for (int e = threadIdx.x; e < kTileVox; e += blockDim.x) {
-    s_num[e] = 0.0f;
-    s_cnt[e] = 0u;
+  __shared__ uint32_t s_pos[kTileVox];
+  __shared__ uint32_t s_start[kTileVox];
+  __shared__ uint32_t s_part[256];
+  const int64_t k = blockIdx.x;  // (block, tile)
+  if (k >= V.nb * V.T) return;
+  const int64_t a0 = V.bt_off[k], a1 = V.bt_off[k + 1];
+  for (int e = threadIdx.x; e < kTileVox; e += blockDim.x) s_cnt[e] = 0u;
+  __syncthreads();
+  for (int64_t p = a0 + threadIdx.x; p < a1; p += blockDim.x) {
+    const uint32_t v = V.packed[p];
+    if (v & 1u) atomicAdd(&s_cnt[(v >> 2) & (kTileVox - 1)], 1u);
   }
   __syncthreads();
+  // exclusive scan of the 2048 counts: 8 per thread, then across threads
+  const int per = kTileVox / 256;
+  uint32_t loc[per];
+  uint32_t tot = 0;
+#pragma unroll
+  for (int q = 0; q < per; ++q) {
+    loc[q] = tot;
+    tot += s_cnt[threadIdx.x * per + q];
+  }
+  s_part[threadIdx.x] = tot;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const uint32_t add = (int)threadIdx.x >= o ? s_part[threadIdx.x - o] : 0u;
+    __syncthreads();
+    s_part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  const uint32_t excl = s_part[threadIdx.x] - tot;
+  // list start in the voxel-major arrays: entries before this list are the
+  // valid entries of all earlier lists, i.e. grp_off[k * kGroups] (filled by
+  // the host from the per-list valid counts)
+  const int64_t base = V.grp_off[k * kGroups];
+#pragma unroll
+  for (int q = 0; q < per; ++q) {
+    const int vox = threadIdx.x * per + q;
+    s_pos[vox] = excl + loc[q];
+    s_start[vox] = excl + loc[q];
+    if ((vox & 63) == 0 && vox > 0) V.grp_off[k * kGroups + vox / 64] = base + excl + loc[q];
+  }
+  __syncthreads();
+  for (int64_t p = a0 + threadIdx.x; p < a1; p += blockDim.x) {
+    const uint32_t v = V.packed[p];
+    if (!(v & 1u)) continue;
+    const int vox = (v >> 2) & (kTileVox - 1);
+    const uint32_t slot = atomicAdd(&s_pos[vox], 1u);
+    const uint32_t last = slot == s_start[vox] + s_cnt[vox] - 1u ? 2u : 0u;  // closes the voxel's run
+    const int64_t dst = base + slot;
+    if (dst >= V.grp_off[(k + 1) * kGroups]) continue;  // cannot happen when the counts agree
+    V.packedB[dst] = 1u | last | ((uint32_t)(vox & 63) << 2) | (v & ~((1u << 13) - 1u));
+    if (V.len_dtype == 0)
+      reinterpret_cast<float *>(V.lenB)[dst] = reinterpret_cast<const float *>(V.len)[p];
+    else
+      reinterpret_cast<__half *>(V.lenB)[dst] = reinterpret_cast<const __half *>(V.len)[p];
+  }
+}
+
+// Scatter of block b, voxel-major: one wavefront per 64-voxel group of a tile.
+// Each voxel's run is reduced with DPP prefix sums (its length is s_j); the
+// lane closing the run applies x_j += lambda num_j / s_j.  No atomics.
+template <int LD>
+__global__ void __launch_bounds__(256) k_plan_scatter(PlanView V, int64_t b, float *__restrict__ x,
+                                                      const uint8_t *__restrict__ mask, float lambda) {
   const int lane = wave_lane();
-  const int nw = blockDim.x / kWave;
-  constexpr int U = 8;
-  for (int64_t cbeg = c0 + (int64_t)(threadIdx.x / kWave) * U; cbeg < c1; cbeg += (int64_t)nw * U) {
+  const int64_t g = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;  // group within the block
+  if (g >= V.T * kGroups) return;
+  const int64_t t = g / kGroups;
+  const int grp = (int)(g % kGroups);
+  const int64_t gi = (b * V.T + t) * kGroups + grp;
+  const int64_t e0 = V.grp_off[gi], e1 = V.grp_off[gi + 1];
+  if (e0 == e1) return;
+  bool inside;
+  const int tile_base = tile_voxel((int)t, 0, V, inside);
+  const int nxy = V.nx * V.ny;
+  float carry = 0.0f;  // sum of the run that continues from the previous chunk
+  int carry_n = 0;
+  constexpr int U = 4;  // chunks whose loads are issued together
+  for (int64_t wb = e0; wb < e1; wb += (int64_t)U * kWave) {
     uint32_t v[U];
-    float l[U], r[U];
+    float val[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
+      const int64_t p = wb + (int64_t)k * kWave + lane;
       v[k] = 0u;
-      l[k] = 0.f;
-      if (cbeg + k < c1) {
-        const int64_t p = (cbeg + k) * kWave + lane;
-        v[k] = __builtin_nontemporal_load(V.packed + p);
-        l[k] = plan_len<LD>(V, p);
+      val[k] = 0.0f;
+      if (p < e1) {
+        v[k] = __builtin_nontemporal_load(V.packedB + p);
+        val[k] = LD == 0 ? __builtin_nontemporal_load(reinterpret_cast<const float *>(V.lenB) + p)
+                         : __half2float(reinterpret_cast<const __half *>(V.lenB)[p]) * V.len_unit;
       }
     }
 #pragma unroll
-    for (int k = 0; k < U; ++k) r[k] = (v[k] & 1u) ? V.rvals[v[k] >> 13] : 0.f;
+    for (int k = 0; k < U; ++k)
+      if (v[k] & 1u) val[k] *= V.rvals[v[k] >> 13];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      if (v[k] & 1u) {
-        const int local = (v[k] >> 2) & (kTileVox - 1);
-        atomicAdd(&s_num[local], r[k] * l[k]);
-        atomicAdd(&s_cnt[local], 1u);
+      const int64_t w = wb + (int64_t)k * kWave;
+      if (w >= e1) break;
+      const bool close = (v[k] & 1u) && ((v[k] >> 1) & 1u);
+      const uint64_t m = __ballot(close);
+      const float S = wave_incl_scan_dpp(val[k]);
+      const uint64_t below = m & ((1ull << lane) - 1);
+      const int prev = below ? 63 - __clzll(below) : -1;
+      const float Sp = __shfl(S, prev < 0 ? 0 : prev, kWave);
+      if (close) {
+        const float num = prev >= 0 ? S - Sp : S + carry;
+        const int cnt = prev >= 0 ? lane - prev : lane + 1 + carry_n;
+        const int local = grp * 64 + ((v[k] >> 2) & 63);
+        const int gv = tile_base + (local >> 8) * nxy + ((local >> 4) & 15) * V.nx + (local & 15);
+        const float xn = x[gv] + lambda * num / (float)cnt;
+        x[gv] = (mask && !mask[gv]) ? 0.0f : xn;
+      }
+      // the run still open at the end of this chunk carries into the next one
+      const int nv = (int)(e1 - w < kWave ? e1 - w : kWave);
+      const int last_close = m ? 63 - __clzll(m) : -1;
+      const float S_end = __shfl(S, nv - 1, kWave);
+      const float S_lc = __shfl(S, last_close < 0 ? 0 : last_close, kWave);
+      if (last_close == nv - 1) {
+        carry = 0.0f;
+        carry_n = 0;
+      } else if (last_close < 0) {
+        carry += S_end;
+        carry_n += nv;
+      } else {
+        carry = S_end - S_lc;
+        carry_n = nv - 1 - last_close;
       }
     }
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < kTileVox; e += blockDim.x) {
-    const uint32_t cnt = s_cnt[e];
-    if (!cnt) continue;
-    bool inside;
-    const int gv = tile_voxel(t, e, V, inside);
-    if (!inside) continue;
-    const float xn = x[gv] + lambda * s_num[e] / (float)cnt;
-    x[gv] = (mask && !mask[gv]) ? 0.0f : xn;
   }
 }
 
@@ -535,10 +619,17 @@ hipError_t launch_plan_resid_rows(const PlanView &V, int64_t b, double *partials
 
 hipError_t launch_plan_scatter(const PlanView &V, int64_t b, float *x, const uint8_t *mask, float lambda,
                                hipStream_t s) {
+  const unsigned g = grid_for(V.T * kGroups, 4, 0x7fffffffu);
   if (V.len_dtype == 0)
-    hipLaunchKernelGGL(k_plan_scatter<0>, dim3((unsigned)V.T), dim3(1024), 0, s, V, b, x, mask, lambda);
+    hipLaunchKernelGGL(k_plan_scatter<0>, dim3(g), dim3(256), 0, s, V, b, x, mask, lambda);
   else
-    hipLaunchKernelGGL(k_plan_scatter<1>, dim3((unsigned)V.T), dim3(1024), 0, s, V, b, x, mask, lambda);
+    hipLaunchKernelGGL(k_plan_scatter<1>, dim3(g), dim3(256), 0, s, V, b, x, mask, lambda);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_build_voxel_major(const PlanView &V, hipStream_t s) {
+  if (V.nb * V.T <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_plan_voxel_major, dim3((unsigned)(V.nb * V.T)), dim3(256), 0, s, V);
   return hipGetLastError();
 }
 
