@@ -30,10 +30,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6    # MI355X vector FP64
-# FP64 operations per most-likely-path sample in the path kernel: covariance
-# moments (2 x 3 Horner polynomials of 8 terms), Kalman gain, positions, world
-# and grid coordinates, and the voxel walk of the segment that starts there
-PATH_FLOPS_PER_POINT = 220
+# FP64 operations per most-likely-path sample in the path kernel (an FMA counts
+# as 2): three antiderivative moments F_p(d1) (8-term Horner + powers, 54),
+# I_m and J_m from them (17), Highland scaling (6), the 2x2 gain and the two
+# lateral offsets (36), world and grid coordinates (15), the segment to the
+# next sample (length, floor, local frame: 17) and its voxel walk (3 axes of
+# crossing set-up plus ~2 steps: 15)
+PATH_FLOPS_PER_POINT = 160
 CALIB_BYTES = 1 << 30      # plain copy used to scale the FETCH/WRITE counters
 KERNEL_SOURCES = ("path_device.h", "trace.hip", "sweep.hip", "plan.hip", "abi.hip", "pct_internal.h")
 
@@ -247,7 +250,8 @@ def main():
     n_blocks = (N + cfg.block - 1) // cfg.block
     lb = 4 if len_dtype == 0 else 2
     # work models per launch (stated in the design doc): HBM bytes or FP64 flops
-    models = {"trace": ("alu", PATH_FLOPS_PER_POINT * points, FP64_PEAK_TFLOPS, "TFLOP/s", "pct::k_trace")}
+    models = {"trace": ("alu", PATH_FLOPS_PER_POINT * points, FP64_PEAK_TFLOPS, "TFLOP/s",
+                        "pct::k_trace_stage<float>" if args.path_fp32 else "pct::k_trace_stage<double>")}
     if plan is not None:
         ps = plan.struct
         lbp = 4 if ps.len_dtype == 0 else 2
@@ -258,10 +262,12 @@ def main():
         models["project"] = ("hbm", ((4 + lb) * nnz + (16 + 8 + 8 + 4) * N) / n_blocks + 20 * M, HBM_PEAK_GBS,
                              "GB/s", "pct::k_project_cached<0>")
     timing = dict(prof)
-    timing["trace"] = (prof["trace_count"][0] + prof["trace_fill"][0], prof["trace_count"][1] + prof["trace_fill"][1])
+    timing["trace"] = prof["trace_path"]
     dom = max((k for k in models if timing.get(k, (0, 0.0))[0]), key=lambda k: timing[k][1])
     launches, tot_ms = timing[dom]
     bound, work, peak, unit, kname = models[dom]
+    if dom == "trace":
+        work = work / launches  # the path pass runs in chunks of rows: work per launch
     avg_ms = tot_ms / launches
     achieved = work / (avg_ms / 1e3) / (1e9 if unit == "GB/s" else 1e12)
     traffic = None
@@ -277,8 +283,9 @@ def main():
                 "work_per_launch": int(work), "work_unit": "bytes" if unit == "GB/s" else "FP64 flops"}
     sweep_ms = (prof["project"][1] + prof["apply"][1] + prof["plan_dot"][1] + prof["plan_rows"][1]
                 + prof["plan_scatter"][1]) / S
-    trace_ms = prof["trace_count"][1] + prof["trace_fill"][1]
-    others = {k: {"achieved": round(models[k][1] / (timing[k][1] / timing[k][0] / 1e3)
+    trace_ms = prof["trace_path"][1] + prof["trace_compact"][1]
+    others = {k: {"achieved": round(models[k][1] / (timing[k][0] if k == "trace" else 1)
+                                    / (timing[k][1] / timing[k][0] / 1e3)
                                     / (1e9 if models[k][3] == "GB/s" else 1e12), 3),
                   "unit": models[k][3], "avg_launch_ms": round(timing[k][1] / timing[k][0], 4)}
               for k in models if timing.get(k, (0, 0.0))[0]}

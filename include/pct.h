@@ -148,16 +148,20 @@ typedef struct {
 } pct_plan;
 
 /* Bytes of scratch that the calls below need for a grid, solver and history
- * count.  `fused` = 1 when rows are recomputed in every sweep (no plan).  The
- * same workspace may be reused by consecutive calls on one stream. */
+ * count.  `fused` = 1 when rows are recomputed in every sweep (no plan).  With
+ * geom given and fused = 0 the size includes the row staging area of the
+ * trace (up to 2^20 rows of the longest possible row, 8 bytes per entry); a
+ * trace given less stages fewer rows at a time (PCT_ENOMEM below one row).
+ * The same workspace may be reused by consecutive calls on one stream. */
 size_t pct_workspace_size(const pct_grid *grid, const pct_geom *geom, const pct_sweep_params *params,
                           int64_t n_hist, int32_t fused);
 
 /* Rows of A for all histories (Sec. 2: MLP per proton, then the path length
- * in each voxel it touches).  Two passes: count, then fill.  If rows->idx is
- * NULL only row_ptr and rows->nnz are produced (a sizing call).  If the total
- * exceeds rows->cap_nnz, row_ptr and nnz are written, nothing else, and
- * PCT_EROWCAP is returned.  Histories with NaN/Inf get empty rows and the call
+ * in each voxel it touches).  One path pass per proton: rows are built into
+ * the workspace's staging area chunk by chunk, then compacted into CSR.  If
+ * rows->idx is NULL only row_ptr and rows->nnz are produced (a sizing call).
+ * If the total exceeds rows->cap_nnz, row_ptr and nnz are written, the rows
+ * that fit are written, and PCT_EROWCAP is returned.  Histories with NaN/Inf get empty rows and the call
  * returns PCT_ENONFINITE after finishing the rest.  Synchronises `stream`. */
 pct_status pct_mlp_trace(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist,
                          pct_rows *rows, void *workspace, size_t ws_bytes, void *stream);
@@ -224,8 +228,8 @@ pct_status pct_roi_stats(const float *x, const uint8_t *labels, int64_t M, int32
  * their summed device time in ms (arrays of PCT_K_COUNT, host memory).
  * Recording adds host work per launch; leave it off outside measurements. */
 enum {
-    PCT_K_TRACE_COUNT = 0,   /* row sizing pass */
-    PCT_K_TRACE_FILL = 1,    /* row fill pass */
+    PCT_K_TRACE_PATH = 0,    /* MLP + voxel walk of every proton (staged rows) */
+    PCT_K_TRACE_COMPACT = 1, /* staged rows -> CSR */
     PCT_K_PROJECT = 2,       /* block projection + scatter (cached or fused) */
     PCT_K_APPLY = 3,         /* block update of x */
     PCT_K_RESIDUAL = 4,      /* ||Ax - b|| */

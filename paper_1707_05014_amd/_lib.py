@@ -71,7 +71,7 @@ class pct_sweep_params(ctypes.Structure):
 EXPORTS = ("pct_workspace_size", "pct_mlp_trace", "pct_project_sweep", "pct_plan_build", "pct_plan_sweep",
            "pct_plan_residual", "pct_reconstruct", "pct_residual", "pct_roi_stats", "pct_profile_enable",
            "pct_profile_read", "pct_last_error")
-KERNEL_CLASSES = ("trace_count", "trace_fill", "project", "apply", "residual", "art", "other", "plan_dot",
+KERNEL_CLASSES = ("trace_path", "trace_compact", "project", "apply", "residual", "art", "other", "plan_dot",
                   "plan_rows", "plan_scatter", "plan_build")
 
 _lib = None

@@ -137,10 +137,13 @@ def sweep_params(algo="drop", block_size=200_000, lam=0.5, n_sweeps=1, order=Non
 _ws_cache: dict = {}
 
 
-def workspace(grid: pct_grid, n_hist: int, device=None, params: "SweepParams | None" = None) -> torch.Tensor:
+def workspace(grid: pct_grid, n_hist: int, device=None, params: "SweepParams | None" = None,
+              geom: pct_geom | None = None) -> torch.Tensor:
+    """Device scratch of pct_workspace_size bytes, cached per device and grown
+    on demand (geom given: includes the trace's row staging area)."""
     lib = _lib.load()
-    nbytes = lib.pct_workspace_size(ctypes.byref(grid), None, ctypes.byref(params.struct) if params else None,
-                                    int(n_hist), 0)
+    nbytes = lib.pct_workspace_size(ctypes.byref(grid), ctypes.byref(geom) if geom is not None else None,
+                                    ctypes.byref(params.struct) if params else None, int(n_hist), 0)
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     ws = _ws_cache.get(dev)
     if ws is None or ws.numel() < nbytes:
@@ -155,7 +158,7 @@ def mlp_trace(grid: pct_grid, geom: pct_geom, hist: Histories, len_dtype: int = 
     """pct_mlp_trace: sizing call, allocation, fill call."""
     lib = _lib.load()
     dev = hist.t["phi"].device
-    ws = workspace(grid, hist.n, dev)
+    ws = workspace(grid, hist.n, dev, geom=geom)
     allow = (_lib.PCT_OK, _lib.PCT_ENONFINITE) if allow_nonfinite else (_lib.PCT_OK,)
     if rows is None:
         rows = Rows(torch.empty(hist.n + 1, dtype=torch.int64, device=dev), None, None, None, len_dtype)
@@ -256,7 +259,7 @@ def reconstruct(grid, geom, hist: Histories, params: SweepParams, x: torch.Tenso
     With a plan, its memory must already be allocated (plan_build sizes it)."""
     lib = _lib.load()
     _check_lengths(grid, hist, x, params)
-    ws = workspace(grid, hist.n, x.device, params)
+    ws = workspace(grid, hist.n, x.device, params, geom=geom if rows is not None else None)
     hs = hist.struct()
     rs = rows.struct() if rows is not None else None
     res = (ctypes.c_double * max(params.n_sweeps, 1))()

@@ -133,12 +133,8 @@ pct_status make_params(const pct_grid *g, const pct_geom *G, pct::PathParams &P)
   for (int n = 0; n < 8; ++n) {
     if (n < G->n_poly && !std::isfinite(G->poly[n])) return fail(PCT_EINVAL, "prior coefficient %d is not finite", n);
     const double an = n < G->n_poly ? G->poly[n] : 0.0;
-    const double n1 = n + 1.0, n2 = n + 2.0, n3 = n + 3.0;
-    const double ci[3] = {an / n1, an / (n1 * n2), 2.0 * an / (n1 * n2 * n3)};
     for (int m = 0; m < 3; ++m) {
-      P.cI_d[m][n] = ci[m];
       P.cF_d[m][n] = an / (n + m + 1.0);
-      P.cI_f[m][n] = (float)P.cI_d[m][n];
       P.cF_f[m][n] = (float)P.cF_d[m][n];
     }
   }
@@ -198,6 +194,8 @@ struct Ctx {
   pct::Workspace W;
   int64_t M, n;
   hipStream_t s;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
 };
 
 pct_status check_ws(void *ws, size_t ws_bytes, int64_t M, int64_t n, int64_t plan_bt = 0) {
@@ -221,30 +219,48 @@ pct_status status_to_code(uint32_t st) {
   return PCT_OK;
 }
 
-pct_status do_trace(Ctx &c, pct_rows *rows) {
+float len_unit(const pct_grid *g) { return std::min(g->dx, std::min(g->dy, g->dz)); }
+
+// One path pass per proton: chunks of rows are traced into staging slots of
+// P.emax entries per row, their counts scanned into row_ptr, then compacted
+// into the CSR arrays.  Without rows->idx only the counts are produced (sizing).
+pct_status do_trace(Ctx &c, const pct_grid *g, pct_rows *rows) {
+  const bool fill = rows->idx != nullptr;
+  int64_t st_rows = std::min<int64_t>(c.n, pct::kStageRows);
+  if (fill) {
+    while (st_rows > 1 && pct::workspace_bytes(c.M, c.n, 0, st_rows * c.P.emax) > c.ws_bytes) st_rows /= 2;
+    const size_t need = pct::workspace_bytes(c.M, c.n, 0, std::max<int64_t>(st_rows, 1) * c.P.emax);
+    if (need > c.ws_bytes)
+      return fail(PCT_ENOMEM, "workspace of %zu bytes given, %zu needed to stage rows", c.ws_bytes, need);
+  }
+  st_rows = std::max<int64_t>(st_rows, 1);
+  c.W = pct::carve_workspace(c.ws, c.M, c.n, 0, fill ? st_rows * c.P.emax : 0);
+  const float scale = 1.0f / len_unit(g);
   HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
-  PROF(PCT_K_TRACE_COUNT,
-       pct::launch_trace(c.P, c.H, c.n, 0, rows->row_ptr, nullptr, nullptr, 0, nullptr, c.W.status, c.s));
-  HIPCHECK(pct::launch_scan_rows(rows->row_ptr, c.n, c.W.scan, c.s));
+  if (c.n == 0) HIPCHECK(pct::launch_scan_rows(rows->row_ptr, 0, 0, c.W.scan, c.s));
+  for (int64_t i0 = 0; i0 < c.n; i0 += st_rows) {
+    const int64_t nr = std::min<int64_t>(st_rows, c.n - i0);
+    PROF(PCT_K_TRACE_PATH, pct::launch_trace_stage(c.P, c.H, i0, nr, rows->row_ptr + i0 + 1,
+                                                   fill ? c.W.st_idx : nullptr, c.W.st_len, rows->norm2,
+                                                   c.W.status, c.s));
+    HIPCHECK(pct::launch_scan_rows(rows->row_ptr, i0, nr, c.W.scan, c.s));
+    if (fill)
+      PROF(PCT_K_TRACE_COMPACT, pct::launch_trace_compact(i0, nr, rows->row_ptr, c.W.st_idx, c.W.st_len, c.P.emax,
+                                                          rows->idx, rows->len, rows->len_dtype, scale,
+                                                          rows->cap_nnz, c.W.status, c.s));
+  }
   int64_t total = 0;
   HIPCHECK(hipMemcpyAsync(&total, rows->row_ptr + c.n, sizeof total, hipMemcpyDeviceToHost, c.s));
   uint32_t st = 0;
   pct_status r = read_status(c, &st);
   if (r != PCT_OK) return r;
   rows->nnz = total;
-  if (st & (pct::kStOverflow | pct::kStRowMismatch)) return status_to_code(st);
-  if (!rows->idx) return status_to_code(st);
-  if (total > rows->cap_nnz)
+  if (st & pct::kStOverflow) return status_to_code(st);
+  if (fill && (st & pct::kStRowCap))
     return fail(PCT_EROWCAP, "rows need %lld entries, capacity is %lld", (long long)total,
                 (long long)rows->cap_nnz);
-  PROF(PCT_K_TRACE_FILL, pct::launch_trace(c.P, c.H, c.n, 1, rows->row_ptr, rows->idx, rows->len, rows->len_dtype,
-                                            rows->norm2, c.W.status, c.s));
-  r = read_status(c, &st);
-  if (r != PCT_OK) return r;
   return status_to_code(st);
 }
-
-float len_unit(const pct_grid *g) { return std::min(g->dx, std::min(g->dy, g->dz)); }
 
 pct_status do_sweep(Ctx &c, const pct_grid *g, const pct_rows *rows, float *x, const pct_sweep_params *p) {
   HIPCHECK(pct::launch_mask(x, p->hull_mask, c.M, c.s));
@@ -290,6 +306,8 @@ pct_status setup(Ctx &c, const pct_grid *grid, const pct_geom *geom, const pct_h
   if ((r = check_ws(ws, ws_bytes, c.M, c.n)) != PCT_OK) return r;
   c.H = hist_ptrs(hist);
   c.W = pct::carve_workspace(ws, c.M, c.n, 0);
+  c.ws = ws;
+  c.ws_bytes = ws_bytes;
   c.s = reinterpret_cast<hipStream_t>(stream);
   return PCT_OK;
 }
@@ -487,13 +505,13 @@ pct_status do_plan_build(Ctx &c, const pct_grid *g, const pct_rows *rows, const 
   HIPCHECK(hipMemcpyAsync(V.grp_off, grp_off.data(), grp_off.size() * 8, hipMemcpyHostToDevice, c.s));
   HIPCHECK(pct::launch_copy_i64_to_u64(V.bt_cur, V.bt_off, d.nb * d.T, c.s));
   if (row_cap != V.ref_base) return fail(PCT_EDEVICE, "plan layout: ref_base is not the first region");
-  HIPCHECK(pct::launch_scan_rows(V.ref_base, c.n, c.W.scan, c.s));
+  HIPCHECK(pct::launch_scan_rows(V.ref_base, 0, c.n, c.W.scan, c.s));
   HIPCHECK(pct::launch_fill_u32(V.packed, E, 0u, c.s));
   PROF(PCT_K_PLAN_BUILD, pct::launch_plan_fill(rows->row_ptr, rows->idx, rows->len, rows->len_dtype, params->order,
                                                c.H.wepl, rows->norm2, c.M, V, c.W.status, c.s));
   PROF(PCT_K_PLAN_BUILD, pct::launch_plan_chunks(V, c.s));
   PROF(PCT_K_PLAN_BUILD, pct::launch_plan_build_voxel_major(V, c.s));
-  HIPCHECK(pct::launch_scan_rows(V.chunk_first_end, tmp.chunks, plan_scan_tmp(&tmp), c.s));
+  HIPCHECK(pct::launch_scan_rows(V.chunk_first_end, 0, tmp.chunks, plan_scan_tmp(&tmp), c.s));
   PROF(PCT_K_PLAN_BUILD, pct::launch_plan_ref_ordinals(V, c.s));
   int64_t refs_total = 0;
   HIPCHECK(hipMemcpyAsync(&refs_total, V.ref_base + c.n, 8, hipMemcpyDeviceToHost, c.s));
@@ -539,21 +557,25 @@ pct_status do_plan_residual(Ctx &c, const pct_plan *plan, const pct::PlanView &V
 
 namespace pct {
 
-size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt) {
-  size_t b = align_up((size_t)(plan_bt > 0 ? plan_bt : 0) * sizeof(int64_t));
-  b += align_up(4 * sizeof(uint32_t));
+// fixed part (status, DROP accumulators, partial sums, scan chunks) followed
+// by one shared tail: the plan sizing counters during a plan build, the
+// staged rows during a trace (never both at once)
+size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots) {
+  size_t b = align_up(4 * sizeof(uint32_t));
   b += align_up((size_t)M * sizeof(float));
   b += align_up((size_t)M * sizeof(uint32_t));
   b += align_up((size_t)kMaxPartials * sizeof(double));
   b += align_up((size_t)((n_hist + kScanChunk - 1) / kScanChunk + 2) * sizeof(int64_t));
+  const size_t plan_b = (size_t)(plan_bt > 0 ? plan_bt : 0) * sizeof(int64_t);
+  const size_t stage_b = 2 * align_up((size_t)(stage_slots > 0 ? stage_slots : 0) * 4);
+  b += align_up(std::max(plan_b, stage_b));
   return b;
 }
 
-Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt) {
+Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots) {
+  (void)plan_bt;
   char *p = static_cast<char *>(base);
   Workspace w;
-  w.plan_scratch = reinterpret_cast<int64_t *>(p);
-  p += align_up((size_t)(plan_bt > 0 ? plan_bt : 0) * sizeof(int64_t));
   w.status = reinterpret_cast<uint32_t *>(p);
   p += align_up(4 * sizeof(uint32_t));
   w.num = reinterpret_cast<float *>(p);
@@ -563,7 +585,10 @@ Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt
   w.partials = reinterpret_cast<double *>(p);
   p += align_up((size_t)kMaxPartials * sizeof(double));
   w.scan = reinterpret_cast<int64_t *>(p);
-  (void)n_hist;
+  p += align_up((size_t)((n_hist + kScanChunk - 1) / kScanChunk + 2) * sizeof(int64_t));
+  w.plan_scratch = reinterpret_cast<int64_t *>(p);
+  w.st_idx = reinterpret_cast<int32_t *>(p);
+  w.st_len = reinterpret_cast<float *>(p + align_up((size_t)(stage_slots > 0 ? stage_slots : 0) * 4));
   return w;
 }
 
@@ -573,12 +598,15 @@ extern "C" {
 
 size_t pct_workspace_size(const pct_grid *grid, const pct_geom *geom, const pct_sweep_params *params,
                           int64_t n_hist, int32_t fused) {
-  (void)geom;
   if (!grid || grid->nx <= 0 || grid->ny <= 0 || grid->nz <= 0 || n_hist < 0) return 0;
   int64_t plan_bt = 0;
   if (params && !fused && params->algo == 1 && params->block_size >= 1)
     plan_bt = plan_scratch_len(plan_dims(grid, n_hist, params->block_size));
-  return pct::workspace_bytes(grid_voxels(grid), n_hist, plan_bt);
+  int64_t stage = 0;
+  pct::PathParams P;
+  if (geom && !fused && make_params(grid, geom, P) == PCT_OK)
+    stage = std::min<int64_t>(n_hist, pct::kStageRows) * P.emax;
+  return pct::workspace_bytes(grid_voxels(grid), n_hist, plan_bt, stage);
 }
 
 pct_status pct_mlp_trace(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist, pct_rows *rows,
@@ -589,7 +617,7 @@ pct_status pct_mlp_trace(const pct_grid *grid, const pct_geom *geom, const pct_h
   if (r != PCT_OK) return r;
   if ((r = check_rows(rows, c.n, false)) != PCT_OK) return r;
   if (rows->idx && (!rows->len || !rows->norm2)) return fail(PCT_EINVAL, "rows.len / rows.norm2 are NULL");
-  return do_trace(c, rows);
+  return do_trace(c, grid, rows);
 }
 
 pct_status pct_project_sweep(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist,
@@ -687,7 +715,7 @@ pct_status pct_reconstruct(const pct_grid *grid, const pct_geom *geom, const pct
   if (!x_inout) return fail(PCT_EINVAL, "x is NULL");
   pct_status trace_st = PCT_OK;
   if (rows) {
-    trace_st = do_trace(c, rows);
+    trace_st = do_trace(c, grid, rows);
     if (trace_st != PCT_OK && trace_st != PCT_ENONFINITE) return trace_st;
   } else {
     HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));

@@ -48,17 +48,27 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
   return v;
 }
 
+// move a wave-uniform value into scalar registers
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uniform(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double uniform(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 template <typename R> __device__ __forceinline__ R rsqrt_(R v);
 template <> __device__ __forceinline__ float rsqrt_(float v) { return sqrtf(v); }
 template <> __device__ __forceinline__ double rsqrt_(double v) { return sqrt(v); }
 
 template <typename R> struct Tables;
 template <> struct Tables<double> {
-  __device__ static const double (&cI(const PathParams &P))[3][8] { return P.cI_d; }
   __device__ static const double (&cF(const PathParams &P))[3][8] { return P.cF_d; }
 };
 template <> struct Tables<float> {
-  __device__ static const float (&cI(const PathParams &P))[3][8] { return P.cI_f; }
   __device__ static const float (&cF(const PathParams &P))[3][8] { return P.cF_f; }
 };
 
@@ -160,28 +170,37 @@ __device__ __forceinline__ void setup_path(const PathParams &P, const float h[10
   pp.FL[1] = moment<R, 1>(cF[1], pp.L);
   pp.FL[2] = moment<R, 2>(cF[2], pp.L);
   pp.valid = true;
+  // every lane computed the same values: keep one copy in scalar registers
+  pp.K = uniform(pp.K);
+  pp.u0 = uniform(pp.u0); pp.L = uniform(pp.L); pp.c = uniform(pp.c); pp.s = uniform(pp.s);
+  pp.t0 = uniform(pp.t0); pp.st0 = uniform(pp.st0); pp.v0 = uniform(pp.v0); pp.sv0 = uniform(pp.sv0);
+  pp.dtt = uniform(pp.dtt); pp.dts = uniform(pp.dts); pp.dvt = uniform(pp.dvt); pp.dvs = uniform(pp.dvs);
+  pp.FL[0] = uniform(pp.FL[0]); pp.FL[1] = uniform(pp.FL[1]); pp.FL[2] = uniform(pp.FL[2]);
 }
 
 // MLP lateral offsets (t, v) at depth d1 from the hull entry, 0 < d1 < L.
 //   S1 ~ [I2 I1; I1 I0],  I_m = int_0^d1 f(s) (d1 - s)^m ds
 //   S2 ~ [J2 J1; J1 J0],  J_m = int_d1^L f(s) (L - s)^m ds
-//   J_m from F_p(x) = int_0^x f(s) s^p ds by the binomial expansion of (L - s)^m
-// (the common factor E0^2/X0 cancels in the gain).
+// Both from the three antiderivative moments F_p(x) = int_0^x f(s) s^p ds by
+// the binomial expansions of (d1 - s)^m and (L - s)^m (the common factor
+// E0^2/X0 cancels in the gain).
 template <typename R>
 __device__ __forceinline__ void mlp_point(const PathParams &P, const ProtonPath<R> &pp, R d1, R &t, R &v) {
-  const auto &cI = Tables<R>::cI(P);
   const auto &cF = Tables<R>::cF(P);
   const R L = pp.L;
   const R d2 = L - d1;
-  R I0 = moment<R, 0>(cI[0], d1);
-  R I1 = moment<R, 1>(cI[1], d1);
-  R I2 = moment<R, 2>(cI[2], d1);
-  const R e0 = pp.FL[0] - moment<R, 0>(cF[0], d1);
-  const R e1 = pp.FL[1] - moment<R, 1>(cF[1], d1);
-  const R e2 = pp.FL[2] - moment<R, 2>(cF[2], d1);
+  const R F0 = moment<R, 0>(cF[0], d1);
+  const R F1 = moment<R, 1>(cF[1], d1);
+  const R F2 = moment<R, 2>(cF[2], d1);
+  R I0 = F0;
+  R I1 = d1 * F0 - F1;
+  R I2 = d1 * (d1 * F0 - (R)2 * F1) + F2;
+  const R e0 = pp.FL[0] - F0;
+  const R e1 = pp.FL[1] - F1;
+  const R e2 = pp.FL[2] - F2;
   R J0 = e0;
   R J1 = L * e0 - e1;
-  R J2 = L * L * e0 - (R)2 * L * e1 + e2;
+  R J2 = L * (L * e0 - (R)2 * e1) + e2;
   if (P.highland) {
     // the logarithmic factor only scales the two covariances; float keeps its
     // relative error near 1e-7 (a ~1e-7 mm change of the path) at a fraction
@@ -392,13 +411,6 @@ __device__ int build_row(const PathParams &P, const float h[10], int *s_vox, flo
     count = out;
   }
   return count;
-}
-
-// dispatch on the path precision chosen at run time (uniform per launch)
-__device__ __forceinline__ int build_row_any(const PathParams &P, const float h[10], int *s_vox, float *s_len,
-                                             int *s_aux, uint32_t *status) {
-  if (P.path_fp32) return build_row<float>(P, h, s_vox, s_len, s_aux, status);
-  return build_row<double>(P, h, s_vox, s_len, s_aux, status);
 }
 
 __device__ __forceinline__ void load_history(const HistPtrs &H, int64_t i, float h[10]) {

@@ -18,6 +18,7 @@ constexpr uint32_t kStNonFinite = 1u;
 constexpr uint32_t kStOverflow = 2u;
 constexpr uint32_t kStRowMismatch = 4u;
 constexpr uint32_t kStBadIndex = 8u;   // an order entry or a cached voxel index out of range
+constexpr uint32_t kStRowCap = 16u;    // the rows need more entries than their capacity
 
 // Everything a path kernel needs, precomputed on the host and passed by value.
 struct PathParams {
@@ -28,10 +29,9 @@ struct PathParams {
   int32_t highland;
   float inv_X0;
   // prior f(s) = sum_n a_n s^n (zero-padded to 8 terms):
-  //   I_m(d) = int_0^d f(s) (d - s)^m ds = d^(m+1) sum_n cI[m][n] d^n, cI = a_n B(n+1, m+1)
-  //   F_p(x) = int_0^x f(s) s^p ds      = x^(p+1) sum_n cF[p][n] x^n, cF = a_n / (n + p + 1)
-  double cI_d[3][8], cF_d[3][8];
-  float cI_f[3][8], cF_f[3][8];
+  //   F_p(x) = int_0^x f(s) s^p ds = x^(p+1) sum_n cF[p][n] x^n, cF = a_n / (n + p + 1)
+  double cF_d[3][8];
+  float cF_f[3][8];
   int32_t path_fp32;  // 1: path positions in float (reduced-precision variant)
   // grid
   int32_t nx, ny, nz;
@@ -56,12 +56,15 @@ struct Workspace {
   uint32_t *cnt;         // [M]
   double *partials;      // [kMaxPartials]
   int64_t *scan;         // [scan_len]
+  int32_t *st_idx;       // [stage_slots] staged row entries of one chunk of rows (trace)
+  float *st_len;         // [stage_slots]
 };
 constexpr int64_t kMaxPartials = 1 << 16;
 constexpr int64_t kScanChunk = 4096;
+constexpr int64_t kStageRows = 1 << 20;  // rows traced per staging chunk
 
-size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt);
-Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt);
+size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots = 0);
+Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots = 0);
 
 // ---- tiled sweep plan (cached rows regrouped by block and spatial tile)
 constexpr int kTX = 16, kTY = 16, kTZ = 8;           // tile of 2048 voxels
@@ -124,10 +127,14 @@ hipError_t launch_plan_resid_rows(const PlanView &V, int64_t b, double *partials
 hipError_t launch_sum_partials(const double *partials, int64_t np, double *out, int sqrt_it, hipStream_t s);
 
 // launchers (return hipError_t of the launch)
-hipError_t launch_trace(const PathParams &P, const HistPtrs &H, int64_t n, int mode, int64_t *row_ptr,
-                        int32_t *idx, void *len, int32_t len_dtype, double *norm2, uint32_t *status,
-                        hipStream_t s);
-hipError_t launch_scan_rows(int64_t *row_ptr, int64_t n, int64_t *scan_tmp, hipStream_t s);
+hipError_t launch_trace_stage(const PathParams &P, const HistPtrs &H, int64_t i0, int64_t nrows, int64_t *cnt,
+                              int32_t *st_idx, float *st_len, double *norm2, uint32_t *status, hipStream_t s);
+hipError_t launch_trace_compact(int64_t i0, int64_t nrows, const int64_t *row_ptr, const int32_t *st_idx,
+                                const float *st_len, int emax, int32_t *idx, void *len, int32_t len_dtype,
+                                float len_scale, int64_t cap, uint32_t *status, hipStream_t s);
+// counts at row_ptr[i0 + 1 .. i0 + nrows] -> offsets continuing from row_ptr[i0]
+// (row_ptr[0] is set to 0 when i0 == 0)
+hipError_t launch_scan_rows(int64_t *row_ptr, int64_t i0, int64_t nrows, int64_t *scan_tmp, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);

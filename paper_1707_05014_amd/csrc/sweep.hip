@@ -60,7 +60,8 @@ __global__ void __launch_bounds__(256) k_project_cached(const int64_t *__restric
 }
 
 // one wavefront per proton of the block: the row is rebuilt in LDS
-__global__ void __launch_bounds__(256) k_project_fused(PathParams P, HistPtrs H, const int64_t *__restrict__ order,
+template <typename R>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_project_fused(PathParams P, HistPtrs H, const int64_t *__restrict__ order,
                                                        int64_t first, int64_t count, int64_t n,
                                                        const float *__restrict__ x, float *num, uint32_t *cnt,
                                                        uint32_t *status) {
@@ -79,7 +80,7 @@ __global__ void __launch_bounds__(256) k_project_fused(PathParams P, HistPtrs H,
     }
     float h[10];
     load_history(H, i, h);
-    const int ne = build_row_any(P, h, s_vox, s_len, s_aux, status);
+    const int ne = build_row<R>(P, h, s_vox, s_len, s_aux, status);
     if (ne == 0) continue;
     float d = 0.0f;
     double n2 = 0.0;
@@ -188,7 +189,8 @@ __global__ void __launch_bounds__(256) k_resid_cached(const int64_t *__restrict_
   if (threadIdx.x == 0) partials[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
-__global__ void __launch_bounds__(256) k_resid_fused(PathParams P, HistPtrs H, int64_t n,
+template <typename R>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_resid_fused(PathParams P, HistPtrs H, int64_t n,
                                                      const float *__restrict__ x, double *partials,
                                                      uint32_t *status) {
   extern __shared__ int smem[];
@@ -203,7 +205,7 @@ __global__ void __launch_bounds__(256) k_resid_fused(PathParams P, HistPtrs H, i
   for (int64_t i = (int64_t)blockIdx.x * P.waves_per_block + wid; i < n; i += stride) {
     float h[10];
     load_history(H, i, h);
-    const int ne = build_row_any(P, h, s_vox, s_len, s_aux, status);
+    const int ne = build_row<R>(P, h, s_vox, s_len, s_aux, status);
     if (ne == 0) continue;
     float d = 0.0f;
     for (int e = lane; e < ne; e += kWave) d = fmaf(s_len[e], x[s_vox[e]], d);
@@ -300,8 +302,12 @@ hipError_t launch_project_fused(const PathParams &P, const HistPtrs &H, const in
   if (count <= 0) return hipSuccess;
   const size_t lds = (size_t)P.waves_per_block * 3 * P.emax * sizeof(int);
   const unsigned grid = grid_for(count, P.waves_per_block, 1u << 20);
-  hipLaunchKernelGGL(k_project_fused, dim3(grid), dim3(P.waves_per_block * kWave), lds, s, P, H, order, first,
-                     count, n, x, num, cnt, status);
+  if (P.path_fp32)
+    hipLaunchKernelGGL(k_project_fused<float>, dim3(grid), dim3(P.waves_per_block * kWave), lds, s, P, H, order,
+                       first, count, n, x, num, cnt, status);
+  else
+    hipLaunchKernelGGL(k_project_fused<double>, dim3(grid), dim3(P.waves_per_block * kWave), lds, s, P, H, order,
+                       first, count, n, x, num, cnt, status);
   return hipGetLastError();
 }
 
@@ -342,8 +348,12 @@ hipError_t launch_residual_fused(const PathParams &P, const HistPtrs &H, int64_t
                                  double *partials, uint32_t *status, double *out, hipStream_t s) {
   const size_t lds = (size_t)P.waves_per_block * 3 * P.emax * sizeof(int);
   const unsigned grid = grid_for(n, P.waves_per_block, (unsigned)(kMaxPartials - 1));
-  hipLaunchKernelGGL(k_resid_fused, dim3(grid), dim3(P.waves_per_block * kWave), lds, s, P, H, n, x, partials,
-                     status);
+  if (P.path_fp32)
+    hipLaunchKernelGGL(k_resid_fused<float>, dim3(grid), dim3(P.waves_per_block * kWave), lds, s, P, H, n, x,
+                       partials, status);
+  else
+    hipLaunchKernelGGL(k_resid_fused<double>, dim3(grid), dim3(P.waves_per_block * kWave), lds, s, P, H, n, x,
+                       partials, status);
   hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(256), 0, s, partials, (int64_t)grid, out);
   return hipGetLastError();
 }

@@ -7,13 +7,16 @@
 
 namespace pct {
 
-// One wavefront per proton.  mode 0: write the entry count to row_ptr[i + 1];
-// mode 1: write the row (idx, len, norm2) at row_ptr[i] (row_ptr already
-// scanned).  Both modes run the same code on the same inputs, so the fill
-// pass reproduces the counted rows exactly.
-__global__ void __launch_bounds__(256) k_trace(PathParams P, HistPtrs H, int64_t n, int mode, int64_t *row_ptr,
-                                               int32_t *idx, void *len, int32_t len_dtype, float len_scale,
-                                               double *norm2, uint32_t *status) {
+// One wavefront per proton of rows [i0, i0 + nrows): the row is built in LDS,
+// its entry count goes to cnt[q] and, when st_idx is given, its entries to
+// the staging slots [q * emax, q * emax + count) with ||a_i||^2 (FP64, from
+// the FP32 lengths) to norm2[i0 + q].  A single path pass per proton: the
+// compaction below moves the staged rows into CSR order once the counts are
+// scanned.
+template <typename R>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_trace_stage(PathParams P, HistPtrs H, int64_t i0, int64_t nrows,
+                                                     int64_t *cnt, int32_t *st_idx, float *st_len, double *norm2,
+                                                     uint32_t *status) {
   extern __shared__ int smem[];
   const int wid = threadIdx.x / kWave;
   const int lane = wave_lane();
@@ -21,32 +24,23 @@ __global__ void __launch_bounds__(256) k_trace(PathParams P, HistPtrs H, int64_t
   float *s_len = reinterpret_cast<float *>(s_vox + P.emax);
   int *s_aux = s_vox + 2 * P.emax;
   const int64_t stride = (int64_t)gridDim.x * P.waves_per_block;
-  for (int64_t i = (int64_t)blockIdx.x * P.waves_per_block + wid; i < n; i += stride) {
+  for (int64_t q = (int64_t)blockIdx.x * P.waves_per_block + wid; q < nrows; q += stride) {
+    const int64_t i = i0 + q;
     float h[10];
     load_history(H, i, h);
     bool fin = true;
-    for (int q = 0; q < 10; ++q) fin = fin && isfinite(h[q]);
+    for (int k = 0; k < 10; ++k) fin = fin && isfinite(h[k]);
     if (!fin && lane == 0) atomicOr(status, kStNonFinite);
-    const int cnt = build_row_any(P, h, s_vox, s_len, s_aux, status);
-    if (mode == 0) {
-      if (lane == 0) row_ptr[i + 1] = cnt;
-      continue;
-    }
-    const int64_t start = row_ptr[i];
-    const int64_t want = row_ptr[i + 1] - start;
-    if (want != cnt) {
-      if (lane == 0) atomicOr(status, kStRowMismatch);
-      if (lane == 0) norm2[i] = 0.0;
-      continue;
-    }
+    const int c = build_row<R>(P, h, s_vox, s_len, s_aux, status);
+    if (lane == 0) cnt[q] = c;
+    if (!st_idx) continue;
+    int32_t *di = st_idx + q * P.emax;
+    float *dl = st_len + q * P.emax;
     double acc = 0.0;
-    for (int e = lane; e < cnt; e += kWave) {
+    for (int e = lane; e < c; e += kWave) {
       const float l = s_len[e];
-      idx[start + e] = s_vox[e];
-      if (len_dtype == 0)
-        reinterpret_cast<float *>(len)[start + e] = l;
-      else
-        reinterpret_cast<__half *>(len)[start + e] = __float2half(l * len_scale);
+      di[e] = s_vox[e];
+      dl[e] = l;
       acc += (double)l * (double)l;
     }
     acc = wave_sum_f64(acc);
@@ -54,9 +48,39 @@ __global__ void __launch_bounds__(256) k_trace(PathParams P, HistPtrs H, int64_t
   }
 }
 
-// row_ptr[1..n] hold counts; turn them into offsets (row_ptr[0] = 0).
-// Three passes over chunks of kScanChunk: chunk totals, a scan of the totals
-// by one workgroup, then in-chunk scans with the chunk offset.
+// Staged rows [i0, i0 + nrows) -> CSR at row_ptr (already scanned), one
+// wavefront per row.  Rows that would end past the capacity are not written
+// (kStRowCap).  LDO: 0 float lengths, 1 half lengths in units of len_unit.
+template <int LDO>
+__global__ void __launch_bounds__(256) k_trace_compact(int64_t i0, int64_t nrows, const int64_t *__restrict__ row_ptr,
+                                                       const int32_t *__restrict__ st_idx,
+                                                       const float *__restrict__ st_len, int emax, int32_t *idx,
+                                                       void *len, float len_scale, int64_t cap, uint32_t *status) {
+  const int lane = wave_lane();
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kWave);
+  for (int64_t q = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; q < nrows; q += stride) {
+    const int64_t e0 = row_ptr[i0 + q], e1 = row_ptr[i0 + q + 1];
+    if (e1 > cap) {
+      if (lane == 0) atomicOr(status, kStRowCap);
+      continue;
+    }
+    const int c = (int)(e1 - e0);
+    const int32_t *si = st_idx + q * emax;
+    const float *sl = st_len + q * emax;
+    for (int e = lane; e < c; e += kWave) {
+      idx[e0 + e] = si[e];
+      if (LDO == 0)
+        reinterpret_cast<float *>(len)[e0 + e] = sl[e];
+      else
+        reinterpret_cast<__half *>(len)[e0 + e] = __float2half(sl[e] * len_scale);
+    }
+  }
+}
+
+// cnt[0..n) hold counts (cnt = row_ptr + i0 + 1); turn them into offsets that
+// continue from row_ptr[i0].  Three passes over chunks of kScanChunk: chunk
+// totals, a scan of the totals by one workgroup, then in-chunk scans with the
+// chunk offset.
 __global__ void __launch_bounds__(256) k_scan_totals(const int64_t *cnt, int64_t n, int64_t *tot) {
   __shared__ int64_t red[256];
   const int64_t c0 = (int64_t)blockIdx.x * kScanChunk;
@@ -71,10 +95,10 @@ __global__ void __launch_bounds__(256) k_scan_totals(const int64_t *cnt, int64_t
   if (threadIdx.x == 0) tot[blockIdx.x] = red[0];
 }
 
-__global__ void __launch_bounds__(256) k_scan_offsets(int64_t *tot, int64_t nchunks) {
+__global__ void __launch_bounds__(256) k_scan_offsets(int64_t *tot, int64_t nchunks, const int64_t *base) {
   __shared__ int64_t buf[256];
   __shared__ int64_t carry;
-  if (threadIdx.x == 0) carry = 0;
+  if (threadIdx.x == 0) carry = *base;
   __syncthreads();
   for (int64_t b = 0; b < nchunks; b += 256) {
     const int64_t e = b + threadIdx.x;
@@ -135,27 +159,43 @@ static inline unsigned grid_for(int64_t n, int per_block, unsigned cap) {
   return (unsigned)g;
 }
 
-hipError_t launch_trace(const PathParams &P, const HistPtrs &H, int64_t n, int mode, int64_t *row_ptr,
-                        int32_t *idx, void *len, int32_t len_dtype, double *norm2, uint32_t *status,
-                        hipStream_t s) {
-  if (n <= 0) return hipSuccess;
+hipError_t launch_trace_stage(const PathParams &P, const HistPtrs &H, int64_t i0, int64_t nrows, int64_t *cnt,
+                              int32_t *st_idx, float *st_len, double *norm2, uint32_t *status, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
   const unsigned threads = (unsigned)(P.waves_per_block * kWave);
   const size_t lds = (size_t)P.waves_per_block * 3 * P.emax * sizeof(int);
-  const unsigned grid = grid_for(n, P.waves_per_block, 1u << 20);
-  const float len_scale = 1.0f / fminf(P.dx, fminf(P.dy, P.dz));
-  hipLaunchKernelGGL(k_trace, dim3(grid), dim3(threads), lds, s, P, H, n, mode, row_ptr, idx, len, len_dtype,
-                     len_scale, norm2, status);
+  const unsigned grid = grid_for(nrows, P.waves_per_block, 1u << 20);
+  if (P.path_fp32)
+    hipLaunchKernelGGL(k_trace_stage<float>, dim3(grid), dim3(threads), lds, s, P, H, i0, nrows, cnt, st_idx, st_len,
+                       norm2, status);
+  else
+    hipLaunchKernelGGL(k_trace_stage<double>, dim3(grid), dim3(threads), lds, s, P, H, i0, nrows, cnt, st_idx,
+                       st_len, norm2, status);
   return hipGetLastError();
 }
 
-hipError_t launch_scan_rows(int64_t *row_ptr, int64_t n, int64_t *scan_tmp, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_first, dim3(1), dim3(1), 0, s, row_ptr);
-  if (n <= 0) return hipGetLastError();
-  const int64_t nchunks = (n + kScanChunk - 1) / kScanChunk;
-  int64_t *cnt = row_ptr + 1;
-  hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)nchunks), dim3(256), 0, s, cnt, n, scan_tmp);
-  hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(256), 0, s, scan_tmp, nchunks);
-  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nchunks), dim3(256), 0, s, cnt, n, scan_tmp);
+hipError_t launch_trace_compact(int64_t i0, int64_t nrows, const int64_t *row_ptr, const int32_t *st_idx,
+                                const float *st_len, int emax, int32_t *idx, void *len, int32_t len_dtype,
+                                float len_scale, int64_t cap, uint32_t *status, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  const unsigned grid = grid_for(nrows, 4, 1u << 20);
+  if (len_dtype == 0)
+    hipLaunchKernelGGL(k_trace_compact<0>, dim3(grid), dim3(256), 0, s, i0, nrows, row_ptr, st_idx, st_len, emax,
+                       idx, len, len_scale, cap, status);
+  else
+    hipLaunchKernelGGL(k_trace_compact<1>, dim3(grid), dim3(256), 0, s, i0, nrows, row_ptr, st_idx, st_len, emax,
+                       idx, len, len_scale, cap, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_rows(int64_t *row_ptr, int64_t i0, int64_t nrows, int64_t *scan_tmp, hipStream_t s) {
+  if (i0 == 0) hipLaunchKernelGGL(k_zero_first, dim3(1), dim3(1), 0, s, row_ptr);
+  if (nrows <= 0) return hipGetLastError();
+  const int64_t nchunks = (nrows + kScanChunk - 1) / kScanChunk;
+  int64_t *cnt = row_ptr + i0 + 1;
+  hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)nchunks), dim3(256), 0, s, cnt, nrows, scan_tmp);
+  hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(256), 0, s, scan_tmp, nchunks, row_ptr + i0);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nchunks), dim3(256), 0, s, cnt, nrows, scan_tmp);
   return hipGetLastError();
 }
 
