@@ -333,8 +333,8 @@ PlanDims plan_dims(const pct_grid *g, int64_t n, int64_t B) {
 int64_t plan_scratch_len(const PlanDims &d) { return d.nb * d.T + d.nb + 8; }
 
 enum {
-  L_REFBASE, L_BT_OFF, L_BT_CUR, L_CTILE, L_EMASK, L_CFE, L_PACKED, L_LEN, L_REFCNT, L_REFS, L_BPERM, L_N2PERM,
-  L_PARTIAL, L_RVALS, L_RESPART, L_BLKRES, L_SCANTMP, L_ENDSLOT, L_GRPOFF, L_PACKEDB, L_LENB, L_COUNT
+  L_REFBASE, L_BT_OFF, L_BT_CUR, L_RORD, L_ORDROW, L_RVALS, L_EMASK, L_CFE, L_PACKED, L_LEN, L_REFCNT, L_REFS, L_BPERM, L_N2PERM,
+  L_PARTIAL, L_RESPART, L_BLKRES, L_SCANTMP, L_ENDSLOT, L_GRPOFF, L_PACKEDB, L_LENB, L_COUNT
 };
 
 size_t plan_layout(const pct_plan *p, size_t off[L_COUNT]) {
@@ -342,10 +342,11 @@ size_t plan_layout(const pct_plan *p, size_t off[L_COUNT]) {
   const int64_t G = (p->block_size + 255) / 256;
   const size_t lb = p->len_dtype == 0 ? 4 : 2;
   const size_t sz[L_COUNT] = {(size_t)(p->n + 1) * 8,   (size_t)(nbT + 1) * 8,   (size_t)nbT * 8,
-                              (size_t)p->chunks * 4,   (size_t)p->chunks * 8,   (size_t)(p->chunks + 1) * 8,
+                              (size_t)p->max_ends * 4, (size_t)p->refs * 4, (size_t)p->block_size * 4,
+                              (size_t)p->chunks * 8,   (size_t)(p->chunks + 1) * 8,
                               (size_t)p->entries * 4,  (size_t)p->entries * lb, (size_t)p->n * 4,
                               (size_t)p->refs * 4,     (size_t)p->n * 4,         (size_t)p->n * 8,
-                              (size_t)p->max_ends * 4, (size_t)p->block_size * 4, (size_t)G * 8,
+                              (size_t)p->max_ends * 4, (size_t)G * 8,
                               (size_t)p->n_blocks * 8,
                               (size_t)((p->chunks + pct::kScanChunk - 1) / pct::kScanChunk + 2) * 8,
                               (size_t)p->refs * 4,
@@ -387,7 +388,9 @@ pct::PlanView plan_view(const pct_plan *p, float len_unit) {
   if (!m) return V;
   V.bt_off = reinterpret_cast<int64_t *>(m + off[L_BT_OFF]);
   V.bt_cur = reinterpret_cast<unsigned long long *>(m + off[L_BT_CUR]);
-  V.chunk_tile = reinterpret_cast<int32_t *>(m + off[L_CTILE]);
+  V.r_ord = reinterpret_cast<float *>(m + off[L_RORD]);
+  V.ord_row = reinterpret_cast<uint32_t *>(m + off[L_ORDROW]);
+  V.rvals = reinterpret_cast<float *>(m + off[L_RVALS]);
   V.end_mask = reinterpret_cast<uint64_t *>(m + off[L_EMASK]);
   V.chunk_first_end = reinterpret_cast<int64_t *>(m + off[L_CFE]);
   V.packed = reinterpret_cast<uint32_t *>(m + off[L_PACKED]);
@@ -398,7 +401,6 @@ pct::PlanView plan_view(const pct_plan *p, float len_unit) {
   V.b_perm = reinterpret_cast<float *>(m + off[L_BPERM]);
   V.n2_perm = reinterpret_cast<double *>(m + off[L_N2PERM]);
   V.partial = reinterpret_cast<float *>(m + off[L_PARTIAL]);
-  V.rvals = reinterpret_cast<float *>(m + off[L_RVALS]);
   V.res_part = reinterpret_cast<double *>(m + off[L_RESPART]);
   V.blk_res = reinterpret_cast<double *>(m + off[L_BLKRES]);
   V.end_slot = reinterpret_cast<uint32_t *>(m + off[L_ENDSLOT]);
@@ -467,6 +469,9 @@ pct_status do_plan_build(Ctx &c, const pct_grid *g, const pct_rows *rows, const 
     for (int64_t t = 0; t < d.T; ++t) {
       const int64_t k = b * d.T + t;
       const int64_t pad = (host[k] + 63) / 64 * 64;
+      if (pad >= (int64_t(1) << 24))
+        return fail(PCT_EINVAL, "block %lld has %lld entries in one tile (limit 2^24): use smaller blocks",
+                    (long long)b, (long long)pad);
       bt_off[k] = E;
       grp_off[(size_t)k * pct::kGroups] = EB;
       E += pad;
@@ -510,9 +515,9 @@ pct_status do_plan_build(Ctx &c, const pct_grid *g, const pct_rows *rows, const 
   PROF(PCT_K_PLAN_BUILD, pct::launch_plan_fill(rows->row_ptr, rows->idx, rows->len, rows->len_dtype, params->order,
                                                c.H.wepl, rows->norm2, c.M, V, c.W.status, c.s));
   PROF(PCT_K_PLAN_BUILD, pct::launch_plan_chunks(V, c.s));
-  PROF(PCT_K_PLAN_BUILD, pct::launch_plan_build_voxel_major(V, c.s));
   HIPCHECK(pct::launch_scan_rows(V.chunk_first_end, 0, tmp.chunks, plan_scan_tmp(&tmp), c.s));
   PROF(PCT_K_PLAN_BUILD, pct::launch_plan_ref_ordinals(V, c.s));
+  PROF(PCT_K_PLAN_BUILD, pct::launch_plan_build_voxel_major(V, c.s));
   int64_t refs_total = 0;
   HIPCHECK(hipMemcpyAsync(&refs_total, V.ref_base + c.n, 8, hipMemcpyDeviceToHost, c.s));
   if ((r = read_status(c, &st)) != PCT_OK) return r;

@@ -84,7 +84,9 @@ struct PlanView {
   float len_unit;
   int64_t *bt_off;          // [nb*T + 1] entry offsets of each (block, tile) list (multiples of 64)
   unsigned long long *bt_cur;  // [nb*T] fill cursors
-  int32_t *chunk_tile;      // [C] linear index of the first voxel of the chunk's tile
+  uint32_t *ord_row;        // [R] per piece end (global ordinal): its row in the block
+  float *r_ord;             // [P] r of the row of every piece end of one block, in ordinal order
+  float *rvals;             // [B] r_i of one block
   uint64_t *end_mask;       // [C] lanes that close a piece (or a chunk)
   int64_t *chunk_first_end; // [C + 1]
   uint32_t *packed;         // [E]
@@ -96,12 +98,12 @@ struct PlanView {
   float *b_perm;            // [n] b in block order
   double *n2_perm;          // [n] ||a||^2 in block order
   float *partial;           // [P] per-piece partial dot products of one block, in row order
-  float *rvals;             // [B] r_i of one block
   double *res_part;         // [ceil(B/256)] residual partial sums of one block
   double *blk_res;          // [nb] squared residual per block
   // voxel-major copy for the scatter: per (block, tile, group of 64 tile-local
   // voxels) the entries sorted by voxel; packed: bit 0 valid, bit 1 last entry
-  // of its voxel, bits 2..7 voxel in group, bits 13..30 row in block
+  // of its voxel, bits 2..7 voxel in group, bits 8..31 offset of the entry's
+  // piece-end ordinal from the first ordinal of its (block, tile) list
   int64_t EB;               // entries (= nnz of the rows)
   int64_t *grp_off;         // [nb*T*kGroups + 1]
   uint32_t *packedB;        // [EB]

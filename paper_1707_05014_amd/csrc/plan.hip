@@ -217,16 +217,6 @@ __global__ void __launch_bounds__(256) k_plan_fill(const int64_t *__restrict__ r
   if (lane == 0) V.ref_cnt[q] = (int32_t)(nref < rcap ? nref : rcap);
 }
 
-// chunk -> linear index of its tile's first voxel (one workgroup per (block, tile) list)
-__global__ void __launch_bounds__(256) k_plan_chunk_tile(PlanView V) {
-  const int64_t k = blockIdx.x;
-  if (k >= V.nb * V.T) return;
-  const int64_t c0 = V.bt_off[k] / kWave, c1 = V.bt_off[k + 1] / kWave;
-  bool inside;
-  const int base = tile_voxel((int)(k % V.T), 0, V, inside);
-  for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) V.chunk_tile[c] = base;
-}
-
 // lanes that close a piece (or a chunk) and their count per chunk
 __global__ void __launch_bounds__(256) k_plan_chunk_ends(PlanView V) {
   const int lane = wave_lane();
@@ -264,68 +254,126 @@ __device__ __forceinline__ float plan_len(const PlanView &V, int64_t p) {
     return __half2float(reinterpret_cast<const __half *>(V.len)[p]) * V.len_unit;
 }
 
-// partial dot products of every piece of block b; a wavefront takes
-// kChunksPerWave consecutive chunks
-constexpr int kChunksPerWave = 8;
+// Partial dot products of every piece of block b.  kDotSplit workgroups of
+// kPlanWaves wavefronts per (block, tile) list, each on an equal share of
+// its chunks (many more workgroups than CUs can hold at once, so the work
+// spreads evenly): x of the tile is staged in LDS
+// (the entries then read it with LDS gathers instead of L1/L2 gathers), and
+// the wavefronts walk batches of kDotBatch consecutive chunks of the list in
+// two levels: level 1 loads the entries, lengths and per-chunk ordinals of a
+// batch; level 2 reads x from LDS and loads the end_slot slices of the
+// chunks.  The level-1 loads of the next batch are issued before the current
+// batch is reduced, so they stay in flight meanwhile.
+#ifndef PCT_DOT_BATCH
+#define PCT_DOT_BATCH 8
+#endif
+constexpr int kDotBatch = PCT_DOT_BATCH;
+constexpr int kPlanWaves = 8;
+constexpr int kPlanThreads = kPlanWaves * kWave;
+constexpr int kDotSplit = 4;   // workgroups per (block, tile) list, each on a quarter of its chunks
 
 template <int LD>
-__global__ void __launch_bounds__(256) k_plan_dot(PlanView V, int64_t b, const float *__restrict__ x) {
-  const int lane = wave_lane();
-  const int64_t c0 = V.bt_off[b * V.T] / kWave, c1 = V.bt_off[(b + 1) * V.T] / kWave;
-  const int64_t cw = c0 + ((int64_t)blockIdx.x * 4 + threadIdx.x / kWave) * kChunksPerWave;
-  if (cw >= c1) return;
-  const int nc = (int)(cw + kChunksPerWave < c1 ? kChunksPerWave : c1 - cw);
-  const int nxy = V.nx * V.ny;
-  // issue every load of the wavefront's chunks before using any of them
-  uint32_t v[kChunksPerWave];
-  float l[kChunksPerWave];
-  int cb[kChunksPerWave];
+__device__ __forceinline__ void dot_level1(const PlanView &V, int64_t cw, int nc, int lane, uint32_t (&v)[kDotBatch],
+                                           float (&l)[kDotBatch], int64_t (&fe)[kDotBatch + 1]) {
 #pragma unroll
-  for (int k = 0; k < kChunksPerWave; ++k) {
+  for (int k = 0; k < kDotBatch; ++k) {
     v[k] = 0u;
     l[k] = 0.f;
-    cb[k] = 0;
     if (k < nc) {
       const int64_t p = (cw + k) * kWave + lane;
       v[k] = __builtin_nontemporal_load(V.packed + p);
       l[k] = plan_len<LD>(V, p);
-      cb[k] = V.chunk_tile[cw + k];
-    }
-  }
-  float xv[kChunksPerWave];
-#pragma unroll
-  for (int k = 0; k < kChunksPerWave; ++k) {
-    xv[k] = 0.f;
-    if (v[k] & 1u) {
-      const int local = (v[k] >> 2) & (kTileVox - 1);
-      const int gv = cb[k] + (local >> 8) * nxy + ((local >> 4) & 15) * V.nx + (local & 15);
-      xv[k] = x[gv];
     }
   }
 #pragma unroll
-  for (int k = 0; k < kChunksPerWave; ++k) {
-    if (k >= nc) break;
-    const bool valid = v[k] & 1u;
-    const bool close = valid && (((v[k] >> 1) & 1u) || lane == kWave - 1);
-    const uint64_t m = __ballot(close);
-    // a piece's sum is the difference of the prefix sums at its closing lane
-    // and at the previous closing lane
-    const float S = wave_incl_scan_dpp(valid ? l[k] * xv[k] : 0.0f);
-    const uint64_t below = m & ((1ull << lane) - 1);
-    const int prev = below ? 63 - __clzll(below) : lane;
-    const float Sp = __shfl(S, prev, kWave);
-    if (close) {
-      // end_slot is indexed by the global ordinal of the piece end
-      const int64_t ord = V.chunk_first_end[cw + k] + __popcll(below);
-      V.partial[V.end_slot[ord]] = below ? S - Sp : S;
+  for (int k = 0; k <= kDotBatch; ++k) fe[k] = k <= nc ? V.chunk_first_end[cw + k] : 0;
+}
+
+// x of tile t (2048 voxels, zero outside the grid) -> s_x
+__device__ __forceinline__ void stage_tile_x(const PlanView &V, int64_t t, const float *__restrict__ x, float *s_x) {
+  const int tx = (int)(t % V.ntx), r = (int)(t / V.ntx), ty = r % V.nty, tz = r / V.nty;
+  for (int i = threadIdx.x; i < kTileVox; i += blockDim.x) {
+    const int ix = tx * kTX + (i & 15), iy = ty * kTY + ((i >> 4) & 15), iz = tz * kTZ + (i >> 8);
+    s_x[i] = (ix < V.nx && iy < V.ny && iz < V.nz) ? x[((int64_t)iz * V.ny + iy) * V.nx + ix] : 0.0f;
+  }
+}
+
+template <int LD>
+__global__ void __launch_bounds__(kPlanThreads) k_plan_dot(PlanView V, int64_t b, const float *__restrict__ x) {
+  __shared__ float s_x[kTileVox];
+  const int lane = wave_lane();
+  const int64_t t = blockIdx.x / kDotSplit;
+  const int part = blockIdx.x % kDotSplit;
+  const int64_t lk = b * V.T + t;
+  const int64_t la = V.bt_off[lk] / kWave, lb = V.bt_off[lk + 1] / kWave;
+  const int64_t ca = la + (lb - la) * part / kDotSplit, cb = la + (lb - la) * (part + 1) / kDotSplit;
+  if (ca == cb) return;  // the whole workgroup leaves
+  stage_tile_x(V, t, x, s_x);
+  __syncthreads();
+  const int64_t nbat = (cb - ca + kDotBatch - 1) / kDotBatch;
+  int64_t j = uniform((int)(threadIdx.x / kWave));
+  if (j >= nbat) return;
+  uint32_t v[kDotBatch];
+  float l[kDotBatch];
+  int64_t fe[kDotBatch + 1];
+  int64_t cw = ca + j * kDotBatch;
+  int nc = (int)(cb - cw < kDotBatch ? cb - cw : kDotBatch);
+  dot_level1<LD>(V, cw, nc, lane, v, l, fe);
+  for (;;) {
+    // level 2 of the current batch
+    float xv[kDotBatch];
+    uint32_t es[kDotBatch];
+#pragma unroll
+    for (int k = 0; k < kDotBatch; ++k) {
+      xv[k] = (v[k] & 1u) ? s_x[(v[k] >> 2) & (kTileVox - 1)] : 0.f;
+      es[k] = (k < nc && lane < fe[k + 1] - fe[k]) ? V.end_slot[fe[k] + lane] : 0u;
     }
+    // level 1 of the next batch
+    const int64_t jn = j + kPlanWaves;
+    uint32_t vn[kDotBatch];
+    float ln[kDotBatch];
+    int64_t fen[kDotBatch + 1];
+    int64_t cwn = 0;
+    int ncn = 0;
+    if (jn < nbat) {
+      cwn = ca + jn * kDotBatch;
+      ncn = (int)(cb - cwn < kDotBatch ? cb - cwn : kDotBatch);
+      dot_level1<LD>(V, cwn, ncn, lane, vn, ln, fen);
+    }
+#pragma unroll
+    for (int k = 0; k < kDotBatch; ++k) {
+      if (k >= nc) continue;  // nc is wave-uniform
+      const bool valid = v[k] & 1u;
+      const bool close = valid && (((v[k] >> 1) & 1u) || lane == kWave - 1);
+      const uint64_t m = __ballot(close);
+      // a piece's sum is the difference of the prefix sums at its closing lane
+      // and at the previous closing lane
+      const float S = wave_incl_scan_dpp(valid ? l[k] * xv[k] : 0.0f);
+      const uint64_t below = m & ((1ull << lane) - 1);
+      const int prev = below ? 63 - __clzll(below) : lane;
+      const float Sp = __shfl(S, prev, kWave);
+      // the end_slot entry of this chunk's n-th piece end sits in lane n
+      const uint32_t slot = (uint32_t)__shfl((int)es[k], __popcll(below), kWave);
+      if (close) V.partial[slot] = below ? S - Sp : S;
+    }
+    if (jn >= nbat) break;
+    j = jn;
+    cw = cwn;
+    nc = ncn;
+#pragma unroll
+    for (int k = 0; k < kDotBatch; ++k) {
+      v[k] = vn[k];
+      l[k] = ln[k];
+    }
+#pragma unroll
+    for (int k = 0; k <= kDotBatch; ++k) fe[k] = fen[k];
   }
 }
 
 // references hold entry positions after the fill pass; record, for every
-// piece end (block-relative ordinal in chunk order), the row-ordered slot of
-// its reference, so k_plan_dot can store each partial next to the other
-// partials of its row
+// piece end (global ordinal in chunk order), the row-ordered slot of its
+// reference, so k_plan_dot can store each partial next to the other partials
+// of its row, and its row in the block, so k_plan_expand can give it r
 __global__ void __launch_bounds__(256) k_plan_ref_ordinals(PlanView V) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= V.n) return;
@@ -339,6 +387,7 @@ __global__ void __launch_bounds__(256) k_plan_ref_ordinals(PlanView V) {
     const int l = p & (kWave - 1);
     const int64_t ord = V.chunk_first_end[c] + __popcll(V.end_mask[c] & ((1ull << l) - 1));
     V.end_slot[ord] = (uint32_t)(k0 + k - rb);
+    V.ord_row[ord] = (uint32_t)(q - b * V.B);
   }
 }
 
@@ -362,6 +411,17 @@ __global__ void __launch_bounds__(256) k_plan_rows(PlanView V, int64_t b) {
   int nref;
   const float d = row_dot(V, q, V.ref_base[b * V.B], nref);
   V.rvals[r] = nref ? (float)(((double)V.b_perm[q] - (double)d) / V.n2_perm[q]) : 0.0f;
+}
+
+// r of every piece end of block b, in ordinal order (coalesced writes; the
+// rows are gathered), so the scatter can stage a tile's r values with
+// contiguous loads
+__global__ void __launch_bounds__(256) k_plan_expand(PlanView V, int64_t b) {
+  const int64_t ob = V.chunk_first_end[V.bt_off[b * V.T] / kWave];
+  const int64_t oe = V.chunk_first_end[V.bt_off[(b + 1) * V.T] / kWave];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t o = ob + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < oe; o += stride)
+    V.r_ord[o - ob] = V.rvals[V.ord_row[o]];
 }
 
 // squared residuals of block b's rows: per-workgroup FP64 sums
@@ -389,7 +449,10 @@ __global__ void __launch_bounds__(256) k_plan_resid_rows(PlanView V, int64_t b, 
 
 // Voxel-major copy of one (block, tile) list: counting sort by tile-local
 // voxel in LDS (one workgroup per list).  Group offsets go to grp_off; the
-// last entry of each voxel's run is flagged.
+// last entry of each voxel's run is flagged; each entry carries the offset of
+// its piece-end ordinal from the list's first ordinal (so the scatter can read
+// its r from the list's ordinals staged in LDS).  Needs end_mask and
+// chunk_first_end.
 __global__ void __launch_bounds__(256) k_plan_voxel_major(PlanView V) {
   __shared__ uint32_t s_cnt[kTileVox];
   __shared__ uint32_t s_pos[kTileVox];
@@ -435,6 +498,7 @@ __global__ void __launch_bounds__(256) k_plan_voxel_major(PlanView V) {
     if ((vox & 63) == 0 && vox > 0) V.grp_off[k * kGroups + vox / 64] = base + excl + loc[q];
   }
   __syncthreads();
+  const int64_t o0 = a0 < a1 ? V.chunk_first_end[a0 / kWave] : 0;
   for (int64_t p = a0 + threadIdx.x; p < a1; p += blockDim.x) {
     const uint32_t v = V.packed[p];
     if (!(v & 1u)) continue;
@@ -443,7 +507,12 @@ __global__ void __launch_bounds__(256) k_plan_voxel_major(PlanView V) {
     const uint32_t last = slot == s_start[vox] + s_cnt[vox] - 1u ? 2u : 0u;  // closes the voxel's run
     const int64_t dst = base + slot;
     if (dst >= V.grp_off[(k + 1) * kGroups]) continue;  // cannot happen when the counts agree
-    V.packedB[dst] = 1u | last | ((uint32_t)(vox & 63) << 2) | (v & ~((1u << 13) - 1u));
+    // the piece end at or after this entry's lane: closes strictly below it
+    // belong to earlier pieces of the chunk
+    const int64_t c = p / kWave;
+    const int l = (int)(p & (kWave - 1));
+    const int64_t ord = V.chunk_first_end[c] + __popcll(V.end_mask[c] & ((1ull << l) - 1));
+    V.packedB[dst] = 1u | last | ((uint32_t)(vox & 63) << 2) | ((uint32_t)(ord - o0) << 8);
     if (V.len_dtype == 0)
       reinterpret_cast<float *>(V.lenB)[dst] = reinterpret_cast<const float *>(V.len)[p];
     else
@@ -451,77 +520,140 @@ __global__ void __launch_bounds__(256) k_plan_voxel_major(PlanView V) {
   }
 }
 
-// Scatter of block b, voxel-major: one wavefront per 64-voxel group of a tile.
-// Each voxel's run is reduced with DPP prefix sums (its length is s_j); the
-// lane closing the run applies x_j += lambda num_j / s_j.  No atomics.
+#ifndef PCT_SCAT_BATCH
+#define PCT_SCAT_BATCH 6
+#endif
+constexpr int kScatBatch = PCT_SCAT_BATCH;
+
 template <int LD>
-__global__ void __launch_bounds__(256) k_plan_scatter(PlanView V, int64_t b, float *__restrict__ x,
-                                                      const uint8_t *__restrict__ mask, float lambda) {
+__device__ __forceinline__ void scatter_level1(const PlanView &V, int64_t wb, int64_t e1, int lane,
+                                               uint32_t (&v)[kScatBatch], float (&val)[kScatBatch]) {
+#pragma unroll
+  for (int k = 0; k < kScatBatch; ++k) {
+    const int64_t p = wb + (int64_t)k * kWave + lane;
+    v[k] = 0u;
+    val[k] = 0.0f;
+    if (p < e1) {
+      v[k] = __builtin_nontemporal_load(V.packedB + p);
+      val[k] = LD == 0 ? __builtin_nontemporal_load(reinterpret_cast<const float *>(V.lenB) + p)
+                       : __half2float(reinterpret_cast<const __half *>(V.lenB)[p]) * V.len_unit;
+    }
+  }
+}
+
+// Scatter of block b, voxel-major.  kScatSplit workgroups per (block, tile),
+// each on an equal share of the tile's 64-voxel groups: r of every piece end
+// of the tile's list is staged in LDS from r_ord (ordinal order; a list with
+// more than kStageOrd ordinals reads r_ord directly instead), then each
+// wavefront takes groups of the share in turn.
+// A voxel's run is reduced with DPP prefix sums (its length is s_j); the lane
+// closing the run leaves (num_j, s_j) in the wavefront's LDS slots, one per
+// voxel of the group (every voxel has exactly one run per list).  After the
+// group, lane l applies x_j += lambda num_j / s_j to voxel l of the group.
+// No atomics.
+constexpr int kStageOrd = 12288;
+constexpr int kScatSplit = 4;  // workgroups per (block, tile), each on a quarter of its voxel groups
+
+template <int LD>
+__global__ void __launch_bounds__(kPlanThreads) k_plan_scatter(PlanView V, int64_t b, float *__restrict__ x,
+                                                               const uint8_t *__restrict__ mask, float lambda) {
+  __shared__ float s_r[kStageOrd];
+  __shared__ float s_num[kPlanWaves][kWave];
+  __shared__ uint32_t s_cnt[kPlanWaves][kWave];
   const int lane = wave_lane();
-  const int64_t g = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;  // group within the block
-  if (g >= V.T * kGroups) return;
-  const int64_t t = g / kGroups;
-  const int grp = (int)(g % kGroups);
-  const int64_t gi = (b * V.T + t) * kGroups + grp;
-  const int64_t e0 = V.grp_off[gi], e1 = V.grp_off[gi + 1];
-  if (e0 == e1) return;
-  bool inside;
-  const int tile_base = tile_voxel((int)t, 0, V, inside);
-  const int nxy = V.nx * V.ny;
-  float carry = 0.0f;  // sum of the run that continues from the previous chunk
-  int carry_n = 0;
-  constexpr int U = 4;  // chunks whose loads are issued together
-  for (int64_t wb = e0; wb < e1; wb += (int64_t)U * kWave) {
-    uint32_t v[U];
-    float val[U];
+  const int wid = uniform((int)(threadIdx.x / kWave));
+  const int64_t t = blockIdx.x / kScatSplit;
+  const int part = blockIdx.x % kScatSplit;
+  const int64_t lk = b * V.T + t;
+  const int64_t a0 = V.bt_off[lk], a1 = V.bt_off[lk + 1];
+  if (a0 == a1) return;  // the whole workgroup leaves
+  // r of the list's piece ends, in ordinal order
+  const float *r_list = V.r_ord + (V.chunk_first_end[a0 / kWave] - V.chunk_first_end[V.bt_off[b * V.T] / kWave]);
+  const int64_t nord = V.chunk_first_end[a1 / kWave] - V.chunk_first_end[a0 / kWave];
+  const bool staged = nord <= kStageOrd;
+  if (staged)
+    for (int64_t i = threadIdx.x; i < nord; i += kPlanThreads) s_r[i] = r_list[i];
+  __syncthreads();
+  constexpr int kGroupsPerPart = kGroups / kScatSplit;
+  for (int grp = part * kGroupsPerPart + wid; grp < (part + 1) * kGroupsPerPart; grp += kPlanWaves) {
+    const int64_t gi = lk * kGroups + grp;
+    const int64_t e0 = V.grp_off[gi], e1 = V.grp_off[gi + 1];
+    if (e0 == e1) continue;
+    // this lane's voxel of the group: its x and mask are fetched before the loop
+    bool inside;
+    const int gv = tile_voxel((int)t, grp * kWave + lane, V, inside);
+    float xl = 0.0f;
+    bool keep = true;
+    if (inside) {
+      xl = x[gv];
+      if (mask) keep = mask[gv] != 0;
+    }
+    s_num[wid][lane] = 0.0f;
+    s_cnt[wid][lane] = 0u;
+    float carry = 0.0f;  // sum of the run that continues from the previous chunk
+    int carry_n = 0;
+    // batches of kScatBatch chunks: the entries of the next batch are loaded
+    // while the current batch is reduced
+    uint32_t v[kScatBatch];
+    float val[kScatBatch];
+    scatter_level1<LD>(V, e0, e1, lane, v, val);
+    for (int64_t wb = e0; wb < e1; wb += (int64_t)kScatBatch * kWave) {
+      float r[kScatBatch];
 #pragma unroll
-    for (int k = 0; k < U; ++k) {
-      const int64_t p = wb + (int64_t)k * kWave + lane;
-      v[k] = 0u;
-      val[k] = 0.0f;
-      if (p < e1) {
-        v[k] = __builtin_nontemporal_load(V.packedB + p);
-        val[k] = LD == 0 ? __builtin_nontemporal_load(reinterpret_cast<const float *>(V.lenB) + p)
-                         : __half2float(reinterpret_cast<const __half *>(V.lenB)[p]) * V.len_unit;
+      for (int k = 0; k < kScatBatch; ++k) {
+        r[k] = 0.0f;
+        if (v[k] & 1u) r[k] = staged ? s_r[v[k] >> 8] : r_list[v[k] >> 8];
+      }
+      const int64_t wn = wb + (int64_t)kScatBatch * kWave;
+      uint32_t vn[kScatBatch];
+      float valn[kScatBatch];
+      if (wn < e1) scatter_level1<LD>(V, wn, e1, lane, vn, valn);
+#pragma unroll
+      for (int k = 0; k < kScatBatch; ++k) {
+        const int64_t w = wb + (int64_t)k * kWave;
+        if (w >= e1) continue;  // wave-uniform
+        const bool close = (v[k] & 1u) && ((v[k] >> 1) & 1u);
+        const uint64_t m = __ballot(close);
+        const float S = wave_incl_scan_dpp(val[k] * r[k]);
+        const uint64_t below = m & ((1ull << lane) - 1);
+        const int prev = below ? 63 - __clzll(below) : -1;
+        const float Sp = __shfl(S, prev < 0 ? 0 : prev, kWave);
+        if (close) {
+          const int vg = (v[k] >> 2) & 63;
+          s_num[wid][vg] = prev >= 0 ? S - Sp : S + carry;
+          s_cnt[wid][vg] = (uint32_t)(prev >= 0 ? lane - prev : lane + 1 + carry_n);
+        }
+        // the run still open at the end of this chunk carries into the next one
+        const int nv = (int)(e1 - w < kWave ? e1 - w : kWave);
+        const int last_close = m ? 63 - __clzll(m) : -1;
+        const float S_end = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, S), nv - 1));
+        const float S_lc = __builtin_bit_cast(
+            float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, S), last_close < 0 ? 0 : last_close));
+        if (last_close == nv - 1) {
+          carry = 0.0f;
+          carry_n = 0;
+        } else if (last_close < 0) {
+          carry += S_end;
+          carry_n += nv;
+        } else {
+          carry = S_end - S_lc;
+          carry_n = nv - 1 - last_close;
+        }
+      }
+      if (wn < e1) {
+#pragma unroll
+        for (int k = 0; k < kScatBatch; ++k) {
+          v[k] = vn[k];
+          val[k] = valn[k];
+        }
       }
     }
-#pragma unroll
-    for (int k = 0; k < U; ++k)
-      if (v[k] & 1u) val[k] *= V.rvals[v[k] >> 13];
-#pragma unroll
-    for (int k = 0; k < U; ++k) {
-      const int64_t w = wb + (int64_t)k * kWave;
-      if (w >= e1) break;
-      const bool close = (v[k] & 1u) && ((v[k] >> 1) & 1u);
-      const uint64_t m = __ballot(close);
-      const float S = wave_incl_scan_dpp(val[k]);
-      const uint64_t below = m & ((1ull << lane) - 1);
-      const int prev = below ? 63 - __clzll(below) : -1;
-      const float Sp = __shfl(S, prev < 0 ? 0 : prev, kWave);
-      if (close) {
-        const float num = prev >= 0 ? S - Sp : S + carry;
-        const int cnt = prev >= 0 ? lane - prev : lane + 1 + carry_n;
-        const int local = grp * 64 + ((v[k] >> 2) & 63);
-        const int gv = tile_base + (local >> 8) * nxy + ((local >> 4) & 15) * V.nx + (local & 15);
-        const float xn = x[gv] + lambda * num / (float)cnt;
-        x[gv] = (mask && !mask[gv]) ? 0.0f : xn;
-      }
-      // the run still open at the end of this chunk carries into the next one
-      const int nv = (int)(e1 - w < kWave ? e1 - w : kWave);
-      const int last_close = m ? 63 - __clzll(m) : -1;
-      const float S_end = __shfl(S, nv - 1, kWave);
-      const float S_lc = __shfl(S, last_close < 0 ? 0 : last_close, kWave);
-      if (last_close == nv - 1) {
-        carry = 0.0f;
-        carry_n = 0;
-      } else if (last_close < 0) {
-        carry += S_end;
-        carry_n += nv;
-      } else {
-        carry = S_end - S_lc;
-        carry_n = nv - 1 - last_close;
-      }
-    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t c = s_cnt[wid][lane];
+    if (inside && c) x[gv] = keep ? xl + lambda * s_num[wid][lane] / (float)c : 0.0f;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -590,25 +722,22 @@ hipError_t launch_plan_ref_ordinals(const PlanView &V, hipStream_t s) {
 }
 
 hipError_t launch_plan_chunks(const PlanView &V, hipStream_t s) {
-  if (V.nb * V.T > 0)
-    hipLaunchKernelGGL(k_plan_chunk_tile, dim3((unsigned)(V.nb * V.T)), dim3(256), 0, s, V);
   if (V.C > 0) hipLaunchKernelGGL(k_plan_chunk_ends, dim3(grid_for(V.C, 4, 0x7fffffffu)), dim3(256), 0, s, V);
   return hipGetLastError();
 }
 
 hipError_t launch_plan_dot(const PlanView &V, int64_t b, const float *x, hipStream_t s) {
-  // chunks of the block are not known on the host: launch for the largest block
-  // (wavefronts past the block's last chunk exit at once)
-  const unsigned g = grid_for((V.maxc + kChunksPerWave - 1) / kChunksPerWave, 4, 0x7fffffffu);
+  if (V.T <= 0) return hipSuccess;
   if (V.len_dtype == 0)
-    hipLaunchKernelGGL(k_plan_dot<0>, dim3(g), dim3(256), 0, s, V, b, x);
+    hipLaunchKernelGGL(k_plan_dot<0>, dim3((unsigned)(V.T * kDotSplit)), dim3(kPlanThreads), 0, s, V, b, x);
   else
-    hipLaunchKernelGGL(k_plan_dot<1>, dim3(g), dim3(256), 0, s, V, b, x);
+    hipLaunchKernelGGL(k_plan_dot<1>, dim3((unsigned)(V.T * kDotSplit)), dim3(kPlanThreads), 0, s, V, b, x);
   return hipGetLastError();
 }
 
 hipError_t launch_plan_rows(const PlanView &V, int64_t b, hipStream_t s) {
   hipLaunchKernelGGL(k_plan_rows, dim3(grid_for(V.B, 256, 0x7fffffffu)), dim3(256), 0, s, V, b);
+  hipLaunchKernelGGL(k_plan_expand, dim3(grid_for(V.P, 256, 8192)), dim3(256), 0, s, V, b);
   return hipGetLastError();
 }
 
@@ -619,11 +748,13 @@ hipError_t launch_plan_resid_rows(const PlanView &V, int64_t b, double *partials
 
 hipError_t launch_plan_scatter(const PlanView &V, int64_t b, float *x, const uint8_t *mask, float lambda,
                                hipStream_t s) {
-  const unsigned g = grid_for(V.T * kGroups, 4, 0x7fffffffu);
+  if (V.T <= 0) return hipSuccess;
   if (V.len_dtype == 0)
-    hipLaunchKernelGGL(k_plan_scatter<0>, dim3(g), dim3(256), 0, s, V, b, x, mask, lambda);
+    hipLaunchKernelGGL(k_plan_scatter<0>, dim3((unsigned)(V.T * kScatSplit)), dim3(kPlanThreads), 0, s, V, b, x,
+                       mask, lambda);
   else
-    hipLaunchKernelGGL(k_plan_scatter<1>, dim3(g), dim3(256), 0, s, V, b, x, mask, lambda);
+    hipLaunchKernelGGL(k_plan_scatter<1>, dim3((unsigned)(V.T * kScatSplit)), dim3(kPlanThreads), 0, s, V, b, x,
+                       mask, lambda);
   return hipGetLastError();
 }
 

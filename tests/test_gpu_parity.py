@@ -299,6 +299,23 @@ def test_plan_ragged_grid_and_blocks():
     assert np.allclose(rg, ro, rtol=1e-3)
 
 
+def test_plan_long_lists(cfg1):
+    """One block of all 1e5 rows: every tile list holds far more piece ends
+    than the scatter stages in LDS, so r is read through the ordinal-to-row
+    map instead (checked against the oracle)."""
+    cfg, h, R = cfg1
+    _say("plan with one block of 100000 rows (unstaged scatter lists)")
+    xo, ro, order, mask = _run_oracle(cfg, h, R, "drop", cfg.n, 3)
+    xg, rg, plan, _ = _plan_run(cfg, h, cfg.n, 3, order, mask)
+    s = plan.struct
+    _say(f"  plan: entries {s.entries} refs {s.refs} tiles {s.n_tiles}")
+    assert s.refs / s.n_tiles > 12288  # lists longer than the LDS stage, on average
+    rel = _rel(xg, xo)
+    _say(f"  image rel-L2 {rel:.2e}")
+    assert rel <= IMG_TOL
+    assert np.allclose(rg, ro, rtol=1e-3)
+
+
 def test_plan_f16_rows_match_csr(cfg1):
     """FP16-length plan against the FP16-length CSR path (same matrix)."""
     cfg, h, R = cfg1
