@@ -334,7 +334,7 @@ int64_t plan_scratch_len(const PlanDims &d) { return d.nb * d.T + d.nb + 8; }
 
 enum {
   L_REFBASE, L_BT_OFF, L_BT_CUR, L_RORD, L_ORDROW, L_RVALS, L_EMASK, L_CFE, L_PACKED, L_LEN, L_REFCNT, L_REFS, L_BPERM, L_N2PERM,
-  L_PARTIAL, L_RESPART, L_BLKRES, L_SCANTMP, L_ENDSLOT, L_GRPOFF, L_PACKEDB, L_LENB, L_COUNT
+  L_PARTIAL, L_RESPART, L_BLKRES, L_SCANTMP, L_ENDSLOT, L_GRPOFF, L_PACKEDB, L_LENB, L_TMPB, L_TMPLENB, L_COUNT
 };
 
 size_t plan_layout(const pct_plan *p, size_t off[L_COUNT]) {
@@ -351,6 +351,8 @@ size_t plan_layout(const pct_plan *p, size_t off[L_COUNT]) {
                               (size_t)((p->chunks + pct::kScanChunk - 1) / pct::kScanChunk + 2) * 8,
                               (size_t)p->refs * 4,
                               (size_t)(nbT * pct::kGroups + 1) * 8,
+                              (size_t)p->entries_vm * 4,
+                              (size_t)p->entries_vm * lb,
                               (size_t)p->entries_vm * 4,
                               (size_t)p->entries_vm * lb};
   size_t o = 0;
@@ -407,6 +409,8 @@ pct::PlanView plan_view(const pct_plan *p, float len_unit) {
   V.grp_off = reinterpret_cast<int64_t *>(m + off[L_GRPOFF]);
   V.packedB = reinterpret_cast<uint32_t *>(m + off[L_PACKEDB]);
   V.lenB = m + off[L_LENB];
+  V.tmpB = reinterpret_cast<uint32_t *>(m + off[L_TMPB]);
+  V.tmp_lenB = m + off[L_TMPLENB];
   return V;
 }
 

@@ -24,16 +24,60 @@ namespace pct {
 
 __device__ __forceinline__ int wave_lane() { return __lane_id(); }
 
+// Cross-lane moves with DPP (GFX9 data-parallel primitives; no LDS traffic).
+// Row shifts move data within rows of 16 lanes, row broadcasts carry lane 15
+// of a row into the next row(s); wave shifts move data by one lane across the
+// whole wavefront.  Lanes without a source lane read 0.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+constexpr int kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138;
+
+// Orders this wavefront's LDS accesses across lanes (a write by one lane,
+// then a read by another) without waiting for its outstanding global loads.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// inclusive prefix sum over the 64 lanes
+__device__ __forceinline__ int wave_incl_scan_i32(int x) {
+  x += __builtin_amdgcn_update_dpp(0, x, kDppRowShr1, 0xf, 0xf, false);
+  x += __builtin_amdgcn_update_dpp(0, x, kDppRowShr2, 0xf, 0xf, false);
+  x += __builtin_amdgcn_update_dpp(0, x, kDppRowShr4, 0xf, 0xf, false);
+  x += __builtin_amdgcn_update_dpp(0, x, kDppRowShr8, 0xf, 0xf, false);
+  x += __builtin_amdgcn_update_dpp(0, x, kDppRowBcast15, 0xa, 0xf, false);
+  x += __builtin_amdgcn_update_dpp(0, x, kDppRowBcast31, 0xc, 0xf, false);
+  return x;
+}
+
+__device__ __forceinline__ float wave_incl_scan_dpp(float x) {
+  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kDppRowShr1, 0xf, 0xf, false));
+  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kDppRowShr2, 0xf, 0xf, false));
+  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kDppRowShr4, 0xf, 0xf, false));
+  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kDppRowShr8, 0xf, 0xf, false));
+  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kDppRowBcast15, 0xa, 0xf, false));
+  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kDppRowBcast31, 0xc, 0xf, false));
+  return x;
+}
+
 // exclusive prefix sum over the 64 lanes
-__device__ __forceinline__ int wave_excl_scan(int v) {
-  const int lane = wave_lane();
-  int x = v;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    int y = __shfl_up(x, o, kWave);
-    if (lane >= o) x += y;
-  }
-  return x - v;
+__device__ __forceinline__ int wave_excl_scan(int v) { return wave_incl_scan_i32(v) - v; }
+
+// the value held by lane + 1 (lane 63 reads 0) / lane - 1 (lane 0 reads 0)
+__device__ __forceinline__ int lane_next(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, kDppWaveShl1, 0xf, 0xf, true);
+}
+__device__ __forceinline__ int lane_prev(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, kDppWaveShr1, 0xf, 0xf, true);
+}
+__device__ __forceinline__ float lane_next(float v) {
+  return __builtin_bit_cast(float, lane_next(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double lane_next(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)lane_next((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)lane_next((int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 __device__ __forceinline__ float wave_sum_f32(float v) {
@@ -59,6 +103,18 @@ __device__ __forceinline__ double uniform(double v) {
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
+
+// 1/a for finite nonzero a: the hardware estimate refined by two Newton steps
+// (within an ulp or two of the quotient; a fraction of the IEEE division's
+// instruction count)
+__device__ __forceinline__ double recip(double a) {
+  double y = __builtin_amdgcn_rcp(a);
+  double e = fma(-a, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-a, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ float recip(float a) { return 1.0f / a; }
 
 template <typename R> __device__ __forceinline__ R rsqrt_(R v);
 template <> __device__ __forceinline__ float rsqrt_(float v) { return sqrtf(v); }
@@ -220,7 +276,7 @@ __device__ __forceinline__ void mlp_point(const PathParams &P, const ProtonPath<
   const R det = C00 * C11 - C01 * C01;
   // first row of S1 R1^T C^-1
   const R A0 = d2 * I1 + I2, A1 = I1;
-  const R inv = (R)1 / det;
+  const R inv = recip(det);
   const R G0 = (A0 * C11 - A1 * C01) * inv;
   const R G1 = (A1 * C00 - A0 * C01) * inv;
   t = pp.t0 + pp.st0 * d1 + (G0 * pp.dtt + G1 * pp.dts);
@@ -240,12 +296,13 @@ __device__ __forceinline__ int walk_segment(const PathParams &P, int bx, int by,
   const W INF = (W)3.0e38f;
   int sx = 0, sy = 0, sz = 0;
   W tx = INF, ty = INF, tz = INF, ddx = INF, ddy = INF, ddz = INF;
-  if (dx > (W)0) { sx = 1; tx = ((W)1 - px) / dx; ddx = (W)1 / dx; }
-  else if (dx < (W)0) { sx = -1; tx = -px / dx; ddx = (W)(-1) / dx; }
-  if (dy > (W)0) { sy = 1; ty = ((W)1 - py) / dy; ddy = (W)1 / dy; }
-  else if (dy < (W)0) { sy = -1; ty = -py / dy; ddy = (W)(-1) / dy; }
-  if (dz > (W)0) { sz = 1; tz = ((W)1 - pz) / dz; ddz = (W)1 / dz; }
-  else if (dz < (W)0) { sz = -1; tz = -pz / dz; ddz = (W)(-1) / dz; }
+  // crossing parameters along the segment: next face per axis, then per voxel
+  if (dx > (W)0) { sx = 1; ddx = recip(dx); tx = ((W)1 - px) * ddx; }
+  else if (dx < (W)0) { sx = -1; ddx = -recip(dx); tx = px * ddx; }
+  if (dy > (W)0) { sy = 1; ddy = recip(dy); ty = ((W)1 - py) * ddy; }
+  else if (dy < (W)0) { sy = -1; ddy = -recip(dy); ty = py * ddy; }
+  if (dz > (W)0) { sz = 1; ddz = recip(dz); tz = ((W)1 - pz) * ddz; }
+  else if (dz < (W)0) { sz = -1; ddz = -recip(dz); tz = pz * ddz; }
   W tc = (W)0;
   int np = 0;
   const W eps = (W)P.eps_len;
@@ -312,8 +369,8 @@ __device__ int build_row(const PathParams &P, const float h[10], int *s_vox, flo
       wz = v;
     }
     const R gx = (wx - gox) * gix, gy = (wy - goy) * giy, gz = (wz - goz) * giz;
-    const R ngx = __shfl_down(gx, 1, kWave), ngy = __shfl_down(gy, 1, kWave), ngz = __shfl_down(gz, 1, kWave);
-    const R nwx = __shfl_down(wx, 1, kWave), nwy = __shfl_down(wy, 1, kWave), nwz = __shfl_down(wz, 1, kWave);
+    const R ngx = lane_next(gx), ngy = lane_next(gy), ngz = lane_next(gz);
+    const R nwx = lane_next(wx), nwy = lane_next(wy), nwz = lane_next(wz);
     int vox[kMaxPieces];
     float len[kMaxPieces];
     int np = 0;
@@ -336,7 +393,7 @@ __device__ int build_row(const PathParams &P, const float h[10], int *s_vox, flo
       if (q == 0 && np > 0) { first = vox[0]; first_len = len[0]; }
       if (q == np - 1) last = vox[q];
     }
-    int prev_last = __shfl_up(last, 1, kWave);
+    int prev_last = lane_prev(last);
     if (lane == 0) prev_last = carry_vox;
     const bool merge = np > 0 && prev_last >= 0 && first == prev_last;
     const int ne = np - (merge ? 1 : 0);
@@ -355,13 +412,11 @@ __device__ int build_row(const PathParams &P, const float h[10], int *s_vox, flo
         s_len[at + q] = len[q];
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    wave_lds_sync();
     // a first piece in the same voxel as the previous piece extends that entry
     if (merge) atomicAdd(&s_len[count + pos - 1], first_len);
     count += total;
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    wave_lds_sync();
     carry_vox = count > 0 ? s_vox[count - 1] : -1;
   }
   // voxels revisited after a short excursion: fold into the first visit
@@ -378,8 +433,7 @@ __device__ int build_row(const PathParams &P, const float h[10], int *s_vox, flo
     }
     any = any || (__ballot(m >= 0) != 0);
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  __builtin_amdgcn_wave_barrier();
+  wave_lds_sync();
   if (any) {
     if (lane == 0) {
       for (int e = 0; e < count; ++e) {
@@ -390,8 +444,7 @@ __device__ int build_row(const PathParams &P, const float h[10], int *s_vox, flo
         s_vox[e] = -1;
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    wave_lds_sync();
     int out = 0;
     for (int e0 = 0; e0 < count; e0 += kWave) {
       const int e = e0 + lane;
@@ -401,11 +454,9 @@ __device__ int build_row(const PathParams &P, const float h[10], int *s_vox, flo
       const int keep = v >= 0 ? 1 : 0;
       const int p = wave_excl_scan(keep);
       const int tot = __shfl(p + keep, kWave - 1, kWave);
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      __builtin_amdgcn_wave_barrier();
+      wave_lds_sync();
       if (keep) { s_vox[out + p] = v; s_len[out + p] = l; }
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      __builtin_amdgcn_wave_barrier();
+      wave_lds_sync();
       out += tot;
     }
     count = out;

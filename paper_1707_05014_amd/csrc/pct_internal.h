@@ -108,6 +108,8 @@ struct PlanView {
   int64_t *grp_off;         // [nb*T*kGroups + 1]
   uint32_t *packedB;        // [EB]
   void *lenB;               // [EB]
+  uint32_t *tmpB;           // [EB] build only: entries grouped by (list, group), list order
+  void *tmp_lenB;           // [EB]
 };
 constexpr int kGroups = kTileVox / 64;  // 64-voxel groups per tile
 

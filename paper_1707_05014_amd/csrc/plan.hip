@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(256) k_plan_count(const int64_t *__restrict__ 
         else
           t = voxel_tile(j, V, local);
       }
-      int tp = __shfl_up(t, 1, kWave);
+      int tp = lane_prev(t);
       if (lane == 0) tp = -2;
       const bool start = valid && (lane == 0 || t != tp);
       const uint64_t starts = __ballot(start);
@@ -135,39 +135,33 @@ __global__ void k_copy_i64_u64(unsigned long long *dst, const int64_t *src, int6
 }
 
 // Fill pass: place each piece in its (block, tile) list, record where each
-// row's pieces end, gather b and ||a||^2 into block order.
+// row's pieces end, gather b and ||a||^2 into block order.  Wavefronts walk
+// the rows of the block order (persistent grid); the next rows' history
+// indices and CSR bounds are loaded a row ahead so their latency overlaps
+// the current row.
 template <int LDI>
-__global__ void __launch_bounds__(256) k_plan_fill(const int64_t *__restrict__ row_ptr,
-                                                   const int32_t *__restrict__ idx, const void *__restrict__ len_in,
-                                                   const int64_t *__restrict__ order, const float *__restrict__ wepl,
-                                                   const double *__restrict__ norm2, int64_t M, PlanView V,
-                                                   uint32_t *status) {
-  const int lane = wave_lane();
-  const int64_t q = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
-  if (q >= V.n) return;
-  const int64_t i = order ? order[q] : q;
-  if ((uint64_t)i >= (uint64_t)V.n) {
-    if (lane == 0) atomicOr(status, kStBadIndex);
-    return;
-  }
+__device__ __forceinline__ void fill_row(const int32_t *__restrict__ idx, const void *__restrict__ len_in, int64_t M,
+                                         const PlanView &V, uint32_t *status, int64_t q, int64_t e0, int64_t e1,
+                                         int lane) {
   const int64_t b = q / V.B;
   const uint32_t row_local = (uint32_t)(q - b * V.B);
-  if (lane == 0) {
-    V.b_perm[q] = wepl[i];
-    V.n2_perm[q] = norm2[i];
-  }
-  const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
   const int64_t rbase = V.ref_base[q], rcap = V.ref_base[q + 1] - rbase;
   int64_t nref = 0;
   for (int64_t w = e0; w < e1; w += kWave) {
     const int64_t e = w + lane;
     const bool valid = e < e1;
     int t = -1, local = 0;
+    float l = 0.f;
+    __half lh = __float2half(0.f);
     if (valid) {
       const int j = idx[e];
+      if (LDI == 0)
+        l = reinterpret_cast<const float *>(len_in)[e];
+      else
+        lh = reinterpret_cast<const __half *>(len_in)[e];
       if ((uint32_t)j < (uint64_t)M) t = voxel_tile(j, V, local);
     }
-    int tp = __shfl_up(t, 1, kWave);
+    int tp = lane_prev(t);
     if (lane == 0) tp = -2;
     const bool start = valid && (lane == 0 || t != tp);
     const uint64_t starts = __ballot(start);
@@ -193,15 +187,10 @@ __global__ void __launch_bounds__(256) k_plan_fill(const int64_t *__restrict__ r
     bool is_ref = false;
     if (write) {
       V.packed[p] = pack_entry(last ? 1u : 0u, (uint32_t)local, row_local);
-      if (V.len_dtype == 0) {
-        const float l = LDI == 0 ? reinterpret_cast<const float *>(len_in)[e]
-                                 : __half2float(reinterpret_cast<const __half *>(len_in)[e]) * V.len_unit;
-        reinterpret_cast<float *>(V.len)[p] = l;
-      } else {
-        reinterpret_cast<__half *>(V.len)[p] =
-            LDI == 1 ? reinterpret_cast<const __half *>(len_in)[e]
-                     : __float2half(reinterpret_cast<const float *>(len_in)[e] / V.len_unit);
-      }
+      if (V.len_dtype == 0)
+        reinterpret_cast<float *>(V.len)[p] = LDI == 0 ? l : __half2float(lh) * V.len_unit;
+      else
+        reinterpret_cast<__half *>(V.len)[p] = LDI == 1 ? lh : __float2half(l / V.len_unit);
       is_ref = last || ((p & (kWave - 1)) == kWave - 1);
     }
     const uint64_t rm = __ballot(is_ref);
@@ -217,33 +206,61 @@ __global__ void __launch_bounds__(256) k_plan_fill(const int64_t *__restrict__ r
   if (lane == 0) V.ref_cnt[q] = (int32_t)(nref < rcap ? nref : rcap);
 }
 
-// lanes that close a piece (or a chunk) and their count per chunk
-__global__ void __launch_bounds__(256) k_plan_chunk_ends(PlanView V) {
+template <int LDI>
+__global__ void __launch_bounds__(256) k_plan_fill(const int64_t *__restrict__ row_ptr,
+                                                   const int32_t *__restrict__ idx, const void *__restrict__ len_in,
+                                                   const int64_t *__restrict__ order, const float *__restrict__ wepl,
+                                                   const double *__restrict__ norm2, int64_t M, PlanView V,
+                                                   uint32_t *status) {
   const int lane = wave_lane();
-  const int64_t c = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
-  if (c >= V.C) return;
-  const uint32_t v = V.packed[c * kWave + lane];
-  const bool valid = v & 1u;
-  const bool close = valid && (((v >> 1) & 1u) || lane == kWave - 1);
-  const uint64_t m = __ballot(close);
-  if (lane == 0) {
-    V.end_mask[c] = m;
-    V.chunk_first_end[c + 1] = __popcll(m);
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  int64_t q = (int64_t)blockIdx.x * 4 + uniform((int)(threadIdx.x / kWave));
+  if (q >= V.n) return;
+  // history index of row q, and of the row after it
+  int64_t i = order ? order[q] : q;
+  int64_t i_next = q + nw < V.n ? (order ? order[q + nw] : q + nw) : 0;
+  for (; q < V.n; q += nw) {
+    const bool bad = (uint64_t)i >= (uint64_t)V.n;
+    int64_t e0 = 0, e1 = 0;
+    if (!bad) {
+      e0 = row_ptr[i];
+      e1 = row_ptr[i + 1];
+      if (lane == 0) {
+        V.b_perm[q] = wepl[i];
+        V.n2_perm[q] = norm2[i];
+      }
+    } else if (lane == 0) {
+      atomicOr(status, kStBadIndex);
+    }
+    const int64_t q2 = q + 2 * nw;
+    const int64_t i_next2 = q2 < V.n ? (order ? order[q2] : q2) : 0;
+    if (!bad) fill_row<LDI>(idx, len_in, M, V, status, q, e0, e1, lane);
+    i = i_next;
+    i_next = i_next2;
   }
 }
 
-// Inclusive prefix sum over the 64 lanes with DPP row shifts and row
-// broadcasts (GFX9 cross-lane data movement; no LDS traffic).
-__device__ __forceinline__ float wave_incl_scan_dpp(float x) {
-  constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
-  constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
-  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kRowShr1, 0xf, 0xf, false));
-  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kRowShr2, 0xf, 0xf, false));
-  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kRowShr4, 0xf, 0xf, false));
-  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kRowShr8, 0xf, 0xf, false));
-  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kRowBcast15, 0xa, 0xf, false));
-  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kRowBcast31, 0xc, 0xf, false));
-  return x;
+// lanes that close a piece (or a chunk) and their count per chunk; a
+// wavefront takes kEndsChunks consecutive chunks, loads first
+constexpr int kEndsChunks = 4;
+
+__global__ void __launch_bounds__(256) k_plan_chunk_ends(PlanView V) {
+  const int lane = wave_lane();
+  const int64_t cw = ((int64_t)blockIdx.x * 4 + threadIdx.x / kWave) * kEndsChunks;
+  if (cw >= V.C) return;
+  uint32_t v[kEndsChunks];
+#pragma unroll
+  for (int q = 0; q < kEndsChunks; ++q) v[q] = cw + q < V.C ? V.packed[(cw + q) * kWave + lane] : 0u;
+#pragma unroll
+  for (int q = 0; q < kEndsChunks; ++q) {
+    const bool valid = v[q] & 1u;
+    const bool close = valid && (((v[q] >> 1) & 1u) || lane == kWave - 1);
+    const uint64_t m = __ballot(close);
+    if (lane == 0 && cw + q < V.C) {
+      V.end_mask[cw + q] = m;
+      V.chunk_first_end[cw + q + 1] = __popcll(m);
+    }
+  }
 }
 
 template <int LD>
@@ -381,13 +398,30 @@ __global__ void __launch_bounds__(256) k_plan_ref_ordinals(PlanView V) {
   const int64_t rb = V.ref_base[b * V.B];
   const int64_t k0 = V.ref_base[q];
   const int nref = V.ref_cnt[q];
-  for (int k = 0; k < nref; ++k) {
-    const uint32_t p = V.refs[k0 + k];
-    const int64_t c = p / kWave;
-    const int l = p & (kWave - 1);
-    const int64_t ord = V.chunk_first_end[c] + __popcll(V.end_mask[c] & ((1ull << l) - 1));
-    V.end_slot[ord] = (uint32_t)(k0 + k - rb);
-    V.ord_row[ord] = (uint32_t)(q - b * V.B);
+  constexpr int U = 4;  // references whose loads are issued together
+  for (int k = 0; k < nref; k += U) {
+    uint32_t p[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) p[u] = k + u < nref ? V.refs[k0 + k + u] : 0u;
+    uint64_t em[U];
+    int64_t fe[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      em[u] = 0ull;
+      fe[u] = 0;
+      if (k + u < nref) {
+        em[u] = V.end_mask[p[u] / kWave];
+        fe[u] = V.chunk_first_end[p[u] / kWave];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (k + u >= nref) break;
+      const int l = p[u] & (kWave - 1);
+      const int64_t ord = fe[u] + __popcll(em[u] & ((1ull << l) - 1));
+      V.end_slot[ord] = (uint32_t)(k0 + k + u - rb);
+      V.ord_row[ord] = (uint32_t)(q - b * V.B);
+    }
   }
 }
 
@@ -447,77 +481,238 @@ __global__ void __launch_bounds__(256) k_plan_resid_rows(PlanView V, int64_t b, 
   if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
-// Voxel-major copy of one (block, tile) list: counting sort by tile-local
-// voxel in LDS (one workgroup per list).  Group offsets go to grp_off; the
-// last entry of each voxel's run is flagged; each entry carries the offset of
-// its piece-end ordinal from the list's first ordinal (so the scatter can read
-// its r from the list's ordinals staged in LDS).  Needs end_mask and
-// chunk_first_end.
-__global__ void __launch_bounds__(256) k_plan_voxel_major(PlanView V) {
-  __shared__ uint32_t s_cnt[kTileVox];
-  __shared__ uint32_t s_pos[kTileVox];
-  __shared__ uint32_t s_start[kTileVox];
-  __shared__ uint32_t s_part[256];
-  const int64_t k = blockIdx.x;  // (block, tile)
-  if (k >= V.nb * V.T) return;
+// ---- voxel-major copy of the lists (layout B), built by two stable
+// counting sorts: k_plan_group_bucket moves each (block, tile) list's entries
+// into its 32 groups of 64 voxels (list order kept within a group; writes go
+// out in runs of about a hundred entries), k_plan_voxel_sort orders each
+// group by voxel (order kept within a voxel) and flags the last entry of
+// every voxel's run.  Ranks within a wavefront come from ballots over the key
+// bits (no atomics), so equal keys keep their list order.
+
+// Key ballots of one chunk: bit planes of a key of NB bits over the lanes.
+template <int NB>
+struct KeyBallots {
+  uint64_t valid;
+  uint64_t plane[NB];
+  __device__ __forceinline__ KeyBallots(uint32_t key, bool ok) {
+    valid = __ballot(ok);
+#pragma unroll
+    for (int bit = 0; bit < NB; ++bit) plane[bit] = __ballot((key >> bit) & 1u);
+  }
+  // valid lanes whose key equals k
+  __device__ __forceinline__ uint64_t lanes_with(uint32_t k) const {
+    uint64_t m = valid;
+#pragma unroll
+    for (int bit = 0; bit < NB; ++bit) m &= ((k >> bit) & 1u) ? plane[bit] : ~plane[bit];
+    return m;
+  }
+};
+
+__device__ __forceinline__ uint64_t lanes_below() {
+  const int lane = wave_lane();
+  return (1ull << lane) - 1ull;
+}
+
+constexpr int kBucketChunks = 4;  // chunks per wavefront per round of k_plan_group_bucket
+
+// One workgroup of kPlanWaves wavefronts per (block, tile) list: writes the
+// group offsets of the list (grp_off, from the list start the host put in
+// grp_off[k * kGroups]) and the entries, grouped, to tmpB / tmp_lenB with the
+// B-layout fields except the run flag.  Lane g of a wavefront keeps the count
+// of group g; an entry's rank among equal keys comes from the key ballots.
+__global__ void __launch_bounds__(kPlanThreads) k_plan_group_bucket(PlanView V) {
+  __shared__ uint32_t s_cnt[kPlanWaves][kGroups];
+  __shared__ int64_t s_off[kPlanWaves][kGroups];
+  __shared__ int64_t s_base[kGroups];
+  const int lane = wave_lane();
+  const int wid = uniform((int)(threadIdx.x / kWave));
+  const int64_t k = blockIdx.x;
   const int64_t a0 = V.bt_off[k], a1 = V.bt_off[k + 1];
-  for (int e = threadIdx.x; e < kTileVox; e += blockDim.x) s_cnt[e] = 0u;
-  __syncthreads();
-  for (int64_t p = a0 + threadIdx.x; p < a1; p += blockDim.x) {
-    const uint32_t v = V.packed[p];
-    if (v & 1u) atomicAdd(&s_cnt[(v >> 2) & (kTileVox - 1)], 1u);
-  }
-  __syncthreads();
-  // exclusive scan of the 2048 counts: 8 per thread, then across threads
-  const int per = kTileVox / 256;
-  uint32_t loc[per];
-  uint32_t tot = 0;
+  const int64_t c0 = a0 / kWave, nch = (a1 - a0) / kWave;
+  const int64_t o0 = nch ? V.chunk_first_end[c0] : 0;
+  // sweep A: entries per group (chunks wid, wid + kPlanWaves, ...; loads of
+  // kBucketChunks chunks issued together)
+  uint32_t cnt = 0;
+  for (int64_t cb = wid; cb < nch; cb += (int64_t)kPlanWaves * kBucketChunks) {
+    uint32_t v[kBucketChunks];
 #pragma unroll
-  for (int q = 0; q < per; ++q) {
-    loc[q] = tot;
-    tot += s_cnt[threadIdx.x * per + q];
-  }
-  s_part[threadIdx.x] = tot;
-  __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {
-    const uint32_t add = (int)threadIdx.x >= o ? s_part[threadIdx.x - o] : 0u;
-    __syncthreads();
-    s_part[threadIdx.x] += add;
-    __syncthreads();
-  }
-  const uint32_t excl = s_part[threadIdx.x] - tot;
-  // list start in the voxel-major arrays: entries before this list are the
-  // valid entries of all earlier lists, i.e. grp_off[k * kGroups] (filled by
-  // the host from the per-list valid counts)
-  const int64_t base = V.grp_off[k * kGroups];
+    for (int q = 0; q < kBucketChunks; ++q) {
+      const int64_t c = cb + (int64_t)q * kPlanWaves;
+      v[q] = c < nch ? V.packed[(c0 + c) * kWave + lane] : 0u;
+    }
 #pragma unroll
-  for (int q = 0; q < per; ++q) {
-    const int vox = threadIdx.x * per + q;
-    s_pos[vox] = excl + loc[q];
-    s_start[vox] = excl + loc[q];
-    if ((vox & 63) == 0 && vox > 0) V.grp_off[k * kGroups + vox / 64] = base + excl + loc[q];
+    for (int q = 0; q < kBucketChunks; ++q) {
+      const KeyBallots<5> kb(((v[q] >> 2) & (kTileVox - 1)) >> 6, v[q] & 1u);
+      cnt += (uint32_t)__popcll(kb.lanes_with((uint32_t)lane));
+    }
+  }
+  if (lane < kGroups) s_cnt[wid][lane] = cnt;
+  __syncthreads();
+  if (wid == 0) {
+    uint32_t tot = 0;
+    if (lane < kGroups)
+      for (int w = 0; w < kPlanWaves; ++w) tot += s_cnt[w][lane];
+    const int64_t base = V.grp_off[k * kGroups] + wave_excl_scan((int)tot);
+    if (lane < kGroups) {
+      s_base[lane] = base;
+      if (lane > 0) V.grp_off[k * kGroups + lane] = base;
+    }
   }
   __syncthreads();
-  const int64_t o0 = a0 < a1 ? V.chunk_first_end[a0 / kWave] : 0;
-  for (int64_t p = a0 + threadIdx.x; p < a1; p += blockDim.x) {
-    const uint32_t v = V.packed[p];
-    if (!(v & 1u)) continue;
-    const int vox = (v >> 2) & (kTileVox - 1);
-    const uint32_t slot = atomicAdd(&s_pos[vox], 1u);
-    const uint32_t last = slot == s_start[vox] + s_cnt[vox] - 1u ? 2u : 0u;  // closes the voxel's run
-    const int64_t dst = base + slot;
-    if (dst >= V.grp_off[(k + 1) * kGroups]) continue;  // cannot happen when the counts agree
-    // the piece end at or after this entry's lane: closes strictly below it
-    // belong to earlier pieces of the chunk
-    const int64_t c = p / kWave;
-    const int l = (int)(p & (kWave - 1));
-    const int64_t ord = V.chunk_first_end[c] + __popcll(V.end_mask[c] & ((1ull << l) - 1));
-    V.packedB[dst] = 1u | last | ((uint32_t)(vox & 63) << 2) | ((uint32_t)(ord - o0) << 8);
-    if (V.len_dtype == 0)
-      reinterpret_cast<float *>(V.lenB)[dst] = reinterpret_cast<const float *>(V.len)[p];
-    else
-      reinterpret_cast<__half *>(V.lenB)[dst] = reinterpret_cast<const __half *>(V.len)[p];
+  // sweep B: rounds of kPlanWaves x kBucketChunks chunks, wavefront w taking
+  // the w-th run of kBucketChunks consecutive chunks of the round
+  const int64_t per_round = (int64_t)kPlanWaves * kBucketChunks;
+  for (int64_t r0 = 0; r0 < nch; r0 += per_round) {
+    uint32_t pv[kBucketChunks], pl[kBucketChunks], pos[kBucketChunks], grp[kBucketChunks];
+    uint64_t em[kBucketChunks];
+    int64_t fe[kBucketChunks];
+#pragma unroll
+    for (int q = 0; q < kBucketChunks; ++q) {
+      const int64_t c = r0 + (int64_t)wid * kBucketChunks + q;
+      pv[q] = 0u;
+      pl[q] = 0u;
+      em[q] = 0ull;
+      fe[q] = 0;
+      if (c < nch) {
+        const int64_t p = (c0 + c) * kWave + lane;
+        pv[q] = V.packed[p];
+        pl[q] = V.len_dtype == 0 ? reinterpret_cast<const uint32_t *>(V.len)[p]
+                                 : (uint32_t)reinterpret_cast<const uint16_t *>(V.len)[p];
+        em[q] = V.end_mask[c0 + c];
+        fe[q] = V.chunk_first_end[c0 + c];
+      }
+    }
+    uint32_t wcur = 0;  // lane g: entries of group g met so far in this round
+#pragma unroll
+    for (int q = 0; q < kBucketChunks; ++q) {
+      const bool valid = pv[q] & 1u;
+      const uint32_t vox = (pv[q] >> 2) & (kTileVox - 1);
+      const uint32_t key = vox >> 6;
+      const KeyBallots<5> kb(key, valid);
+      const uint32_t before = (uint32_t)__shfl((int)wcur, (int)key, kWave);
+      pos[q] = before + (uint32_t)__popcll(kb.lanes_with(key) & lanes_below());
+      grp[q] = key;
+      wcur += (uint32_t)__popcll(kb.lanes_with((uint32_t)lane));
+      // the piece end at or after this entry: closes strictly below this
+      // lane belong to earlier pieces of the chunk
+      const int64_t ord = fe[q] + __popcll(em[q] & lanes_below());
+      pv[q] = valid ? (1u | ((vox & 63u) << 2) | ((uint32_t)(ord - o0) << 8)) : 0u;
+    }
+    if (lane < kGroups) s_cnt[wid][lane] = wcur;
+    __syncthreads();
+    if (threadIdx.x < kGroups) {
+      int64_t run = s_base[threadIdx.x];
+      for (int w = 0; w < kPlanWaves; ++w) {
+        s_off[w][threadIdx.x] = run;
+        run += s_cnt[w][threadIdx.x];
+      }
+      s_base[threadIdx.x] = run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kBucketChunks; ++q) {
+      if (!(pv[q] & 1u)) continue;
+      const int64_t dst = s_off[wid][grp[q]] + pos[q];
+      V.tmpB[dst] = pv[q];
+      if (V.len_dtype == 0)
+        reinterpret_cast<uint32_t *>(V.tmp_lenB)[dst] = pl[q];
+      else
+        reinterpret_cast<uint16_t *>(V.tmp_lenB)[dst] = (uint16_t)pl[q];
+    }
   }
+}
+
+constexpr int kSortChunks = 8;     // chunks whose loads k_plan_voxel_sort issues together
+constexpr int kSortWindow = 2048;  // output entries a wavefront assembles in LDS before writing them out
+constexpr int kSortWaves = 4;
+
+// One (block, tile, group) list: sweep A counts entries per voxel; sweep B
+// places them (stable), through an LDS window of kSortWindow output slots
+// that is written out with contiguous stores (lists longer than the window
+// take one sweep B per window).  Lane v keeps the count, then the cursor, of
+// voxel v of the group.
+__device__ __forceinline__ void voxel_sort_group(const PlanView &V, int64_t gi, int lane, uint32_t *s_v,
+                                                 uint32_t *s_l) {
+  const int64_t e0 = V.grp_off[gi], e1 = V.grp_off[gi + 1];
+  if (e0 == e1) return;
+  const int64_t step = (int64_t)kSortChunks * kWave;
+  // sweep A: entries per voxel of the group
+  uint32_t cnt = 0;
+  for (int64_t w = e0; w < e1; w += step) {
+    uint32_t v[kSortChunks];
+#pragma unroll
+    for (int q = 0; q < kSortChunks; ++q) {
+      const int64_t p = w + (int64_t)q * kWave + lane;
+      v[q] = p < e1 ? V.tmpB[p] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kSortChunks; ++q) {
+      const KeyBallots<6> kb((v[q] >> 2) & 63u, v[q] & 1u);
+      cnt += (uint32_t)__popcll(kb.lanes_with((uint32_t)lane));
+    }
+  }
+  // run starts (exclusive scan over the 64 voxels); a run ends at start + cnt - 1
+  const uint32_t start = (uint32_t)wave_excl_scan((int)cnt);
+  const uint32_t end = start + cnt;
+  const int64_t n = e1 - e0;
+  for (int64_t wlo = 0; wlo < n; wlo += kSortWindow) {
+    const int64_t whi = wlo + kSortWindow < n ? wlo + kSortWindow : n;
+    uint32_t cur = start;
+    // sweep B: stable placement of the slots that fall in [wlo, whi)
+    for (int64_t w = e0; w < e1; w += step) {
+      uint32_t v[kSortChunks], l[kSortChunks];
+#pragma unroll
+      for (int q = 0; q < kSortChunks; ++q) {
+        const int64_t p = w + (int64_t)q * kWave + lane;
+        v[q] = 0u;
+        l[q] = 0u;
+        if (p < e1) {
+          v[q] = V.tmpB[p];
+          l[q] = V.len_dtype == 0 ? reinterpret_cast<const uint32_t *>(V.tmp_lenB)[p]
+                                  : (uint32_t)reinterpret_cast<const uint16_t *>(V.tmp_lenB)[p];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kSortChunks; ++q) {
+        const bool valid = v[q] & 1u;
+        const uint32_t key = (v[q] >> 2) & 63u;
+        const KeyBallots<6> kb(key, valid);
+        const uint32_t slot = (uint32_t)__shfl((int)cur, (int)key, kWave) +
+                              (uint32_t)__popcll(kb.lanes_with(key) & lanes_below());
+        const uint32_t run_end = (uint32_t)__shfl((int)end, (int)key, kWave) - 1u;
+        cur += (uint32_t)__popcll(kb.lanes_with((uint32_t)lane));
+        if (valid && slot >= wlo && slot < whi) {
+          s_v[slot - wlo] = v[q] | (slot == run_end ? 2u : 0u);
+          s_l[slot - wlo] = l[q];
+        }
+      }
+    }
+    wave_lds_sync();
+    // the window, in order
+    for (int64_t o = wlo + lane; o < whi; o += kWave) {
+      const int64_t dst = e0 + o;
+      V.packedB[dst] = s_v[o - wlo];
+      if (V.len_dtype == 0)
+        reinterpret_cast<uint32_t *>(V.lenB)[dst] = s_l[o - wlo];
+      else
+        reinterpret_cast<uint16_t *>(V.lenB)[dst] = (uint16_t)s_l[o - wlo];
+    }
+    wave_lds_sync();
+  }
+}
+
+// Wavefronts walk the (block, tile, group) lists (persistent grid): each
+// orders its group's entries by voxel (stable) from tmpB into packedB / lenB
+// and flags each voxel's last entry.
+__global__ void __launch_bounds__(kSortWaves * kWave) k_plan_voxel_sort(PlanView V) {
+  __shared__ uint32_t s_v[kSortWaves][kSortWindow];
+  __shared__ uint32_t s_l[kSortWaves][kSortWindow];
+  const int lane = wave_lane();
+  const int wid = uniform((int)(threadIdx.x / kWave));
+  const int64_t ng = V.nb * V.T * kGroups;
+  const int64_t nw = (int64_t)gridDim.x * kSortWaves;
+  for (int64_t gi = (int64_t)blockIdx.x * kSortWaves + wid; gi < ng; gi += nw)
+    voxel_sort_group(V, gi, lane, s_v[wid], s_l[wid]);
 }
 
 #ifndef PCT_SCAT_BATCH
@@ -648,12 +843,10 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan_scatter(PlanView V, int64
         }
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    wave_lds_sync();
     const uint32_t c = s_cnt[wid][lane];
     if (inside && c) x[gv] = keep ? xl + lambda * s_num[wid][lane] / (float)c : 0.0f;
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    wave_lds_sync();
   }
 }
 
@@ -705,7 +898,7 @@ hipError_t launch_plan_fill(const int64_t *row_ptr, const int32_t *idx, const vo
                             const int64_t *order, const float *wepl, const double *norm2, int64_t M,
                             const PlanView &V, uint32_t *status, hipStream_t s) {
   if (V.n <= 0) return hipSuccess;
-  const unsigned g = grid_for(V.n, 4, 0x7fffffffu);
+  const unsigned g = grid_for(V.n, 4, 256 * 8);
   if (len_in_dtype == 0)
     hipLaunchKernelGGL(k_plan_fill<0>, dim3(g), dim3(256), 0, s, row_ptr, idx, len_in, order, wepl, norm2, M, V,
                        status);
@@ -722,7 +915,8 @@ hipError_t launch_plan_ref_ordinals(const PlanView &V, hipStream_t s) {
 }
 
 hipError_t launch_plan_chunks(const PlanView &V, hipStream_t s) {
-  if (V.C > 0) hipLaunchKernelGGL(k_plan_chunk_ends, dim3(grid_for(V.C, 4, 0x7fffffffu)), dim3(256), 0, s, V);
+  if (V.C > 0)
+    hipLaunchKernelGGL(k_plan_chunk_ends, dim3(grid_for(V.C, 4 * kEndsChunks, 0x7fffffffu)), dim3(256), 0, s, V);
   return hipGetLastError();
 }
 
@@ -760,7 +954,9 @@ hipError_t launch_plan_scatter(const PlanView &V, int64_t b, float *x, const uin
 
 hipError_t launch_plan_build_voxel_major(const PlanView &V, hipStream_t s) {
   if (V.nb * V.T <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_plan_voxel_major, dim3((unsigned)(V.nb * V.T)), dim3(256), 0, s, V);
+  hipLaunchKernelGGL(k_plan_group_bucket, dim3((unsigned)(V.nb * V.T)), dim3(kPlanThreads), 0, s, V);
+  hipLaunchKernelGGL(k_plan_voxel_sort, dim3(grid_for(V.nb * V.T * kGroups, kSortWaves, 256 * 2)),
+                     dim3(kSortWaves * kWave), 0, s, V);
   return hipGetLastError();
 }
 
