@@ -554,7 +554,7 @@ pct_status do_plan_sweep(Ctx &c, const pct_plan *plan, const pct::PlanView &V, f
 pct_status do_plan_residual(Ctx &c, const pct_plan *plan, const pct::PlanView &V, const float *x, double *out) {
   const int64_t G = (plan->block_size + 255) / 256;
   for (int64_t b = 0; b < plan->n_blocks; ++b) {
-    PROF(PCT_K_RESIDUAL, pct::launch_plan_dot(V, b, x, c.s));
+    PROF(PCT_K_PLAN_DOT, pct::launch_plan_dot(V, b, x, c.s));
     PROF(PCT_K_RESIDUAL, pct::launch_plan_resid_rows(V, b, V.res_part, c.s));
     PROF(PCT_K_RESIDUAL, pct::launch_sum_partials(V.res_part, G, V.blk_res + b, 0, c.s));
   }
