@@ -212,7 +212,7 @@ def main():
             plan = api.plan_build(grid, H, rows, params)  # sizing + allocation
             torch.cuda.synchronize()
             ps = plan.struct
-            log(f"plan: {ps.entries} entries, {ps.chunks} chunks, {ps.refs} reference slots, "
+            log(f"plan: {ps.entries} entries, {ps.chunks} chunks, {ps.refs} reference slots reserved, "
                 f"{ps.bytes / 1e9:.2f} GB")
 
     def step():
@@ -255,9 +255,17 @@ def main():
     if plan is not None:
         ps = plan.struct
         lbp = 4 if ps.len_dtype == 0 else 2
-        per_block_rows = ((4 + lbp) * nnz + (4 + 8 + 12) * N) / n_blocks
-        models["plan_scatter"] = ("hbm", per_block_rows + 8 * M, HBM_PEAK_GBS, "GB/s", "pct::k_plan_scatter<0>")
-        models["plan_dot"] = ("hbm", per_block_rows + 4 * M, HBM_PEAK_GBS, "GB/s", "pct::k_plan_dot<0>")
+        # algorithmic bytes per launch (one block): the dot streams the block's
+        # layout-A entries (2 B code + length), 8 B per chunk (first piece-end
+        # ordinal), reads each piece end's row slot and writes its partial
+        # (4 + 4 B) and reads x once (4 B/voxel); the scatter streams the
+        # layout-B entries (4 B code + length), reads r per piece end (4 B)
+        # and reads and writes x (8 B/voxel)
+        ends_pb = ps.ends / n_blocks
+        models["plan_dot"] = ("hbm", ((2 + lbp) * ps.entries + 8 * ps.chunks) / n_blocks + 8 * ends_pb + 4 * M,
+                              HBM_PEAK_GBS, "GB/s", "pct::k_plan_dot<1>" if lbp == 2 else "pct::k_plan_dot<0>")
+        models["plan_scatter"] = ("hbm", (4 + lbp) * nnz / n_blocks + 4 * ends_pb + 8 * M, HBM_PEAK_GBS, "GB/s",
+                                  "pct::k_plan_scatter<1>" if lbp == 2 else "pct::k_plan_scatter<0>")
     if rows is not None:
         models["project"] = ("hbm", ((4 + lb) * nnz + (16 + 8 + 8 + 4) * N) / n_blocks + 20 * M, HBM_PEAK_GBS,
                              "GB/s", "pct::k_project_cached<0>")

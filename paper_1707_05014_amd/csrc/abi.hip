@@ -344,7 +344,7 @@ size_t plan_layout(const pct_plan *p, size_t off[L_COUNT]) {
   const size_t sz[L_COUNT] = {(size_t)(p->n + 1) * 8,   (size_t)(nbT + 1) * 8,   (size_t)nbT * 8,
                               (size_t)p->max_ends * 4, (size_t)p->refs * 4, (size_t)p->block_size * 4,
                               (size_t)p->chunks * 8,   (size_t)(p->chunks + 1) * 8,
-                              (size_t)p->entries * 4,  (size_t)p->entries * lb, (size_t)p->n * 4,
+                              (size_t)p->entries * 2,  (size_t)p->entries * lb, (size_t)p->n * 4,
                               (size_t)p->refs * 4,     (size_t)p->n * 4,         (size_t)p->n * 8,
                               (size_t)p->max_ends * 4, (size_t)G * 8,
                               (size_t)p->n_blocks * 8,
@@ -395,7 +395,7 @@ pct::PlanView plan_view(const pct_plan *p, float len_unit) {
   V.rvals = reinterpret_cast<float *>(m + off[L_RVALS]);
   V.end_mask = reinterpret_cast<uint64_t *>(m + off[L_EMASK]);
   V.chunk_first_end = reinterpret_cast<int64_t *>(m + off[L_CFE]);
-  V.packed = reinterpret_cast<uint32_t *>(m + off[L_PACKED]);
+  V.packed = reinterpret_cast<uint16_t *>(m + off[L_PACKED]);
   V.len = m + off[L_LEN];
   V.ref_base = reinterpret_cast<int64_t *>(m + off[L_REFBASE]);
   V.ref_cnt = reinterpret_cast<int32_t *>(m + off[L_REFCNT]);
@@ -515,18 +515,20 @@ pct_status do_plan_build(Ctx &c, const pct_grid *g, const pct_rows *rows, const 
   HIPCHECK(pct::launch_copy_i64_to_u64(V.bt_cur, V.bt_off, d.nb * d.T, c.s));
   if (row_cap != V.ref_base) return fail(PCT_EDEVICE, "plan layout: ref_base is not the first region");
   HIPCHECK(pct::launch_scan_rows(V.ref_base, 0, c.n, c.W.scan, c.s));
-  HIPCHECK(pct::launch_fill_u32(V.packed, E, 0u, c.s));
+  HIPCHECK(pct::launch_fill_u32(reinterpret_cast<uint32_t *>(V.packed), E / 2, 0u, c.s));
   PROF(PCT_K_PLAN_BUILD, pct::launch_plan_fill(rows->row_ptr, rows->idx, rows->len, rows->len_dtype, params->order,
                                                c.H.wepl, rows->norm2, c.M, V, c.W.status, c.s));
   PROF(PCT_K_PLAN_BUILD, pct::launch_plan_chunks(V, c.s));
   HIPCHECK(pct::launch_scan_rows(V.chunk_first_end, 0, tmp.chunks, plan_scan_tmp(&tmp), c.s));
   PROF(PCT_K_PLAN_BUILD, pct::launch_plan_ref_ordinals(V, c.s));
   PROF(PCT_K_PLAN_BUILD, pct::launch_plan_build_voxel_major(V, c.s));
-  int64_t refs_total = 0;
+  int64_t refs_total = 0, ends = 0;
   HIPCHECK(hipMemcpyAsync(&refs_total, V.ref_base + c.n, 8, hipMemcpyDeviceToHost, c.s));
+  HIPCHECK(hipMemcpyAsync(&ends, V.chunk_first_end + tmp.chunks, 8, hipMemcpyDeviceToHost, c.s));
   if ((r = read_status(c, &st)) != PCT_OK) return r;
   if (st) return status_to_code(st);
   if (refs_total != tmp.refs) return fail(PCT_EDEVICE, "plan reference count changed between passes");
+  tmp.ends = ends;
   tmp.ready = 1;
   *plan = tmp;
   return PCT_OK;

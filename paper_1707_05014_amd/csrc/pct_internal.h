@@ -71,10 +71,10 @@ constexpr int kTX = 16, kTY = 16, kTZ = 8;           // tile of 2048 voxels
 constexpr int kTileVox = kTX * kTY * kTZ;
 constexpr int kRowBits = 18;                          // row-in-block index bits
 constexpr int64_t kMaxPlanBlock = int64_t(1) << kRowBits;
-// packed entry: bit 0 valid, bit 1 last entry of a piece, bits 2..12 voxel in
-// tile, bits 13..30 row in block
-__host__ __device__ inline uint32_t pack_entry(uint32_t last, uint32_t vox, uint32_t row) {
-  return 1u | (last << 1) | (vox << 2) | (row << 13);
+// layout-A entry (16 bits): bit 0 valid, bit 1 last entry of a piece, bits
+// 2..12 voxel in tile
+__host__ __device__ inline uint16_t pack_entry(uint32_t last, uint32_t vox) {
+  return (uint16_t)(1u | (last << 1) | (vox << 2));
 }
 
 struct PlanView {
@@ -89,7 +89,7 @@ struct PlanView {
   float *rvals;             // [B] r_i of one block
   uint64_t *end_mask;       // [C] lanes that close a piece (or a chunk)
   int64_t *chunk_first_end; // [C + 1]
-  uint32_t *packed;         // [E]
+  uint16_t *packed;         // [E] layout-A entries (see pack_entry)
   void *len;                // [E] float or half
   int64_t *ref_base;        // [n + 1]
   int32_t *ref_cnt;         // [n]

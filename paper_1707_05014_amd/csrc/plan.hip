@@ -144,7 +144,6 @@ __device__ __forceinline__ void fill_row(const int32_t *__restrict__ idx, const 
                                          const PlanView &V, uint32_t *status, int64_t q, int64_t e0, int64_t e1,
                                          int lane) {
   const int64_t b = q / V.B;
-  const uint32_t row_local = (uint32_t)(q - b * V.B);
   const int64_t rbase = V.ref_base[q], rcap = V.ref_base[q + 1] - rbase;
   int64_t nref = 0;
   for (int64_t w = e0; w < e1; w += kWave) {
@@ -186,7 +185,7 @@ __device__ __forceinline__ void fill_row(const int32_t *__restrict__ idx, const 
     const bool last = lane == pe - 1;
     bool is_ref = false;
     if (write) {
-      V.packed[p] = pack_entry(last ? 1u : 0u, (uint32_t)local, row_local);
+      V.packed[p] = pack_entry(last ? 1u : 0u, (uint32_t)local);
       if (V.len_dtype == 0)
         reinterpret_cast<float *>(V.len)[p] = LDI == 0 ? l : __half2float(lh) * V.len_unit;
       else
@@ -250,7 +249,7 @@ __global__ void __launch_bounds__(256) k_plan_chunk_ends(PlanView V) {
   if (cw >= V.C) return;
   uint32_t v[kEndsChunks];
 #pragma unroll
-  for (int q = 0; q < kEndsChunks; ++q) v[q] = cw + q < V.C ? V.packed[(cw + q) * kWave + lane] : 0u;
+  for (int q = 0; q < kEndsChunks; ++q) v[q] = cw + q < V.C ? (uint32_t)V.packed[(cw + q) * kWave + lane] : 0u;
 #pragma unroll
   for (int q = 0; q < kEndsChunks; ++q) {
     const bool valid = v[q] & 1u;
@@ -298,7 +297,7 @@ __device__ __forceinline__ void dot_level1(const PlanView &V, int64_t cw, int nc
     l[k] = 0.f;
     if (k < nc) {
       const int64_t p = (cw + k) * kWave + lane;
-      v[k] = __builtin_nontemporal_load(V.packed + p);
+      v[k] = (uint32_t)__builtin_nontemporal_load(V.packed + p);
       l[k] = plan_len<LD>(V, p);
     }
   }
@@ -538,7 +537,7 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan_group_bucket(PlanView V) 
 #pragma unroll
     for (int q = 0; q < kBucketChunks; ++q) {
       const int64_t c = cb + (int64_t)q * kPlanWaves;
-      v[q] = c < nch ? V.packed[(c0 + c) * kWave + lane] : 0u;
+      v[q] = c < nch ? (uint32_t)V.packed[(c0 + c) * kWave + lane] : 0u;
     }
 #pragma unroll
     for (int q = 0; q < kBucketChunks; ++q) {
@@ -575,7 +574,7 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan_group_bucket(PlanView V) 
       fe[q] = 0;
       if (c < nch) {
         const int64_t p = (c0 + c) * kWave + lane;
-        pv[q] = V.packed[p];
+        pv[q] = (uint32_t)V.packed[p];
         pl[q] = V.len_dtype == 0 ? reinterpret_cast<const uint32_t *>(V.len)[p]
                                  : (uint32_t)reinterpret_cast<const uint16_t *>(V.len)[p];
         em[q] = V.end_mask[c0 + c];

@@ -308,8 +308,8 @@ def test_plan_long_lists(cfg1):
     xo, ro, order, mask = _run_oracle(cfg, h, R, "drop", cfg.n, 3)
     xg, rg, plan, _ = _plan_run(cfg, h, cfg.n, 3, order, mask)
     s = plan.struct
-    _say(f"  plan: entries {s.entries} refs {s.refs} tiles {s.n_tiles}")
-    assert s.refs / s.n_tiles > 12288  # lists longer than the LDS stage, on average
+    _say(f"  plan: entries {s.entries} piece ends {s.ends} tiles {s.n_tiles}")
+    assert s.ends / s.n_tiles > 12288  # lists longer than the LDS stage, on average
     rel = _rel(xg, xo)
     _say(f"  image rel-L2 {rel:.2e}")
     assert rel <= IMG_TOL
