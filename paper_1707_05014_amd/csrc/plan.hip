@@ -273,36 +273,56 @@ __device__ __forceinline__ float plan_len(const PlanView &V, int64_t p) {
 // Partial dot products of every piece of block b.  kDotSplit workgroups of
 // kPlanWaves wavefronts per (block, tile) list, each on an equal share of
 // its chunks (many more workgroups than CUs can hold at once, so the work
-// spreads evenly): x of the tile is staged in LDS
-// (the entries then read it with LDS gathers instead of L1/L2 gathers), and
-// the wavefronts walk batches of kDotBatch consecutive chunks of the list in
-// two levels: level 1 loads the entries, lengths and per-chunk ordinals of a
-// batch; level 2 reads x from LDS and loads the end_slot slices of the
-// chunks.  The level-1 loads of the next batch are issued before the current
-// batch is reduced, so they stay in flight meanwhile.
+// spreads evenly): x of the tile is staged in LDS (the entries then read it
+// with LDS gathers instead of L1/L2 gathers).  A wavefront walks batches of
+// kDotBatch consecutive chunks (batch j, j + kPlanWaves, ...) in a
+// three-stage software pipeline: stage A loads a batch's entries, lengths and
+// per-chunk piece-end ordinals; stage B loads the end_slot slices of the
+// batch's chunks (it needs stage A's ordinals); stage C reduces the batch.
+// While batch j is reduced, stage A of j + 2 and stage B of j + 1 are in
+// flight.  Every load is issued unconditionally (addresses clamped into the
+// list, results masked), so the wait counts stay static.
 #ifndef PCT_DOT_BATCH
-#define PCT_DOT_BATCH 8
+#define PCT_DOT_BATCH 4
 #endif
 constexpr int kDotBatch = PCT_DOT_BATCH;
 constexpr int kPlanWaves = 8;
 constexpr int kPlanThreads = kPlanWaves * kWave;
 constexpr int kDotSplit = 4;   // workgroups per (block, tile) list, each on a quarter of its chunks
 
+struct DotStageA {
+  uint32_t v[kDotBatch];  // entry codes (0 past the share's end)
+  float l[kDotBatch];     // lengths
+  int64_t fe[kDotBatch];  // first piece-end ordinal of each chunk
+  int ne[kDotBatch];      // piece ends of each chunk (>= 1 for any chunk holding an entry)
+};
+
 template <int LD>
-__device__ __forceinline__ void dot_level1(const PlanView &V, int64_t cw, int nc, int lane, uint32_t (&v)[kDotBatch],
-                                           float (&l)[kDotBatch], int64_t (&fe)[kDotBatch + 1]) {
+__device__ __forceinline__ void dot_stage_a(const PlanView &V, int64_t ca, int64_t cb, int64_t j, int lane,
+                                            DotStageA &a) {
 #pragma unroll
   for (int k = 0; k < kDotBatch; ++k) {
-    v[k] = 0u;
-    l[k] = 0.f;
-    if (k < nc) {
-      const int64_t p = (cw + k) * kWave + lane;
-      v[k] = (uint32_t)__builtin_nontemporal_load(V.packed + p);
-      l[k] = plan_len<LD>(V, p);
-    }
+    const int64_t c0 = ca + j * kDotBatch + k;
+    const bool in = c0 < cb;
+    const int64_t c = in ? c0 : cb - 1;
+    const int64_t p = c * kWave + lane;
+    const uint32_t v = (uint32_t)__builtin_nontemporal_load(V.packed + p);
+    const float l = plan_len<LD>(V, p);
+    a.v[k] = in ? v : 0u;
+    a.l[k] = l;
+    const int64_t f0 = V.chunk_first_end[c], f1 = V.chunk_first_end[c + 1];
+    a.fe[k] = f0;
+    a.ne[k] = (int)(f1 - f0);
   }
+}
+
+__device__ __forceinline__ void dot_stage_b(const PlanView &V, const DotStageA &a, int lane,
+                                            uint32_t (&es)[kDotBatch]) {
 #pragma unroll
-  for (int k = 0; k <= kDotBatch; ++k) fe[k] = k <= nc ? V.chunk_first_end[cw + k] : 0;
+  for (int k = 0; k < kDotBatch; ++k) {
+    const int n = a.ne[k] > 0 ? a.ne[k] : 1;
+    es[k] = V.end_slot[a.fe[k] + (lane < n ? lane : n - 1)];
+  }
 }
 
 // x of tile t (2048 voxels, zero outside the grid) -> s_x
@@ -329,60 +349,42 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan_dot(PlanView V, int64_t b
   const int64_t nbat = (cb - ca + kDotBatch - 1) / kDotBatch;
   int64_t j = uniform((int)(threadIdx.x / kWave));
   if (j >= nbat) return;
-  uint32_t v[kDotBatch];
-  float l[kDotBatch];
-  int64_t fe[kDotBatch + 1];
-  int64_t cw = ca + j * kDotBatch;
-  int nc = (int)(cb - cw < kDotBatch ? cb - cw : kDotBatch);
-  dot_level1<LD>(V, cw, nc, lane, v, l, fe);
+  // batches past the last are loaded as the last one again (never reduced)
+  const int64_t jlast = j + (nbat - 1 - j) / kPlanWaves * kPlanWaves;
+  DotStageA a0, a1, a2;
+  uint32_t e0[kDotBatch], e1[kDotBatch];
+  dot_stage_a<LD>(V, ca, cb, j, lane, a0);
+  dot_stage_a<LD>(V, ca, cb, j + kPlanWaves <= jlast ? j + kPlanWaves : jlast, lane, a1);
+  dot_stage_b(V, a0, lane, e0);
   for (;;) {
-    // level 2 of the current batch
-    float xv[kDotBatch];
-    uint32_t es[kDotBatch];
-#pragma unroll
-    for (int k = 0; k < kDotBatch; ++k) {
-      xv[k] = (v[k] & 1u) ? s_x[(v[k] >> 2) & (kTileVox - 1)] : 0.f;
-      es[k] = (k < nc && lane < fe[k + 1] - fe[k]) ? V.end_slot[fe[k] + lane] : 0u;
-    }
-    // level 1 of the next batch
-    const int64_t jn = j + kPlanWaves;
-    uint32_t vn[kDotBatch];
-    float ln[kDotBatch];
-    int64_t fen[kDotBatch + 1];
-    int64_t cwn = 0;
-    int ncn = 0;
-    if (jn < nbat) {
-      cwn = ca + jn * kDotBatch;
-      ncn = (int)(cb - cwn < kDotBatch ? cb - cwn : kDotBatch);
-      dot_level1<LD>(V, cwn, ncn, lane, vn, ln, fen);
-    }
+    const int64_t j1 = j + kPlanWaves, j2 = j + 2 * kPlanWaves;
+    dot_stage_b(V, a1, lane, e1);
+    dot_stage_a<LD>(V, ca, cb, j2 <= jlast ? j2 : jlast, lane, a2);
+    const int nc = (int)(cb - (ca + j * kDotBatch) < kDotBatch ? cb - (ca + j * kDotBatch) : kDotBatch);
 #pragma unroll
     for (int k = 0; k < kDotBatch; ++k) {
       if (k >= nc) continue;  // nc is wave-uniform
-      const bool valid = v[k] & 1u;
-      const bool close = valid && (((v[k] >> 1) & 1u) || lane == kWave - 1);
+      const uint32_t v = a0.v[k];
+      const bool valid = v & 1u;
+      const float xv = valid ? s_x[(v >> 2) & (kTileVox - 1)] : 0.f;
+      const bool close = valid && (((v >> 1) & 1u) || lane == kWave - 1);
       const uint64_t m = __ballot(close);
       // a piece's sum is the difference of the prefix sums at its closing lane
       // and at the previous closing lane
-      const float S = wave_incl_scan_dpp(valid ? l[k] * xv[k] : 0.0f);
+      const float S = wave_incl_scan_dpp(valid ? a0.l[k] * xv : 0.0f);
       const uint64_t below = m & ((1ull << lane) - 1);
       const int prev = below ? 63 - __clzll(below) : lane;
       const float Sp = __shfl(S, prev, kWave);
       // the end_slot entry of this chunk's n-th piece end sits in lane n
-      const uint32_t slot = (uint32_t)__shfl((int)es[k], __popcll(below), kWave);
+      const uint32_t slot = (uint32_t)__shfl((int)e0[k], __popcll(below), kWave);
       if (close) V.partial[slot] = below ? S - Sp : S;
     }
-    if (jn >= nbat) break;
-    j = jn;
-    cw = cwn;
-    nc = ncn;
+    if (j1 > jlast) break;
+    j = j1;
+    a0 = a1;
+    a1 = a2;
 #pragma unroll
-    for (int k = 0; k < kDotBatch; ++k) {
-      v[k] = vn[k];
-      l[k] = ln[k];
-    }
-#pragma unroll
-    for (int k = 0; k <= kDotBatch; ++k) fe[k] = fen[k];
+    for (int k = 0; k < kDotBatch; ++k) e0[k] = e1[k];
   }
 }
 
