@@ -325,13 +325,23 @@ __device__ __forceinline__ void dot_stage_b(const PlanView &V, const DotStageA &
   }
 }
 
-// x of tile t (2048 voxels, zero outside the grid) -> s_x
+// x of tile t (2048 voxels, zero outside the grid) -> s_x; every thread
+// issues its kTileVox / kPlanThreads loads before storing any (voxels outside
+// the grid load voxel 0 and store 0)
 __device__ __forceinline__ void stage_tile_x(const PlanView &V, int64_t t, const float *__restrict__ x, float *s_x) {
+  constexpr int kPer = kTileVox / kPlanThreads;
   const int tx = (int)(t % V.ntx), r = (int)(t / V.ntx), ty = r % V.nty, tz = r / V.nty;
-  for (int i = threadIdx.x; i < kTileVox; i += blockDim.x) {
+  float xv[kPer];
+  bool in[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int i = (int)threadIdx.x + u * kPlanThreads;
     const int ix = tx * kTX + (i & 15), iy = ty * kTY + ((i >> 4) & 15), iz = tz * kTZ + (i >> 8);
-    s_x[i] = (ix < V.nx && iy < V.ny && iz < V.nz) ? x[((int64_t)iz * V.ny + iy) * V.nx + ix] : 0.0f;
+    in[u] = ix < V.nx && iy < V.ny && iz < V.nz;
+    xv[u] = x[in[u] ? ((int64_t)iz * V.ny + iy) * V.nx + ix : 0];
   }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) s_x[(int)threadIdx.x + u * kPlanThreads] = in[u] ? xv[u] : 0.0f;
 }
 
 template <int LD>
@@ -767,8 +777,24 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan_scatter(PlanView V, int64
   const float *r_list = V.r_ord + (V.chunk_first_end[a0 / kWave] - V.chunk_first_end[V.bt_off[b * V.T] / kWave]);
   const int64_t nord = V.chunk_first_end[a1 / kWave] - V.chunk_first_end[a0 / kWave];
   const bool staged = nord <= kStageOrd;
-  if (staged)
-    for (int64_t i = threadIdx.x; i < nord; i += kPlanThreads) s_r[i] = r_list[i];
+  if (staged && nord > 0) {
+    // kStageLoads loads per thread in flight before any store (indices past
+    // the list read its last value and store nothing)
+    constexpr int kStageLoads = 8;
+    for (int64_t i0 = threadIdx.x; i0 < nord; i0 += (int64_t)kPlanThreads * kStageLoads) {
+      float rv[kStageLoads];
+#pragma unroll
+      for (int u = 0; u < kStageLoads; ++u) {
+        const int64_t i = i0 + (int64_t)u * kPlanThreads;
+        rv[u] = r_list[i < nord ? i : nord - 1];
+      }
+#pragma unroll
+      for (int u = 0; u < kStageLoads; ++u) {
+        const int64_t i = i0 + (int64_t)u * kPlanThreads;
+        if (i < nord) s_r[i] = rv[u];
+      }
+    }
+  }
   __syncthreads();
   constexpr int kGroupsPerPart = kGroups / kScatSplit;
   for (int grp = part * kGroupsPerPart + wid; grp < (part + 1) * kGroupsPerPart; grp += kPlanWaves) {
