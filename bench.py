@@ -356,6 +356,7 @@ def main():
             "rows": "fused" if args.fused else cfg.rows, "path_positions": "f32" if args.path_fp32 else "f64",
             "nnz_per_history": round(nnz / N, 2) if nnz else None,
             "trace_ms": round(trace_ms, 3), "sweep_ms": round(sweep_ms, 3),
+            "sweep_only_hist_per_s": round(N / (sweep_ms / 1e3), 1) if sweep_ms > 0 else None,
             "residual_ms": round(residual_ms, 3),
             "kernel_ms": {k: [v[0], round(v[1], 3)] for k, v in prof.items()},
             "kernel_rates": others, "path_points": points,
