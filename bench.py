@@ -266,9 +266,13 @@ def main():
                               HBM_PEAK_GBS, "GB/s", "pct::k_plan_dot<1>" if lbp == 2 else "pct::k_plan_dot<0>")
         models["plan_scatter"] = ("hbm", (4 + lbp) * nnz / n_blocks + 4 * ends_pb + 8 * M, HBM_PEAK_GBS, "GB/s",
                                   "pct::k_plan_scatter<1>" if lbp == 2 else "pct::k_plan_scatter<0>")
-    if rows is not None:
+    if rows is not None and plan is None:
         models["project"] = ("hbm", ((4 + lb) * nnz + (16 + 8 + 8 + 4) * N) / n_blocks + 20 * M, HBM_PEAK_GBS,
                              "GB/s", "pct::k_project_cached<0>")
+    if args.fused:
+        # rows rebuilt in every block: the path work of the block's histories
+        models["project"] = ("alu", PATH_FLOPS_PER_POINT * points / n_blocks, FP64_PEAK_TFLOPS, "TFLOP/s",
+                             "pct::k_project_fused<float>" if args.path_fp32 else "pct::k_project_fused<double>")
     timing = dict(prof)
     timing["trace"] = prof["trace_path"]
     dom = max((k for k in models if timing.get(k, (0, 0.0))[0]), key=lambda k: timing[k][1])

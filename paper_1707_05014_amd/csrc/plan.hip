@@ -267,7 +267,8 @@ __device__ __forceinline__ float plan_len(const PlanView &V, int64_t p) {
   if constexpr (LD == 0)
     return __builtin_nontemporal_load(reinterpret_cast<const float *>(V.len) + p);
   else
-    return __half2float(reinterpret_cast<const __half *>(V.len)[p]) * V.len_unit;
+    return __half2float(__builtin_bit_cast(
+               __half, __builtin_nontemporal_load(reinterpret_cast<const uint16_t *>(V.len) + p))) * V.len_unit;
 }
 
 // Partial dot products of every piece of block b.  kDotSplit workgroups of
@@ -734,16 +735,19 @@ constexpr int kScatBatch = PCT_SCAT_BATCH;
 template <int LD>
 __device__ __forceinline__ void scatter_level1(const PlanView &V, int64_t wb, int64_t e1, int lane,
                                                uint32_t (&v)[kScatBatch], float (&val)[kScatBatch]) {
+  // loads are unconditional (entries past e1 read entry e1 - 1 and are
+  // masked), so wait counts stay static
 #pragma unroll
   for (int k = 0; k < kScatBatch; ++k) {
-    const int64_t p = wb + (int64_t)k * kWave + lane;
-    v[k] = 0u;
-    val[k] = 0.0f;
-    if (p < e1) {
-      v[k] = __builtin_nontemporal_load(V.packedB + p);
-      val[k] = LD == 0 ? __builtin_nontemporal_load(reinterpret_cast<const float *>(V.lenB) + p)
-                       : __half2float(reinterpret_cast<const __half *>(V.lenB)[p]) * V.len_unit;
-    }
+    const int64_t p0 = wb + (int64_t)k * kWave + lane;
+    const bool in = p0 < e1;
+    const int64_t p = in ? p0 : e1 - 1;
+    const uint32_t vv = __builtin_nontemporal_load(V.packedB + p);
+    const float l = LD == 0 ? __builtin_nontemporal_load(reinterpret_cast<const float *>(V.lenB) + p)
+                            : __half2float(__builtin_bit_cast(__half, __builtin_nontemporal_load(
+                                  reinterpret_cast<const uint16_t *>(V.lenB) + p))) * V.len_unit;
+    v[k] = in ? vv : 0u;
+    val[k] = in ? l : 0.0f;
   }
 }
 
