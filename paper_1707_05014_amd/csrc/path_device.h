@@ -120,13 +120,23 @@ template <typename R> __device__ __forceinline__ R rsqrt_(R v);
 template <> __device__ __forceinline__ float rsqrt_(float v) { return sqrtf(v); }
 template <> __device__ __forceinline__ double rsqrt_(double v) { return sqrt(v); }
 
+// The prior's antiderivative tables cF[p][n] (3 x 8), staged per workgroup in
+// LDS so that they do not occupy scalar registers for the whole kernel.
 template <typename R> struct Tables;
 template <> struct Tables<double> {
-  __device__ static const double (&cF(const PathParams &P))[3][8] { return P.cF_d; }
+  __device__ static const double *cF(const PathParams &P) { return &P.cF_d[0][0]; }
 };
 template <> struct Tables<float> {
-  __device__ static const float (&cF(const PathParams &P))[3][8] { return P.cF_f; }
+  __device__ static const float *cF(const PathParams &P) { return &P.cF_f[0][0]; }
 };
+
+// copy the tables into s_cF[24] (all threads of the workgroup call it; it
+// ends with a workgroup barrier)
+template <typename R>
+__device__ __forceinline__ void stage_prior(const PathParams &P, R *s_cF) {
+  if (threadIdx.x < 24) s_cF[threadIdx.x] = Tables<R>::cF(P)[threadIdx.x];
+  __syncthreads();
+}
 
 // Interval [lo, hi] of u on which the line t(u) = t_ref + st (u - u_ref),
 // v(u) = v_ref + sv (u - u_ref) lies in the elliptic-cylinder hull.
@@ -171,7 +181,7 @@ struct ProtonPath {
 
 // Horner: d^(M+1) * sum_n c[n] d^n
 template <typename R, int M>
-__device__ __forceinline__ R moment(const R (&c)[8], R d) {
+__device__ __forceinline__ R moment(const R *c, R d) {
   R acc = (R)0;
 #pragma unroll
   for (int q = 7; q >= 0; --q) acc = acc * d + c[q];
@@ -185,7 +195,7 @@ __device__ __forceinline__ R moment(const R (&c)[8], R d) {
 // The hull intersections and end states are found in double for both path
 // precisions: they are per proton, and near-tangent lines are ill-conditioned.
 template <typename R>
-__device__ __forceinline__ void setup_path(const PathParams &P, const float h[10], ProtonPath<R> &pp) {
+__device__ __forceinline__ void setup_path(const PathParams &P, const R *cF, const float h[10], ProtonPath<R> &pp) {
   pp.valid = false;
   pp.K = 0;
   bool fin = true;
@@ -221,10 +231,9 @@ __device__ __forceinline__ void setup_path(const PathParams &P, const float h[10
   pp.dts = (R)((double)h[7] - st0);
   pp.dvt = (R)(v2 - (v0 + sv0 * L));
   pp.dvs = (R)((double)h[8] - sv0);
-  const auto &cF = Tables<R>::cF(P);
-  pp.FL[0] = moment<R, 0>(cF[0], pp.L);
-  pp.FL[1] = moment<R, 1>(cF[1], pp.L);
-  pp.FL[2] = moment<R, 2>(cF[2], pp.L);
+  pp.FL[0] = moment<R, 0>(cF, pp.L);
+  pp.FL[1] = moment<R, 1>(cF + 8, pp.L);
+  pp.FL[2] = moment<R, 2>(cF + 16, pp.L);
   pp.valid = true;
   // every lane computed the same values: keep one copy in scalar registers
   pp.K = uniform(pp.K);
@@ -241,13 +250,13 @@ __device__ __forceinline__ void setup_path(const PathParams &P, const float h[10
 // the binomial expansions of (d1 - s)^m and (L - s)^m (the common factor
 // E0^2/X0 cancels in the gain).
 template <typename R>
-__device__ __forceinline__ void mlp_point(const PathParams &P, const ProtonPath<R> &pp, R d1, R &t, R &v) {
-  const auto &cF = Tables<R>::cF(P);
+__device__ __forceinline__ void mlp_point(const PathParams &P, const R *cF, const ProtonPath<R> &pp, R d1, R &t,
+                                          R &v) {
   const R L = pp.L;
   const R d2 = L - d1;
-  const R F0 = moment<R, 0>(cF[0], d1);
-  const R F1 = moment<R, 1>(cF[1], d1);
-  const R F2 = moment<R, 2>(cF[2], d1);
+  const R F0 = moment<R, 0>(cF, d1);
+  const R F1 = moment<R, 1>(cF + 8, d1);
+  const R F2 = moment<R, 2>(cF + 16, d1);
   R I0 = F0;
   R I1 = d1 * F0 - F1;
   R I2 = d1 * (d1 * F0 - (R)2 * F1) + F2;
@@ -329,14 +338,14 @@ __device__ __forceinline__ int walk_segment(const PathParams &P, int bx, int by,
 }
 
 // Build the row of one proton in the wavefront's LDS slice (s_vox, s_len,
-// s_aux of P.emax entries each).  Returns the entry count (wave-uniform);
+// s_aux of P.emax entries each); cF = the staged prior tables.  Returns the entry count (wave-uniform);
 // on a bound violation sets `status` bits and returns 0.
 template <typename R>
-__device__ int build_row(const PathParams &P, const float h[10], int *s_vox, float *s_len, int *s_aux,
+__device__ int build_row(const PathParams &P, const R *cF, const float h[10], int *s_vox, float *s_len, int *s_aux,
                          uint32_t *status) {
   const int lane = wave_lane();
   ProtonPath<R> pp;
-  setup_path<R>(P, h, pp);
+  setup_path<R>(P, cF, h, pp);
   if (!pp.valid) return 0;
   if (pp.K > P.kmax) {
     if (lane == 0) atomicOr(status, kStOverflow);
@@ -361,7 +370,7 @@ __device__ int build_row(const PathParams &P, const float h[10], int *s_vox, flo
         d1 = pp.L;
       } else {
         d1 = (R)k * du;
-        mlp_point<R>(P, pp, d1, t, v);
+        mlp_point<R>(P, cF, pp, d1, t, v);
       }
       const R u = pp.u0 + d1;
       wx = u * pp.c - t * pp.s;

@@ -71,6 +71,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   int *s_vox = smem + wid * 3 * P.emax;
   float *s_len = reinterpret_cast<float *>(s_vox + P.emax);
   int *s_aux = s_vox + 2 * P.emax;
+  __shared__ R s_cF[24];
+  stage_prior<R>(P, s_cF);
   const int64_t stride = (int64_t)gridDim.x * P.waves_per_block;
   for (int64_t q = (int64_t)blockIdx.x * P.waves_per_block + wid; q < count; q += stride) {
     const int64_t i = order ? order[first + q] : first + q;
@@ -80,7 +82,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     }
     float h[10];
     load_history(H, i, h);
-    const int ne = build_row<R>(P, h, s_vox, s_len, s_aux, status);
+    const int ne = build_row<R>(P, s_cF, h, s_vox, s_len, s_aux, status);
     if (ne == 0) continue;
     float d = 0.0f;
     double n2 = 0.0;
@@ -200,12 +202,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   int *s_vox = smem + wid * 3 * P.emax;
   float *s_len = reinterpret_cast<float *>(s_vox + P.emax);
   int *s_aux = s_vox + 2 * P.emax;
+  __shared__ R s_cF[24];
+  stage_prior<R>(P, s_cF);
   double acc = 0.0;
   const int64_t stride = (int64_t)gridDim.x * P.waves_per_block;
   for (int64_t i = (int64_t)blockIdx.x * P.waves_per_block + wid; i < n; i += stride) {
     float h[10];
     load_history(H, i, h);
-    const int ne = build_row<R>(P, h, s_vox, s_len, s_aux, status);
+    const int ne = build_row<R>(P, s_cF, h, s_vox, s_len, s_aux, status);
     if (ne == 0) continue;
     float d = 0.0f;
     for (int e = lane; e < ne; e += kWave) d = fmaf(s_len[e], x[s_vox[e]], d);

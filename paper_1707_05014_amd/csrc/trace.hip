@@ -23,6 +23,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   int *s_vox = smem + wid * 3 * P.emax;
   float *s_len = reinterpret_cast<float *>(s_vox + P.emax);
   int *s_aux = s_vox + 2 * P.emax;
+  __shared__ R s_cF[24];
+  stage_prior<R>(P, s_cF);
   const int64_t stride = (int64_t)gridDim.x * P.waves_per_block;
   for (int64_t q = (int64_t)blockIdx.x * P.waves_per_block + wid; q < nrows; q += stride) {
     const int64_t i = i0 + q;
@@ -31,7 +33,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     bool fin = true;
     for (int k = 0; k < 10; ++k) fin = fin && isfinite(h[k]);
     if (!fin && lane == 0) atomicOr(status, kStNonFinite);
-    const int c = build_row<R>(P, h, s_vox, s_len, s_aux, status);
+    const int c = build_row<R>(P, s_cF, h, s_vox, s_len, s_aux, status);
     if (lane == 0) cnt[q] = c;
     if (!st_idx) continue;
     int32_t *di = st_idx + q * P.emax;
