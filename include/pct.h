@@ -250,6 +250,52 @@ pct_status pct_profile_read(int64_t *launches, double *ms);
 /* Message for the last failing call on this thread (empty if none). */
 const char *pct_last_error(void);
 
+/* ---- Learned warm start: operations of a small 3D U-Net on the image.
+ * A network trained on pairs (image after a few sweeps, image after many
+ * sweeps) produced by the solver itself gives the initial guess x0 of the
+ * sweeps (the paper leaves x0 to the user, Sec. 2.1); the plain sweeps from
+ * the hull start stay the fallback.  Tensors are device float32 [C][D][H][W]
+ * (W fastest), caller-owned; outputs must not alias inputs.  D*H*W < 2^31.
+ * Gradients are written, not accumulated.  Every call is asynchronous on
+ * `stream` and returns PCT_EINVAL for NULL pointers or bad sizes. */
+
+/* y[co] = b[co] + sum_ci w[co][ci] (*) x[ci], 3x3x3 kernel, zero padding.
+ * w [cout][cin][3][3][3]; b [cout] or NULL. */
+pct_status pct_cnn_conv3d(const float *x, const float *w, const float *b, float *y, int32_t cin, int32_t cout,
+                          int32_t D, int32_t H, int32_t W, void *stream);
+/* input gradient dx [cin] of the convolution from dy [cout]; wt: scratch of
+ * cin * cout * 27 floats */
+pct_status pct_cnn_conv3d_bwd_data(const float *dy, const float *w, float *dx, float *wt, int32_t cin, int32_t cout,
+                                   int32_t D, int32_t H, int32_t W, void *stream);
+/* floats of scratch that pct_cnn_conv3d_bwd_weight needs */
+int64_t pct_cnn_wgrad_scratch(int32_t cin, int32_t cout, int32_t D, int32_t H, int32_t W);
+/* weight gradient dw [cout][cin][27] and bias gradient db [cout] (or NULL)
+ * from the layer input x [cin] and dy [cout]; fixed summation order */
+pct_status pct_cnn_conv3d_bwd_weight(const float *x, const float *dy, float *dw, float *db, float *scratch,
+                                     int32_t cin, int32_t cout, int32_t D, int32_t H, int32_t W, void *stream);
+/* y = max(x, 0); dx = dy where y > 0 (y = the ReLU output) */
+pct_status pct_cnn_relu(const float *x, float *y, int64_t n, void *stream);
+pct_status pct_cnn_relu_bwd(const float *y, const float *dy, float *dx, int64_t n, void *stream);
+/* 2x2x2 average pooling [C][D][H][W] -> [C][D/2][H/2][W/2] (D, H, W even) and
+ * its gradient */
+pct_status pct_cnn_pool(const float *x, float *y, int32_t C, int32_t D, int32_t H, int32_t W, void *stream);
+pct_status pct_cnn_pool_bwd(const float *dy, float *dx, int32_t C, int32_t D, int32_t H, int32_t W, void *stream);
+/* nearest 2x upsampling [C][d][h][w] -> [C][2d][2h][2w] and its gradient */
+pct_status pct_cnn_upsample(const float *x, float *y, int32_t C, int32_t d, int32_t h, int32_t w, void *stream);
+pct_status pct_cnn_upsample_bwd(const float *dy, float *dx, int32_t C, int32_t d, int32_t h, int32_t w,
+                                void *stream);
+/* y = a + b (elementwise, n values) */
+pct_status pct_cnn_add(const float *a, const float *b, float *y, int64_t n, void *stream);
+/* *loss (device double) = mean (y - t)^2 over n values (FP64 sums in fixed
+ * order); dy = 2 (y - t) / n when dy != NULL; scratch: pct_cnn_mse_scratch(n)
+ * doubles */
+int64_t pct_cnn_mse_scratch(int64_t n);
+pct_status pct_cnn_mse(const float *y, const float *t, float *dy, double *scratch, double *loss, int64_t n,
+                       void *stream);
+/* one Adam step (Kingma & Ba 2015, bias-corrected, step >= 1) on n weights */
+pct_status pct_cnn_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float beta1, float beta2,
+                        float eps, int32_t step, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -71,7 +71,10 @@ class pct_sweep_params(ctypes.Structure):
 
 EXPORTS = ("pct_workspace_size", "pct_mlp_trace", "pct_project_sweep", "pct_plan_build", "pct_plan_sweep",
            "pct_plan_residual", "pct_reconstruct", "pct_residual", "pct_roi_stats", "pct_profile_enable",
-           "pct_profile_read", "pct_last_error")
+           "pct_profile_read", "pct_last_error",
+           "pct_cnn_conv3d", "pct_cnn_conv3d_bwd_data", "pct_cnn_wgrad_scratch", "pct_cnn_conv3d_bwd_weight",
+           "pct_cnn_relu", "pct_cnn_relu_bwd", "pct_cnn_pool", "pct_cnn_pool_bwd", "pct_cnn_upsample",
+           "pct_cnn_upsample_bwd", "pct_cnn_add", "pct_cnn_mse_scratch", "pct_cnn_mse", "pct_cnn_adam")
 KERNEL_CLASSES = ("trace_path", "trace_compact", "project", "apply", "residual", "art", "other", "plan_dot",
                   "plan_rows", "plan_scatter", "plan_build")
 
@@ -126,6 +129,29 @@ def load(path: str | None = None):
     lib.pct_profile_read.argtypes = [P(ctypes.c_int64), P(ctypes.c_double)]
     lib.pct_last_error.restype = ctypes.c_char_p
     lib.pct_last_error.argtypes = []
+    i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    cnn = {
+        "pct_cnn_conv3d": [_fp, _fp, _fp, _fp, i32, i32, i32, i32, i32, _fp],
+        "pct_cnn_conv3d_bwd_data": [_fp, _fp, _fp, _fp, i32, i32, i32, i32, i32, _fp],
+        "pct_cnn_conv3d_bwd_weight": [_fp, _fp, _fp, _fp, _fp, i32, i32, i32, i32, i32, _fp],
+        "pct_cnn_relu": [_fp, _fp, i64, _fp],
+        "pct_cnn_relu_bwd": [_fp, _fp, _fp, i64, _fp],
+        "pct_cnn_pool": [_fp, _fp, i32, i32, i32, i32, _fp],
+        "pct_cnn_pool_bwd": [_fp, _fp, i32, i32, i32, i32, _fp],
+        "pct_cnn_upsample": [_fp, _fp, i32, i32, i32, i32, _fp],
+        "pct_cnn_upsample_bwd": [_fp, _fp, i32, i32, i32, i32, _fp],
+        "pct_cnn_add": [_fp, _fp, _fp, i64, _fp],
+        "pct_cnn_mse": [_fp, _fp, _fp, _fp, _fp, i64, _fp],
+        "pct_cnn_adam": [_fp, _fp, _fp, _fp, i64, f32, f32, f32, f32, i32, _fp],
+    }
+    for name, argt in cnn.items():
+        fn = getattr(lib, name)
+        fn.restype = ctypes.c_int
+        fn.argtypes = argt
+    lib.pct_cnn_wgrad_scratch.restype = i64
+    lib.pct_cnn_wgrad_scratch.argtypes = [i32, i32, i32, i32, i32]
+    lib.pct_cnn_mse_scratch.restype = i64
+    lib.pct_cnn_mse_scratch.argtypes = [i64]
     if path is None:
         _lib = lib
     return lib

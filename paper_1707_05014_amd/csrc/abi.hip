@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "cnn_internal.h"
 #include "pct_internal.h"
 
 namespace {
@@ -817,5 +818,125 @@ pct_status pct_profile_read(int64_t *launches, double *ms) {
 }
 
 const char *pct_last_error(void) { return g_err.c_str(); }
+
+// ---- warm-start network operations
+#define CNN_VOL_CHECK(C, D, H, W)                                                                       \
+  do {                                                                                                  \
+    if ((C) <= 0 || (D) <= 0 || (H) <= 0 || (W) <= 0) return fail(PCT_EINVAL, "sizes must be positive"); \
+    if ((int64_t)(D) * (H) * (W) >= (int64_t(1) << 31)) return fail(PCT_EINVAL, "volume has 2^31 voxels or more"); \
+  } while (0)
+
+pct_status pct_cnn_conv3d(const float *x, const float *w, const float *b, float *y, int32_t cin, int32_t cout,
+                          int32_t D, int32_t H, int32_t W, void *stream) {
+  g_err.clear();
+  CNN_VOL_CHECK(cin, D, H, W);
+  if (cout <= 0) return fail(PCT_EINVAL, "cout must be positive");
+  if (!x || !w || !y) return fail(PCT_EINVAL, "NULL tensor");
+  HIPCHECK(pct::cnn::conv3d(x, w, b, y, cin, cout, D, H, W, reinterpret_cast<hipStream_t>(stream)));
+  return PCT_OK;
+}
+
+pct_status pct_cnn_conv3d_bwd_data(const float *dy, const float *w, float *dx, float *wt, int32_t cin, int32_t cout,
+                                   int32_t D, int32_t H, int32_t W, void *stream) {
+  g_err.clear();
+  CNN_VOL_CHECK(cin, D, H, W);
+  if (cout <= 0) return fail(PCT_EINVAL, "cout must be positive");
+  if (!dy || !w || !dx || !wt) return fail(PCT_EINVAL, "NULL tensor");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIPCHECK(pct::cnn::flip_weights(w, wt, cin, cout, s));
+  HIPCHECK(pct::cnn::conv3d(dy, wt, nullptr, dx, cout, cin, D, H, W, s));
+  return PCT_OK;
+}
+
+int64_t pct_cnn_wgrad_scratch(int32_t cin, int32_t cout, int32_t D, int32_t H, int32_t W) {
+  if (cin <= 0 || cout <= 0 || D <= 0 || H <= 0 || W <= 0) return 0;
+  return pct::cnn::wgrad_chunks(D, H, W) * cout * ((int64_t)cin * 27 + 1);
+}
+
+pct_status pct_cnn_conv3d_bwd_weight(const float *x, const float *dy, float *dw, float *db, float *scratch,
+                                     int32_t cin, int32_t cout, int32_t D, int32_t H, int32_t W, void *stream) {
+  g_err.clear();
+  CNN_VOL_CHECK(cin, D, H, W);
+  if (cout <= 0) return fail(PCT_EINVAL, "cout must be positive");
+  if (!x || !dy || !dw || !scratch) return fail(PCT_EINVAL, "NULL tensor");
+  HIPCHECK(pct::cnn::conv3d_wgrad(x, dy, dw, db, scratch, cin, cout, D, H, W, reinterpret_cast<hipStream_t>(stream)));
+  return PCT_OK;
+}
+
+pct_status pct_cnn_relu(const float *x, float *y, int64_t n, void *stream) {
+  g_err.clear();
+  if (n < 0 || (n > 0 && (!x || !y))) return fail(PCT_EINVAL, "bad relu arguments");
+  HIPCHECK(pct::cnn::relu(x, y, n, reinterpret_cast<hipStream_t>(stream)));
+  return PCT_OK;
+}
+
+pct_status pct_cnn_relu_bwd(const float *y, const float *dy, float *dx, int64_t n, void *stream) {
+  g_err.clear();
+  if (n < 0 || (n > 0 && (!y || !dy || !dx))) return fail(PCT_EINVAL, "bad relu_bwd arguments");
+  HIPCHECK(pct::cnn::relu_bwd(y, dy, dx, n, reinterpret_cast<hipStream_t>(stream)));
+  return PCT_OK;
+}
+
+pct_status pct_cnn_pool(const float *x, float *y, int32_t C, int32_t D, int32_t H, int32_t W, void *stream) {
+  g_err.clear();
+  CNN_VOL_CHECK(C, D, H, W);
+  if ((D | H | W) & 1) return fail(PCT_EINVAL, "pooling needs even D, H, W");
+  if (!x || !y) return fail(PCT_EINVAL, "NULL tensor");
+  HIPCHECK(pct::cnn::pool(x, y, C, D, H, W, reinterpret_cast<hipStream_t>(stream)));
+  return PCT_OK;
+}
+
+pct_status pct_cnn_pool_bwd(const float *dy, float *dx, int32_t C, int32_t D, int32_t H, int32_t W, void *stream) {
+  g_err.clear();
+  CNN_VOL_CHECK(C, D, H, W);
+  if ((D | H | W) & 1) return fail(PCT_EINVAL, "pooling needs even D, H, W");
+  if (!dy || !dx) return fail(PCT_EINVAL, "NULL tensor");
+  HIPCHECK(pct::cnn::pool_bwd(dy, dx, C, D, H, W, reinterpret_cast<hipStream_t>(stream)));
+  return PCT_OK;
+}
+
+pct_status pct_cnn_upsample(const float *x, float *y, int32_t C, int32_t d, int32_t h, int32_t w, void *stream) {
+  g_err.clear();
+  CNN_VOL_CHECK(C, 2 * d, 2 * h, 2 * w);
+  if (!x || !y) return fail(PCT_EINVAL, "NULL tensor");
+  HIPCHECK(pct::cnn::upsample(x, y, C, d, h, w, reinterpret_cast<hipStream_t>(stream)));
+  return PCT_OK;
+}
+
+pct_status pct_cnn_upsample_bwd(const float *dy, float *dx, int32_t C, int32_t d, int32_t h, int32_t w,
+                                void *stream) {
+  g_err.clear();
+  CNN_VOL_CHECK(C, 2 * d, 2 * h, 2 * w);
+  if (!dy || !dx) return fail(PCT_EINVAL, "NULL tensor");
+  HIPCHECK(pct::cnn::upsample_bwd(dy, dx, C, d, h, w, reinterpret_cast<hipStream_t>(stream)));
+  return PCT_OK;
+}
+
+pct_status pct_cnn_add(const float *a, const float *b, float *y, int64_t n, void *stream) {
+  g_err.clear();
+  if (n < 0 || (n > 0 && (!a || !b || !y))) return fail(PCT_EINVAL, "bad add arguments");
+  HIPCHECK(pct::cnn::add(a, b, y, n, reinterpret_cast<hipStream_t>(stream)));
+  return PCT_OK;
+}
+
+int64_t pct_cnn_mse_scratch(int64_t n) { return n > 0 ? pct::cnn::mse_parts(n) : 0; }
+
+pct_status pct_cnn_mse(const float *y, const float *t, float *dy, double *scratch, double *loss, int64_t n,
+                       void *stream) {
+  g_err.clear();
+  if (n <= 0 || !y || !t || !scratch || !loss) return fail(PCT_EINVAL, "bad mse arguments");
+  HIPCHECK(pct::cnn::mse(y, t, dy, scratch, loss, n, reinterpret_cast<hipStream_t>(stream)));
+  return PCT_OK;
+}
+
+pct_status pct_cnn_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float beta1, float beta2,
+                        float eps, int32_t step, void *stream) {
+  g_err.clear();
+  if (n < 0 || (n > 0 && (!w || !g || !m || !v))) return fail(PCT_EINVAL, "bad adam arguments");
+  if (step < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return fail(PCT_EINVAL, "bad adam hyper-parameters");
+  HIPCHECK(pct::cnn::adam(w, g, m, v, n, lr, beta1, beta2, eps, step, reinterpret_cast<hipStream_t>(stream)));
+  return PCT_OK;
+}
 
 }  // extern "C"

@@ -1,0 +1,418 @@
+// Kernels of the learned warm start: a small 3D U-Net over the image volume
+// (channels-first, one volume at a time: tensor [C][D][H][W], W fastest).
+// Operations: 3x3x3 convolution with zero padding (forward, input gradient,
+// weight and bias gradients), ReLU, 2x2x2 average pooling, nearest 2x
+// upsampling, addition, mean squared error and an Adam step.  FP32 storage
+// and accumulation; reductions (weight gradients, loss) are formed in a fixed
+// order, so every result is reproducible.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cnn_internal.h"
+#include "path_device.h"
+
+namespace pct {
+namespace cnn {
+
+constexpr int kThreads = 256;
+constexpr int kTaps = 27;
+
+struct Vol {
+  int D, H, W;
+  int64_t V;
+};
+
+__device__ __forceinline__ Vol make_vol(int D, int H, int W) { return {D, H, W, (int64_t)D * H * W}; }
+
+// The 27 neighbour offsets of voxel p and which of them lie inside the volume.
+__device__ __forceinline__ uint32_t tap_mask(const Vol &v, int z, int y, int x) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int t = 0; t < kTaps; ++t) {
+    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+    const bool in = z + dz >= 0 && z + dz < v.D && y + dy >= 0 && y + dy < v.H && x + dx >= 0 && x + dx < v.W;
+    m |= in ? (1u << t) : 0u;
+  }
+  return m;
+}
+
+__device__ __forceinline__ int64_t tap_offset(const Vol &v, int t) {
+  const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+  return ((int64_t)dz * v.H + dy) * v.W + dx;
+}
+
+// y[co] = b[co] + sum_ci sum_t w[co][ci][t] x[ci][p + off(t)], for a block of
+// COB output channels per thread (weights are wave-uniform: scalar loads).
+template <int COB>
+__global__ void __launch_bounds__(kThreads) k_conv3d(const float *__restrict__ x, const float *__restrict__ w,
+                                                     const float *__restrict__ b, float *__restrict__ y, int cin,
+                                                     int cout, int D, int H, int W) {
+  const Vol v = make_vol(D, H, W);
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int co0 = blockIdx.y * COB;
+  const bool live = p < v.V;
+  const int64_t pc = live ? p : 0;
+  const int xq = (int)(pc % W), yq = (int)((pc / W) % H), zq = (int)(pc / ((int64_t)W * H));
+  const uint32_t m = tap_mask(v, zq, yq, xq);
+  float acc[COB];
+#pragma unroll
+  for (int c = 0; c < COB; ++c) acc[c] = (b && co0 + c < cout) ? b[co0 + c] : 0.0f;
+  for (int ci = 0; ci < cin; ++ci) {
+    const float *xc = x + (int64_t)ci * v.V + pc;
+    float xt[kTaps];
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) {
+      // taps outside the volume read the centre voxel (always in bounds) and use 0
+      const bool in = (m >> t) & 1u;
+      const float xv = xc[in ? tap_offset(v, t) : 0];
+      xt[t] = in ? xv : 0.0f;
+    }
+#pragma unroll
+    for (int c = 0; c < COB; ++c) {
+      if (co0 + c < cout) {
+        const float *wc = w + ((int64_t)(co0 + c) * cin + ci) * kTaps;
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t) acc[c] = fmaf(wc[t], xt[t], acc[c]);
+      }
+    }
+  }
+  if (!live) return;
+#pragma unroll
+  for (int c = 0; c < COB; ++c)
+    if (co0 + c < cout) y[(int64_t)(co0 + c) * v.V + p] = acc[c];
+}
+
+// wt[ci][co][26 - t] = w[co][ci][t]: the input gradient of a convolution is the
+// convolution of the output gradient with these weights
+__global__ void __launch_bounds__(kThreads) k_flip(const float *__restrict__ w, float *__restrict__ wt, int cin,
+                                                   int cout) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t n = (int64_t)cin * cout * kTaps;
+  if (i >= n) return;
+  const int t = (int)(i % kTaps);
+  const int64_t r = i / kTaps;
+  const int ci = (int)(r % cin), co = (int)(r / cin);
+  wt[((int64_t)ci * cout + co) * kTaps + (kTaps - 1 - t)] = w[i];
+}
+
+// Weight and bias gradients, stage 1: workgroup g sums over its kWgVox voxels
+//   part[g][co][ci][t] = sum_p dy[co][p] x[ci][p + off(t)],  part[g][co][cin*27] = sum_p dy[co][p]
+// (grid: chunks x cout).  Each thread folds kWgVox / kThreads voxels in
+// registers, each wavefront adds its lanes with DPP prefix sums, and the
+// workgroup adds its wavefronts in order.
+constexpr int kWgVox = 2048;
+constexpr int kWaves = kThreads / 64;
+
+__device__ __forceinline__ float wave_total(float v) {
+  const float s = wave_incl_scan_dpp(v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, s), 63));
+}
+
+__global__ void __launch_bounds__(kThreads) k_wgrad_part(const float *__restrict__ x, const float *__restrict__ dy,
+                                                         float *__restrict__ part, int cin, int cout, int D, int H,
+                                                         int W) {
+  __shared__ float red[kWaves][kTaps + 1];
+  const Vol v = make_vol(D, H, W);
+  const int co = blockIdx.y;
+  const int64_t g = blockIdx.x;
+  const int wid = threadIdx.x / 64, lane = threadIdx.x % 64;
+  constexpr int kPer = kWgVox / kThreads;
+  float gv[kPer];
+  int32_t pv[kPer];
+  uint32_t mv[kPer];
+  float gsum = 0.0f;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int64_t p = g * kWgVox + (int64_t)k * kThreads + threadIdx.x;
+    const bool live = p < v.V;
+    pv[k] = live ? (int32_t)p : 0;
+    gv[k] = live ? dy[(int64_t)co * v.V + p] : 0.0f;
+    const int xq = pv[k] % W, yq = (pv[k] / W) % H, zq = pv[k] / (W * H);
+    mv[k] = live ? tap_mask(v, zq, yq, xq) : 0u;
+    gsum += gv[k];
+  }
+  const int64_t stride = (int64_t)cin * kTaps + 1;
+  float *out = part + (g * cout + co) * stride;
+  for (int ci = 0; ci < cin; ++ci) {
+    const float *xc = x + (int64_t)ci * v.V;
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) {
+      const int64_t off = tap_offset(v, t);
+      float a = 0.0f;
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        // taps outside the volume read the centre voxel (always in bounds) and use 0
+        const bool in = (mv[k] >> t) & 1u;
+        const float xv = xc[in ? pv[k] + off : pv[k]];
+        a = fmaf(gv[k], in ? xv : 0.0f, a);
+      }
+      const float sw = wave_total(a);
+      if (lane == 0) red[wid][t] = sw;
+    }
+    if (ci == 0) {
+      const float sg = wave_total(gsum);
+      if (lane == 0) red[wid][kTaps] = sg;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < kTaps) {
+      float s = 0.0f;
+      for (int w2 = 0; w2 < kWaves; ++w2) s += red[w2][threadIdx.x];
+      out[(int64_t)ci * kTaps + threadIdx.x] = s;
+    }
+    if (ci == 0 && threadIdx.x == kTaps) {
+      float s = 0.0f;
+      for (int w2 = 0; w2 < kWaves; ++w2) s += red[w2][kTaps];
+      out[(int64_t)cin * kTaps] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// stage 2: dw[co][ci][t] = sum_g part[g][co][ci][t] (g in order), db likewise
+__global__ void __launch_bounds__(kThreads) k_wgrad_sum(const float *__restrict__ part, float *__restrict__ dw,
+                                                        float *__restrict__ db, int64_t chunks, int cin, int cout) {
+  const int64_t stride = (int64_t)cin * kTaps + 1;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= (int64_t)cout * stride) return;
+  const int64_t co = i / stride, j = i % stride;
+  float s = 0.0f;
+  for (int64_t g = 0; g < chunks; ++g) s += part[(g * cout + co) * stride + j];
+  if (j < (int64_t)cin * kTaps)
+    dw[co * cin * kTaps + j] = s;
+  else if (db)
+    db[co] = s;
+}
+
+__global__ void __launch_bounds__(kThreads) k_relu(const float *__restrict__ x, float *__restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) y[i] = fmaxf(x[i], 0.0f);
+}
+
+// dx = dy where y > 0 (y = the ReLU output), else 0
+__global__ void __launch_bounds__(kThreads) k_relu_bwd(const float *__restrict__ y, const float *__restrict__ dy,
+                                                       float *__restrict__ dx, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) dx[i] = y[i] > 0.0f ? dy[i] : 0.0f;
+}
+
+// 2x2x2 average pooling of [C][D][H][W] (even D, H, W) -> [C][D/2][H/2][W/2]
+__global__ void __launch_bounds__(kThreads) k_pool(const float *__restrict__ x, float *__restrict__ y, int C, int D,
+                                                   int H, int W) {
+  const int d = D / 2, h = H / 2, w = W / 2;
+  const int64_t n = (int64_t)C * d * h * w;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const int xo = (int)(i % w), yo = (int)((i / w) % h), zo = (int)((i / ((int64_t)w * h)) % d);
+  const int64_t c = i / ((int64_t)w * h * d);
+  const float *xc = x + c * D * H * W;
+  float s = 0.0f;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int z = 2 * zo + (q >> 2), yy = 2 * yo + ((q >> 1) & 1), xx = 2 * xo + (q & 1);
+    s += xc[((int64_t)z * H + yy) * W + xx];
+  }
+  y[i] = s * 0.125f;
+}
+
+// gradient of the pooling: every fine voxel gets 1/8 of its coarse voxel's gradient
+__global__ void __launch_bounds__(kThreads) k_pool_bwd(const float *__restrict__ dy, float *__restrict__ dx, int C,
+                                                       int D, int H, int W) {
+  const int64_t n = (int64_t)C * D * H * W;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const int xx = (int)(i % W), yy = (int)((i / W) % H), z = (int)((i / ((int64_t)W * H)) % D);
+  const int64_t c = i / ((int64_t)W * H * D);
+  const int d = D / 2, h = H / 2, w = W / 2;
+  dx[i] = 0.125f * dy[((c * d + z / 2) * h + yy / 2) * w + xx / 2];
+}
+
+// nearest 2x upsampling of [C][d][h][w] -> [C][2d][2h][2w]
+__global__ void __launch_bounds__(kThreads) k_up(const float *__restrict__ x, float *__restrict__ y, int C, int d,
+                                                 int h, int w) {
+  const int D = 2 * d, H = 2 * h, W = 2 * w;
+  const int64_t n = (int64_t)C * D * H * W;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const int xx = (int)(i % W), yy = (int)((i / W) % H), z = (int)((i / ((int64_t)W * H)) % D);
+  const int64_t c = i / ((int64_t)W * H * D);
+  y[i] = x[((c * d + z / 2) * h + yy / 2) * w + xx / 2];
+}
+
+// gradient of the upsampling: each coarse voxel sums its 8 fine voxels
+__global__ void __launch_bounds__(kThreads) k_up_bwd(const float *__restrict__ dy, float *__restrict__ dx, int C,
+                                                     int d, int h, int w) {
+  const int D = 2 * d, H = 2 * h, W = 2 * w;
+  const int64_t n = (int64_t)C * d * h * w;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const int xo = (int)(i % w), yo = (int)((i / w) % h), zo = (int)((i / ((int64_t)w * h)) % d);
+  const int64_t c = i / ((int64_t)w * h * d);
+  const float *g = dy + c * D * H * W;
+  float s = 0.0f;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int z = 2 * zo + (q >> 2), yy = 2 * yo + ((q >> 1) & 1), xx = 2 * xo + (q & 1);
+    s += g[((int64_t)z * H + yy) * W + xx];
+  }
+  dx[i] = s;
+}
+
+__global__ void __launch_bounds__(kThreads) k_add(const float *__restrict__ a, const float *__restrict__ b,
+                                                  float *__restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) y[i] = a[i] + b[i];
+}
+
+// mean squared error: dy = 2 (y - t) / n, per-workgroup FP64 sums of (y - t)^2
+__global__ void __launch_bounds__(kThreads) k_mse(const float *__restrict__ y, const float *__restrict__ t,
+                                                  float *__restrict__ dy, double *__restrict__ part, int64_t n) {
+  __shared__ double red[kThreads];
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  double e2 = 0.0;
+  if (i < n) {
+    const float e = y[i] - t[i];
+    if (dy) dy[i] = 2.0f * e / (float)n;
+    e2 = (double)e * (double)e;
+  }
+  red[threadIdx.x] = e2;
+  __syncthreads();
+  for (int o = kThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(kThreads) k_mse_final(const double *__restrict__ part, int64_t np, int64_t n,
+                                                        double *__restrict__ loss) {
+  __shared__ double red[kThreads];
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < np; k += kThreads) s += part[k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = red[0] / (double)n;
+}
+
+// Adam (Kingma & Ba 2015) with bias correction, step >= 1
+__global__ void __launch_bounds__(kThreads) k_adam(float *__restrict__ w, const float *__restrict__ g,
+                                                   float *__restrict__ m, float *__restrict__ v, int64_t n, float lr,
+                                                   float b1, float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+hipError_t conv3d(const float *x, const float *w, const float *b, float *y, int cin, int cout, int D, int H, int W,
+                  hipStream_t s) {
+  const int64_t V = (int64_t)D * H * W;
+  if (V <= 0 || cout <= 0) return hipSuccess;
+  if (cout >= 16) {
+    hipLaunchKernelGGL(k_conv3d<16>, dim3(blocks_for(V), (unsigned)((cout + 15) / 16)), dim3(kThreads), 0, s, x, w,
+                       b, y, cin, cout, D, H, W);
+  } else if (cout >= 4) {
+    hipLaunchKernelGGL(k_conv3d<4>, dim3(blocks_for(V), (unsigned)((cout + 3) / 4)), dim3(kThreads), 0, s, x, w, b,
+                       y, cin, cout, D, H, W);
+  } else {
+    hipLaunchKernelGGL(k_conv3d<1>, dim3(blocks_for(V), (unsigned)cout), dim3(kThreads), 0, s, x, w, b, y, cin, cout,
+                       D, H, W);
+  }
+  return hipGetLastError();
+}
+
+hipError_t flip_weights(const float *w, float *wt, int cin, int cout, hipStream_t s) {
+  const int64_t n = (int64_t)cin * cout * kTaps;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_flip, dim3(blocks_for(n)), dim3(kThreads), 0, s, w, wt, cin, cout);
+  return hipGetLastError();
+}
+
+int64_t wgrad_chunks(int D, int H, int W) { return ((int64_t)D * H * W + kWgVox - 1) / kWgVox; }
+
+hipError_t conv3d_wgrad(const float *x, const float *dy, float *dw, float *db, float *part, int cin, int cout, int D,
+                        int H, int W, hipStream_t s) {
+  const int64_t chunks = wgrad_chunks(D, H, W);
+  if (chunks <= 0 || cout <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_wgrad_part, dim3((unsigned)chunks, (unsigned)cout), dim3(kThreads), 0, s, x, dy, part, cin,
+                     cout, D, H, W);
+  const int64_t n = (int64_t)cout * ((int64_t)cin * kTaps + 1);
+  hipLaunchKernelGGL(k_wgrad_sum, dim3(blocks_for(n)), dim3(kThreads), 0, s, part, dw, db, chunks, cin, cout);
+  return hipGetLastError();
+}
+
+hipError_t relu(const float *x, float *y, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_relu, dim3(blocks_for(n)), dim3(kThreads), 0, s, x, y, n);
+  return hipGetLastError();
+}
+
+hipError_t relu_bwd(const float *y, const float *dy, float *dx, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_relu_bwd, dim3(blocks_for(n)), dim3(kThreads), 0, s, y, dy, dx, n);
+  return hipGetLastError();
+}
+
+hipError_t pool(const float *x, float *y, int C, int D, int H, int W, hipStream_t s) {
+  const int64_t n = (int64_t)C * (D / 2) * (H / 2) * (W / 2);
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pool, dim3(blocks_for(n)), dim3(kThreads), 0, s, x, y, C, D, H, W);
+  return hipGetLastError();
+}
+
+hipError_t pool_bwd(const float *dy, float *dx, int C, int D, int H, int W, hipStream_t s) {
+  const int64_t n = (int64_t)C * D * H * W;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pool_bwd, dim3(blocks_for(n)), dim3(kThreads), 0, s, dy, dx, C, D, H, W);
+  return hipGetLastError();
+}
+
+hipError_t upsample(const float *x, float *y, int C, int d, int h, int w, hipStream_t s) {
+  const int64_t n = (int64_t)C * 8 * d * h * w;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_up, dim3(blocks_for(n)), dim3(kThreads), 0, s, x, y, C, d, h, w);
+  return hipGetLastError();
+}
+
+hipError_t upsample_bwd(const float *dy, float *dx, int C, int d, int h, int w, hipStream_t s) {
+  const int64_t n = (int64_t)C * d * h * w;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_up_bwd, dim3(blocks_for(n)), dim3(kThreads), 0, s, dy, dx, C, d, h, w);
+  return hipGetLastError();
+}
+
+hipError_t add(const float *a, const float *b, float *y, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add, dim3(blocks_for(n)), dim3(kThreads), 0, s, a, b, y, n);
+  return hipGetLastError();
+}
+
+int64_t mse_parts(int64_t n) { return (n + kThreads - 1) / kThreads; }
+
+hipError_t mse(const float *y, const float *t, float *dy, double *part, double *loss, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t np = mse_parts(n);
+  hipLaunchKernelGGL(k_mse, dim3((unsigned)np), dim3(kThreads), 0, s, y, t, dy, part, n);
+  hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(kThreads), 0, s, part, np, n, loss);
+  return hipGetLastError();
+}
+
+hipError_t adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
+                int step, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(kThreads), 0, s, w, g, m, v, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+}  // namespace cnn
+}  // namespace pct
