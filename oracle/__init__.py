@@ -14,6 +14,8 @@ The arithmetic lives in ``oracle.c`` (plain FP64 C):
                         as block size 1;
   * ``residual``     -- ||Ax - b||_2.
 ``roi_means`` is the ROI analysis of Sec. 3.2 / 4.2 (mean RSP per insert).
+``oracle.cnn`` (NumPy, FP64) holds the operations and gradients of the
+warm-start network that produces x0 (Sec. 2.1 leaves x0 open).
 
 Parity pins: see tests/test_oracle_*.py.  The full reconstructed image has no
 closed form; it is pinned only piecewise (path, traversal, solver), so the
