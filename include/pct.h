@@ -255,7 +255,8 @@ const char *pct_last_error(void);
  * sweeps) produced by the solver itself gives the initial guess x0 of the
  * sweeps (the paper leaves x0 to the user, Sec. 2.1); the plain sweeps from
  * the hull start stay the fallback.  Tensors are device float32 [C][D][H][W]
- * (W fastest), caller-owned; outputs must not alias inputs.  D*H*W < 2^31.
+ * (W fastest), caller-owned; outputs must not alias inputs, except that
+ * relu, relu_bwd, add and mask may run in place (output == an input).  D*H*W < 2^31.
  * Gradients are written, not accumulated.  Every call is asynchronous on
  * `stream` and returns PCT_EINVAL for NULL pointers or bad sizes. */
 
@@ -286,6 +287,8 @@ pct_status pct_cnn_upsample_bwd(const float *dy, float *dx, int32_t C, int32_t d
                                 void *stream);
 /* y = a + b (elementwise, n values) */
 pct_status pct_cnn_add(const float *a, const float *b, float *y, int64_t n, void *stream);
+/* y = x inside the mask (mask[i] != 0, uint8 [n]), 0 outside; may run in place */
+pct_status pct_cnn_mask(const float *x, const uint8_t *mask, float *y, int64_t n, void *stream);
 /* *loss (device double) = mean (y - t)^2 over n values (FP64 sums in fixed
  * order); dy = 2 (y - t) / n when dy != NULL; scratch: pct_cnn_mse_scratch(n)
  * doubles */

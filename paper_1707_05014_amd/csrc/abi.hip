@@ -919,6 +919,13 @@ pct_status pct_cnn_add(const float *a, const float *b, float *y, int64_t n, void
   return PCT_OK;
 }
 
+pct_status pct_cnn_mask(const float *x, const uint8_t *mask, float *y, int64_t n, void *stream) {
+  g_err.clear();
+  if (n < 0 || (n > 0 && (!x || !mask || !y))) return fail(PCT_EINVAL, "bad mask arguments");
+  HIPCHECK(pct::cnn::mask(x, mask, y, n, reinterpret_cast<hipStream_t>(stream)));
+  return PCT_OK;
+}
+
 int64_t pct_cnn_mse_scratch(int64_t n) { return n > 0 ? pct::cnn::mse_parts(n) : 0; }
 
 pct_status pct_cnn_mse(const float *y, const float *t, float *dy, double *scratch, double *loss, int64_t n,

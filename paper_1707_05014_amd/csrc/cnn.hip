@@ -183,14 +183,15 @@ __global__ void __launch_bounds__(kThreads) k_wgrad_sum(const float *__restrict_
     db[co] = s;
 }
 
-__global__ void __launch_bounds__(kThreads) k_relu(const float *__restrict__ x, float *__restrict__ y, int64_t n) {
+__global__ void __launch_bounds__(kThreads) k_relu(const float *x, float *y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i < n) y[i] = fmaxf(x[i], 0.0f);
 }
 
-// dx = dy where y > 0 (y = the ReLU output), else 0
-__global__ void __launch_bounds__(kThreads) k_relu_bwd(const float *__restrict__ y, const float *__restrict__ dy,
-                                                       float *__restrict__ dx, int64_t n) {
+// dx = dy where y > 0 (y = the ReLU output), else 0.  The elementwise kernels
+// read and write element i only, so they may run in place.
+__global__ void __launch_bounds__(kThreads) k_relu_bwd(const float *y, const float *dy, float *dx,
+                                                       int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i < n) dx[i] = y[i] > 0.0f ? dy[i] : 0.0f;
 }
@@ -257,10 +258,16 @@ __global__ void __launch_bounds__(kThreads) k_up_bwd(const float *__restrict__ d
   dx[i] = s;
 }
 
-__global__ void __launch_bounds__(kThreads) k_add(const float *__restrict__ a, const float *__restrict__ b,
-                                                  float *__restrict__ y, int64_t n) {
+__global__ void __launch_bounds__(kThreads) k_add(const float *a, const float *b, float *y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i < n) y[i] = a[i] + b[i];
+}
+
+// y = x where mask != 0, else 0 (restricts an image to the object's hull)
+__global__ void __launch_bounds__(kThreads) k_mask(const float *x, const uint8_t *__restrict__ mask, float *y,
+                                                   int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) y[i] = mask[i] ? x[i] : 0.0f;
 }
 
 // mean squared error: dy = 2 (y - t) / n, per-workgroup FP64 sums of (y - t)^2
@@ -393,6 +400,12 @@ hipError_t upsample_bwd(const float *dy, float *dx, int C, int d, int h, int w, 
 hipError_t add(const float *a, const float *b, float *y, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_add, dim3(blocks_for(n)), dim3(kThreads), 0, s, a, b, y, n);
+  return hipGetLastError();
+}
+
+hipError_t mask(const float *x, const uint8_t *m, float *y, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mask, dim3(blocks_for(n)), dim3(kThreads), 0, s, x, m, y, n);
   return hipGetLastError();
 }
 
