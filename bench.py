@@ -59,6 +59,17 @@ def parse():
     ap.add_argument("--skip-accuracy", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--max-sweeps-acc", type=int, default=30)
+    ap.add_argument("--warmstart", action="store_true",
+                    help="learned warm start: train the 3D U-Net on solver pairs of seeded phantoms, then compare "
+                         "the time to <= 1%% RSP error from the hull start and from the network's x0")
+    ap.add_argument("--ws-train", type=int, default=24, help="training phantoms (seeds 1000, 1001, ...)")
+    ap.add_argument("--ws-n", type=int, default=10_000_000, help="histories per phantom (training and evaluation)")
+    ap.add_argument("--ws-steps", type=int, default=600, help="Adam steps (one phantom per step)")
+    ap.add_argument("--ws-lr", type=float, default=1e-3)
+    ap.add_argument("--ws-variants", type=str, default="2:0",
+                    help="networks to compare: '<input sweeps joined by ->:<coarse-loss weight>', comma separated")
+    ap.add_argument("--ws-out", type=int, default=20, help="sweeps of the training target")
+    ap.add_argument("--ws-channels", type=str, default="16,32,64,64")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this benchmark and exit")
     return ap.parse_args()
@@ -158,6 +169,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built",
               file=sys.stderr)
         sys.exit(2)
+    if args.warmstart:
+        warmstart_experiment(args)
+        return
     import numpy as np
     import torch
 
@@ -370,6 +384,178 @@ def main():
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def warmstart_experiment(args):
+    """Time to <= 1% RSP error from the hull start and from the learned warm
+    start, on the held-out phantom of the 2e8-history workload (seed 3)
+    with --ws-n histories.  The network is trained first on pairs (images
+    after the input sweeps, image after --ws-out sweeps) of --ws-train seeded
+    phantoms reconstructed the same way (same history count, block size and
+    relaxation).  --ws-variants lists networks to train and compare, each as
+    "<input sweeps joined by '-'>:<coarse-loss weight>".  Prints one JSON line
+    (value: the first variant's time to <= 1%)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1707_05014_amd import _lib, api, cnn
+    from paper_1707_05014_amd import warmstart as wsm
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    _lib.load()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    N = args.ws_n
+    variants = []
+    for v in args.ws_variants.split(","):
+        ins, w = v.split(":")
+        variants.append((tuple(int(q) for q in ins.split("-")), float(w)))
+    snaps_needed = sorted({q for ins, _ in variants for q in ins} | {args.ws_out})
+    last_in = max(q for ins, _ in variants for q in ins)
+
+    def setup(cfg):
+        g = cfg.grid
+        b = cfg.phantom.body
+        t0 = time.time()
+        h = synth.generate(cfg)
+        gen_s = time.time() - t0
+        grid = api.make_grid(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.ox, g.oy, g.oz)
+        geom = api.make_geom(cfg.beam.u_in, cfg.beam.u_out, b.ax[0], b.ax[1], b.z0, b.z1, min(g.dx, g.dy, g.dz),
+                             synth.prior_poly(cfg.beam.E_kin))
+        H = api.Histories.from_numpy(h, device=dev)
+        del h
+        order = torch.from_numpy(synth.block_order(cfg.n, cfg.perm_seed)).to(dev)
+        mask = torch.from_numpy(synth.hull_mask(cfg)).to(dev)
+        params = api.sweep_params("drop", cfg.block, cfg.lam, 1, order=order, hull_mask=mask)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rows = api.mlp_trace(grid, geom, H)
+        plan = api.plan_build(grid, H, rows, params)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        return dict(grid=grid, H=H, rows=rows, plan=plan, params=params, mask=mask, gen_s=gen_s, setup_s=setup_s)
+
+    # ---- training pairs from the solver on seeded phantoms
+    train_snaps = []
+    t_data = time.time()
+    for i in range(args.ws_train):
+        cfg = synth.training_config(1000 + i, N)
+        S = setup(cfg)
+        x = S["mask"].to(torch.float32)
+        train_snaps.append(wsm.sweep_snapshots(S["grid"], S["plan"], x, S["params"], snaps_needed))
+        log(f"training phantom {i + 1}/{args.ws_train} (seed {1000 + i}): generated in {S['gen_s']:.1f} s")
+        grid_t = S["grid"]
+        del S, x
+    data_s = time.time() - t_data
+
+    channels = tuple(int(c) for c in args.ws_channels.split(","))
+    nets = []
+    for ins, wc in variants:
+        pairs = [(wsm.net_input(sn, ins, grid_t), wsm.volume(sn[args.ws_out], grid_t)) for sn in train_snaps]
+        net = cnn.UNet3D(channels, device=dev, seed=7, in_channels=len(ins))
+        losses, train_s = wsm.train(net, pairs, args.ws_steps, args.ws_lr, seed=11, coarse_weight=wc, log=log)
+        log(f"variant {ins}:{wc}: trained {args.ws_steps} steps in {train_s:.1f} s; loss {losses[0]:.3e} -> "
+            f"{np.mean(losses[-24:]):.3e}")
+        nets.append((ins, wc, net, losses, train_s))
+        del pairs
+    del train_snaps
+
+    # ---- evaluation on the held-out phantom
+    cfg = synth.config(5, n=N)
+    S = setup(cfg)
+    grid, plan, params, mask = S["grid"], S["plan"], S["params"], S["mask"]
+    labels = torch.from_numpy(synth.roi_labels(cfg)).to(dev)
+    true_rsp = synth.insert_rsp(cfg)
+    truth = torch.from_numpy(synth.truth_image(cfg)).to(dev)
+    inside = mask.bool()
+
+    def rsp_err(x):
+        sums, cnts = api.roi_stats(x, labels, len(true_rsp))
+        means = (sums / cnts.clamp(min=1)).cpu().numpy()
+        return float(np.max(np.abs(means - true_rsp) / true_rsp))
+
+    def rel_l2(x):
+        return float(torch.linalg.vector_norm((x - truth)[inside]) / torch.linalg.vector_norm(truth[inside]))
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    def sweeps_until(x, max_sweeps, t_start, errs):
+        t = t_start
+        for s in range(1, max_sweeps + 1):
+            _, dt = timed(lambda: api.plan_sweep(grid, plan, x, params))
+            t += dt
+            errs.append(rsp_err(x))
+            if errs[-1] <= 0.01:
+                return s, t
+        return None, None
+
+    # hull start, with the snapshots the networks read
+    x = mask.to(torch.float32)
+    e_h = []
+    snaps = {}
+    t = S["setup_s"]
+    hit_h = t_h = None
+    t_at = {}
+    for s_ in range(1, args.max_sweeps_acc + 1):
+        _, dt = timed(lambda: api.plan_sweep(grid, plan, x, params))
+        t += dt
+        t_at[s_] = t
+        e_h.append(rsp_err(x))
+        if s_ in snaps_needed:
+            snaps[s_] = x.clone()
+        if e_h[-1] <= 0.01 and hit_h is None:
+            hit_h, t_h = s_, t
+        if hit_h is not None and s_ >= last_in:
+            break
+    l2_h = rel_l2(x)
+    hull = {"sweeps_to_1pct": hit_h, "time_to_1pct_s": round(t_h, 4) if t_h else None,
+            "rsp_err_per_sweep": [round(e, 5) for e in e_h[: hit_h or len(e_h)]],
+            "rel_l2_after_sweeps": {k: round(rel_l2(v), 5) for k, v in snaps.items()}}
+    results = []
+    for ins, wc, net, losses, train_s in nets:
+        inp = wsm.net_input(snaps, ins, grid)
+        x0, t_net = timed(lambda: wsm.warm_start(net, inp, mask))
+        err_net = rsp_err(x0)
+        l2_net = rel_l2(x0)
+        t0 = t_at[max(ins)] + t_net
+        e_c = []
+        if err_net <= 0.01:
+            hit_c, t_c = 0, t0
+        else:
+            hit_c, t_c = sweeps_until(x0, args.max_sweeps_acc, t0, e_c)
+        results.append({
+            "inputs_after_sweeps": list(ins), "coarse_loss_weight": wc, "net_ms": round(t_net * 1e3, 3),
+            "rsp_err_of_net_output": round(err_net, 5), "rel_l2_of_net_output": round(l2_net, 5),
+            "sweeps_after_net_to_1pct": hit_c,
+            "total_sweeps": (max(ins) + hit_c) if hit_c is not None else None,
+            "time_to_1pct_s": round(t_c, 4) if t_c else None,
+            "speedup_vs_hull_start": round(t_h / t_c, 3) if (t_h and t_c) else None,
+            "rsp_err_per_sweep_after_net": [round(e, 5) for e in e_c],
+            "train_s": round(train_s, 1), "train_ms_per_step": round(train_s * 1e3 / max(args.ws_steps, 1), 2),
+            "loss_first": losses[0], "loss_last24_mean": float(np.mean(losses[-24:]))})
+        log(f"variant {ins}:{wc}: {results[-1]}")
+    first = results[0]
+    out = {
+        "metric": "time to <= 1% RSP error (learned warm start vs hull start)",
+        "value": first["time_to_1pct_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+        "speedup_vs_hull_start": first["speedup_vs_hull_start"],
+        "dtype": "f32", "data": "synthetic (seeded phantoms + Fermi-Eyges transport)",
+        "config": {"workload": f"held-out head phantom (seed 3), {N} histories, 200x200x40 voxels of 1 mm, "
+                               f"DROP blocks of {cfg.block}, lambda {cfg.lam}, rows cached (f32), tiled sweep plan",
+                   "network": {"channels": list(channels), "train_phantoms": args.ws_train,
+                               "train_steps": args.ws_steps, "lr": args.ws_lr, "target_sweeps": args.ws_out}},
+        "setup_s": round(S["setup_s"], 4), "training_data_s": round(data_s, 1),
+        "hull_start": hull, "warm_start": results,
     }
     print(json.dumps(out), flush=True)
 

@@ -287,6 +287,8 @@ pct_status pct_cnn_upsample_bwd(const float *dy, float *dx, int32_t C, int32_t d
                                 void *stream);
 /* y = a + b (elementwise, n values) */
 pct_status pct_cnn_add(const float *a, const float *b, float *y, int64_t n, void *stream);
+/* y += a * x (n values; x and y must not alias) */
+pct_status pct_cnn_axpy(float a, const float *x, float *y, int64_t n, void *stream);
 /* y = x inside the mask (mask[i] != 0, uint8 [n]), 0 outside; may run in place */
 pct_status pct_cnn_mask(const float *x, const uint8_t *mask, float *y, int64_t n, void *stream);
 /* *loss (device double) = mean (y - t)^2 over n values (FP64 sums in fixed

@@ -110,14 +110,14 @@ def adam(w, g, m, v, lr, b1, b2, eps, step):
 
 
 # ---------------------------------------------------------------- network
-def unet_layers(channels):
+def unet_layers(channels, in_ch=1):
     """Convolution shapes (cin, cout) in order: encoder levels 0..L-1 (two
     each; the second one of the deepest level maps back to channels[L-2]),
     then decoder levels L-2..0 (two each; the second one maps to the next
     shallower level's channels, at level 0 to 1 channel)."""
     L = len(channels)
     shapes = []
-    cin = 1
+    cin = in_ch
     for lvl, c in enumerate(channels):
         # the deepest level hands channels[L-2] features up to the decoder
         cout2 = channels[L - 2] if (lvl == L - 1 and L > 1) else c
@@ -130,20 +130,21 @@ def unet_layers(channels):
     return shapes
 
 
-def unet_init(channels, seed):
+def unet_init(channels, seed, in_ch=1):
     rng = np.random.default_rng(seed)
     params = []
-    for cin, cout in unet_layers(channels):
+    for cin, cout in unet_layers(channels, in_ch):
         std = np.sqrt(2.0 / (27 * cin))
         params.append((rng.normal(0, std, (cout, cin, 3, 3, 3)), np.zeros(cout)))
     return params
 
 
 def unet_forward(params, x, channels):
-    """x [1][D][H][W] -> (output, tape).  Encoder level l: conv, relu, conv,
-    relu (kept for the skip), pool to the next level.  Decoder level l (from
-    L-1 down to 1): upsample, add the level's encoder output, conv, relu, conv
-    (+ relu except at level 1).  Output = x + last conv."""
+    """x [in_ch][D][H][W] -> (output [1][D][H][W], tape).  Encoder level l:
+    conv, relu, conv, relu (kept for the skip), pool to the next level.
+    Decoder level l (from L-2 down to 0): upsample, add the level's encoder
+    output, conv, relu, conv (+ relu except at level 0).  Output = the last
+    input channel + last conv."""
     L = len(channels)
     tape = {}
     h = x
@@ -163,7 +164,7 @@ def unet_forward(params, x, channels):
         a2 = relu(z2) if lvl > 0 else z2
         tape[("dec", lvl)] = (s, a1, a2)
         h = a2
-    return x + h, tape
+    return x[-1:] + h, tape
 
 
 def unet_backward(params, x, channels, tape, dout):

@@ -74,7 +74,7 @@ EXPORTS = ("pct_workspace_size", "pct_mlp_trace", "pct_project_sweep", "pct_plan
            "pct_profile_read", "pct_last_error",
            "pct_cnn_conv3d", "pct_cnn_conv3d_bwd_data", "pct_cnn_wgrad_scratch", "pct_cnn_conv3d_bwd_weight",
            "pct_cnn_relu", "pct_cnn_relu_bwd", "pct_cnn_pool", "pct_cnn_pool_bwd", "pct_cnn_upsample",
-           "pct_cnn_upsample_bwd", "pct_cnn_add", "pct_cnn_mask", "pct_cnn_mse_scratch", "pct_cnn_mse", "pct_cnn_adam")
+           "pct_cnn_upsample_bwd", "pct_cnn_add", "pct_cnn_axpy", "pct_cnn_mask", "pct_cnn_mse_scratch", "pct_cnn_mse", "pct_cnn_adam")
 KERNEL_CLASSES = ("trace_path", "trace_compact", "project", "apply", "residual", "art", "other", "plan_dot",
                   "plan_rows", "plan_scatter", "plan_build")
 
@@ -142,6 +142,7 @@ def load(path: str | None = None):
         "pct_cnn_upsample_bwd": [_fp, _fp, i32, i32, i32, i32, _fp],
         "pct_cnn_add": [_fp, _fp, _fp, i64, _fp],
         "pct_cnn_mask": [_fp, _fp, _fp, i64, _fp],
+        "pct_cnn_axpy": [f32, _fp, _fp, i64, _fp],
         "pct_cnn_mse": [_fp, _fp, _fp, _fp, _fp, i64, _fp],
         "pct_cnn_adam": [_fp, _fp, _fp, _fp, i64, f32, f32, f32, f32, i32, _fp],
     }

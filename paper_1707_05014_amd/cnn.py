@@ -135,6 +135,14 @@ def add(a, b, y, stream=None):
     return y
 
 
+def axpy(a: float, x, y, stream=None):
+    """y += a * x."""
+    if x.numel() != y.numel():
+        raise ValueError("axpy: sizes differ")
+    check(_lib.load().pct_cnn_axpy(float(a), _dev(x, "x"), _dev(y, "y"), x.numel(), _s(stream)))
+    return y
+
+
 def mask(x, m, y, stream=None):
     """y = x inside the hull mask m (uint8, same size), 0 outside."""
     if not (x.numel() == m.numel() == y.numel()) or m.dtype != torch.uint8 or not (m.is_cuda and m.is_contiguous()):
@@ -172,11 +180,11 @@ def adam(w, g, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
 
 
 # ----------------------------------------------------------- network
-def layer_shapes(channels):
+def layer_shapes(channels, in_channels=1):
     """(cin, cout) of every convolution in execution order."""
     L = len(channels)
     out = []
-    prev = 1
+    prev = in_channels
     for l, c in enumerate(channels):
         last = channels[L - 2] if (l == L - 1 and L > 1) else c
         out.append((prev, c))
@@ -192,12 +200,13 @@ class UNet3D:
     """Parameters live in one flat float32 device buffer (weights then bias
     per layer), so gradients and the Adam moments are single buffers too."""
 
-    def __init__(self, channels=(16, 32, 64, 64), device="cuda", seed: int = 0):
+    def __init__(self, channels=(16, 32, 64, 64), device="cuda", seed: int = 0, in_channels: int = 1):
         self.channels = tuple(int(c) for c in channels)
-        if len(self.channels) < 2 or min(self.channels) < 1:
+        if len(self.channels) < 2 or min(self.channels) < 1 or in_channels < 1:
             raise ValueError("the network needs at least two levels of positive channel counts")
         self.L = len(self.channels)
-        self.shapes = layer_shapes(self.channels)
+        self.in_channels = int(in_channels)
+        self.shapes = layer_shapes(self.channels, self.in_channels)
         self.device = torch.device(device)
         sizes = []
         for cin, cout in self.shapes:
@@ -248,13 +257,14 @@ class UNet3D:
             bd.copy_(torch.as_tensor(np.asarray(b), dtype=torch.float32))
 
     def save(self, path: str):
-        np.savez(path, channels=np.array(self.channels), flat=self.flat.cpu().numpy(), m=self.m.cpu().numpy(),
-                 v=self.v.cpu().numpy(), step=np.array(self.step_count))
+        np.savez(path, channels=np.array(self.channels), in_channels=np.array(self.in_channels),
+                 flat=self.flat.cpu().numpy(), m=self.m.cpu().numpy(), v=self.v.cpu().numpy(),
+                 step=np.array(self.step_count))
 
     @classmethod
     def load(cls, path: str, device="cuda") -> "UNet3D":
         z = np.load(path)
-        net = cls(tuple(int(c) for c in z["channels"]), device=device)
+        net = cls(tuple(int(c) for c in z["channels"]), device=device, in_channels=int(z["in_channels"]))
         net.flat.copy_(torch.from_numpy(z["flat"]))
         net.m.copy_(torch.from_numpy(z["m"]))
         net.v.copy_(torch.from_numpy(z["v"]))
@@ -263,8 +273,8 @@ class UNet3D:
 
     # -- passes
     def _check_input(self, x):
-        if x.dim() != 4 or x.shape[0] != 1:
-            raise ValueError("input must be [1][D][H][W]")
+        if x.dim() != 4 or x.shape[0] != self.in_channels:
+            raise ValueError(f"input must be [{self.in_channels}][D][H][W]")
         f = 1 << (self.L - 1)
         if any(int(s) % f for s in x.shape[1:]):
             raise ValueError(f"D, H, W must be multiples of {f}")
@@ -274,7 +284,8 @@ class UNet3D:
         return torch.empty((c,) + tuple(dhw), dtype=torch.float32, device=self.device)
 
     def forward(self, x: torch.Tensor, keep: bool = False, stream=None) -> torch.Tensor:
-        """Output [1][D][H][W]; with keep=True the activations are kept for backward()."""
+        """Output [1][D][H][W] = last input channel + network; with keep=True
+        the activations are kept for backward()."""
         self._check_input(x)
         k = 0
         h = x
@@ -318,7 +329,7 @@ class UNet3D:
             k += 2
             h = z2
         out = self._empty(1, dims)
-        add(x, h, out, stream)
+        add(x[self.in_channels - 1:], h, out, stream)
         self._tape = (enc, dec) if keep else None
         return out
 
@@ -373,11 +384,32 @@ class UNet3D:
         assert k == 0
         return self.grad
 
-    def loss_and_grad(self, x, target, stream=None) -> torch.Tensor:
-        """Forward, MSE against target and backward; returns the loss (device float64 [1])."""
+    def loss_and_grad(self, x, target, coarse_weight: float = 0.0, stream=None) -> torch.Tensor:
+        """Forward, loss against target and backward; returns MSE(y, t)
+        (device float64 [1]).  The gradient is that of
+        MSE(y, t) + coarse_weight * MSE(P(y), P(t))
+        with P = two 2x2x2 average poolings (4x4x4 block means): the coarse
+        term weighs the slowly converging low-frequency part of the error,
+        which voxel noise in the target hides from the plain MSE."""
         y = self.forward(x, keep=True, stream=stream)
         dy = torch.empty_like(y)
         loss = mse(y, target, dy, stream=stream)
+        if coarse_weight > 0.0:
+            dims = [tuple(int(s) for s in y.shape[1:])]
+            for _ in range(2):
+                dims.append(tuple(d // 2 for d in dims[-1]))
+            if any(d % 4 for d in dims[0]):
+                raise ValueError("the coarse loss needs D, H, W divisible by 4")
+            yc, tc = y, target
+            for k in (1, 2):
+                yc = pool(yc, self._empty(1, dims[k]), stream)
+                tc = pool(tc, self._empty(1, dims[k]), stream)
+            gc = self._empty(1, dims[2])
+            mse(yc, tc, gc, stream=stream)
+            # d/dy of w * MSE(P(y), P(t)): the coarse gradient spread back by the pooling adjoints
+            g1 = pool_bwd(gc, self._empty(1, dims[1]), stream)
+            g0 = pool_bwd(g1, self._empty(1, dims[0]), stream)
+            axpy(float(coarse_weight), g0, dy, stream)
         self.backward(dy, stream)
         self._tape = None
         return loss
@@ -387,7 +419,7 @@ class UNet3D:
         adam(self.flat, self.grad, self.m, self.v, lr, self.step_count, beta1, beta2, eps, stream)
 
     def train_step(self, x, target, lr: float, stream=None) -> torch.Tensor:
-        loss = self.loss_and_grad(x, target, stream)
+        loss = self.loss_and_grad(x, target, stream=stream)
         self.adam_step(lr, stream=stream)
         return loss
 

@@ -919,6 +919,13 @@ pct_status pct_cnn_add(const float *a, const float *b, float *y, int64_t n, void
   return PCT_OK;
 }
 
+pct_status pct_cnn_axpy(float a, const float *x, float *y, int64_t n, void *stream) {
+  g_err.clear();
+  if (n < 0 || (n > 0 && (!x || !y))) return fail(PCT_EINVAL, "bad axpy arguments");
+  HIPCHECK(pct::cnn::axpy(a, x, y, n, reinterpret_cast<hipStream_t>(stream)));
+  return PCT_OK;
+}
+
 pct_status pct_cnn_mask(const float *x, const uint8_t *mask, float *y, int64_t n, void *stream) {
   g_err.clear();
   if (n < 0 || (n > 0 && (!x || !mask || !y))) return fail(PCT_EINVAL, "bad mask arguments");

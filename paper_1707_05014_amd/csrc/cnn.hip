@@ -95,13 +95,18 @@ __global__ void __launch_bounds__(kThreads) k_flip(const float *__restrict__ w, 
   wt[((int64_t)ci * cout + co) * kTaps + (kTaps - 1 - t)] = w[i];
 }
 
-// Weight and bias gradients, stage 1: workgroup g sums over its kWgVox voxels
-//   part[g][co][ci][t] = sum_p dy[co][p] x[ci][p + off(t)],  part[g][co][cin*27] = sum_p dy[co][p]
-// (grid: chunks x cout).  Each thread folds kWgVox / kThreads voxels in
-// registers, each wavefront adds its lanes with DPP prefix sums, and the
-// workgroup adds its wavefronts in order.
-constexpr int kWgVox = 2048;
+// Weight and bias gradients, stage 1: workgroup (tile g, channel block)
+// sums over the tile's voxels
+//   part[g][co][ci*27 + t] = sum_p dy[co][p] x[ci][p + off(t)],  part[g][co][cin*27] = sum_p dy[co][p]
+// A tile is 64 voxels along W (one per lane) x kTileY rows x kTileZ planes;
+// the four wavefronts take every fourth row, so row coordinates are
+// wave-uniform and only the W-neighbours' validity varies per lane.  Each
+// lane folds its rows into kWgCob x 27 register accumulators per input
+// channel; each wavefront then adds its lanes with DPP prefix sums and the
+// workgroup adds its wavefronts in order (fixed summation order throughout).
 constexpr int kWaves = kThreads / 64;
+constexpr int kWgCob = 4;
+constexpr int kTileY = 16, kTileZ = 16;
 
 __device__ __forceinline__ float wave_total(float v) {
   const float s = wave_incl_scan_dpp(v);
@@ -110,59 +115,78 @@ __device__ __forceinline__ float wave_total(float v) {
 
 __global__ void __launch_bounds__(kThreads) k_wgrad_part(const float *__restrict__ x, const float *__restrict__ dy,
                                                          float *__restrict__ part, int cin, int cout, int D, int H,
-                                                         int W) {
-  __shared__ float red[kWaves][kTaps + 1];
-  const Vol v = make_vol(D, H, W);
-  const int co = blockIdx.y;
-  const int64_t g = blockIdx.x;
-  const int wid = threadIdx.x / 64, lane = threadIdx.x % 64;
-  constexpr int kPer = kWgVox / kThreads;
-  float gv[kPer];
-  int32_t pv[kPer];
-  uint32_t mv[kPer];
-  float gsum = 0.0f;
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const int64_t p = g * kWgVox + (int64_t)k * kThreads + threadIdx.x;
-    const bool live = p < v.V;
-    pv[k] = live ? (int32_t)p : 0;
-    gv[k] = live ? dy[(int64_t)co * v.V + p] : 0.0f;
-    const int xq = pv[k] % W, yq = (pv[k] / W) % H, zq = pv[k] / (W * H);
-    mv[k] = live ? tap_mask(v, zq, yq, xq) : 0u;
-    gsum += gv[k];
-  }
+                                                         int W, int tiles_x, int tiles_y) {
+  __shared__ float red[kWaves][kWgCob][kTaps + 1];
+  const int tile = blockIdx.x;
+  const int txi = tile % tiles_x, tyi = (tile / tiles_x) % tiles_y, tzi = tile / (tiles_x * tiles_y);
+  const int co0 = blockIdx.y * kWgCob;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int xq = txi * 64 + lane;
+  const bool xin = xq < W;
+  const int xc = xin ? xq : W - 1;  // lanes past the edge read a valid voxel and use 0
+  const bool xm = xin && xq >= 1, xp = xin && xq + 1 < W;
+  const int y0 = tyi * kTileY, z0 = tzi * kTileZ;
+  const int ny = min(kTileY, H - y0), nz = min(kTileZ, D - z0);
+  const int nrows = ny * nz;
+  const int64_t V = (int64_t)D * H * W;
   const int64_t stride = (int64_t)cin * kTaps + 1;
-  float *out = part + (g * cout + co) * stride;
+  float gsum[kWgCob];
+#pragma unroll
+  for (int c = 0; c < kWgCob; ++c) gsum[c] = 0.0f;
   for (int ci = 0; ci < cin; ++ci) {
-    const float *xc = x + (int64_t)ci * v.V;
+    const float *xch = x + (int64_t)ci * V;
+    float acc[kWgCob][kTaps];
 #pragma unroll
-    for (int t = 0; t < kTaps; ++t) {
-      const int64_t off = tap_offset(v, t);
-      float a = 0.0f;
+    for (int c = 0; c < kWgCob; ++c)
 #pragma unroll
-      for (int k = 0; k < kPer; ++k) {
-        // taps outside the volume read the centre voxel (always in bounds) and use 0
-        const bool in = (mv[k] >> t) & 1u;
-        const float xv = xc[in ? pv[k] + off : pv[k]];
-        a = fmaf(gv[k], in ? xv : 0.0f, a);
+      for (int t = 0; t < kTaps; ++t) acc[c][t] = 0.0f;
+    for (int r = wid; r < nrows; r += kWaves) {
+      const int zz = z0 + r / ny, yy = y0 + r % ny;  // wave-uniform
+      const int64_t p = ((int64_t)zz * H + yy) * W + xc;
+      float g[kWgCob];
+#pragma unroll
+      for (int c = 0; c < kWgCob; ++c) {
+        const float gv = (co0 + c < cout) ? dy[(int64_t)(co0 + c) * V + p] : 0.0f;
+        g[c] = xin ? gv : 0.0f;
+        if (ci == 0) gsum[c] += g[c];
       }
-      const float sw = wave_total(a);
-      if (lane == 0) red[wid][t] = sw;
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        const int dz = a / 3 - 1, dyy = a % 3 - 1;
+        const bool rowin = zz + dz >= 0 && zz + dz < D && yy + dyy >= 0 && yy + dyy < H;  // wave-uniform
+        if (!rowin) continue;
+        const float *row = xch + p + ((int64_t)dz * H + dyy) * W;
+        const float vm = row[xm ? -1 : 0], v0 = row[0], vp = row[xp ? 1 : 0];
+        const float xv[3] = {xm ? vm : 0.0f, v0, xp ? vp : 0.0f};
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+          for (int c = 0; c < kWgCob; ++c) acc[c][a * 3 + b] = fmaf(g[c], xv[b], acc[c][a * 3 + b]);
+      }
     }
+#pragma unroll
+    for (int c = 0; c < kWgCob; ++c)
+#pragma unroll
+      for (int t = 0; t < kTaps; ++t) {
+        const float sw = wave_total(acc[c][t]);
+        if (lane == 0) red[wid][c][t] = sw;
+      }
     if (ci == 0) {
-      const float sg = wave_total(gsum);
-      if (lane == 0) red[wid][kTaps] = sg;
+#pragma unroll
+      for (int c = 0; c < kWgCob; ++c) {
+        const float sg = wave_total(gsum[c]);
+        if (lane == 0) red[wid][c][kTaps] = sg;
+      }
     }
     __syncthreads();
-    if ((int)threadIdx.x < kTaps) {
-      float s = 0.0f;
-      for (int w2 = 0; w2 < kWaves; ++w2) s += red[w2][threadIdx.x];
-      out[(int64_t)ci * kTaps + threadIdx.x] = s;
-    }
-    if (ci == 0 && threadIdx.x == kTaps) {
-      float s = 0.0f;
-      for (int w2 = 0; w2 < kWaves; ++w2) s += red[w2][kTaps];
-      out[(int64_t)cin * kTaps] = s;
+    if ((int)threadIdx.x < kWgCob * (kTaps + 1)) {
+      const int c = threadIdx.x / (kTaps + 1), t = threadIdx.x % (kTaps + 1);
+      if (co0 + c < cout && (t < kTaps || ci == 0)) {
+        float sum = 0.0f;
+        for (int w2 = 0; w2 < kWaves; ++w2) sum += red[w2][c][t];
+        float *out = part + ((int64_t)tile * cout + co0 + c) * stride;
+        out[t < kTaps ? (int64_t)ci * kTaps + t : (int64_t)cin * kTaps] = sum;
+      }
     }
     __syncthreads();
   }
@@ -263,6 +287,13 @@ __global__ void __launch_bounds__(kThreads) k_add(const float *a, const float *b
   if (i < n) y[i] = a[i] + b[i];
 }
 
+// y += a x
+__global__ void __launch_bounds__(kThreads) k_axpy(float a, const float *__restrict__ x, float *__restrict__ y,
+                                                   int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) y[i] = fmaf(a, x[i], y[i]);
+}
+
 // y = x where mask != 0, else 0 (restricts an image to the object's hull)
 __global__ void __launch_bounds__(kThreads) k_mask(const float *x, const uint8_t *__restrict__ mask, float *y,
                                                    int64_t n) {
@@ -344,14 +375,19 @@ hipError_t flip_weights(const float *w, float *wt, int cin, int cout, hipStream_
   return hipGetLastError();
 }
 
-int64_t wgrad_chunks(int D, int H, int W) { return ((int64_t)D * H * W + kWgVox - 1) / kWgVox; }
+static inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+int64_t wgrad_chunks(int D, int H, int W) {
+  return (int64_t)ceil_div(W, 64) * ceil_div(H, kTileY) * ceil_div(D, kTileZ);
+}
 
 hipError_t conv3d_wgrad(const float *x, const float *dy, float *dw, float *db, float *part, int cin, int cout, int D,
                         int H, int W, hipStream_t s) {
   const int64_t chunks = wgrad_chunks(D, H, W);
   if (chunks <= 0 || cout <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_wgrad_part, dim3((unsigned)chunks, (unsigned)cout), dim3(kThreads), 0, s, x, dy, part, cin,
-                     cout, D, H, W);
+  const int tx = ceil_div(W, 64), ty = ceil_div(H, kTileY);
+  hipLaunchKernelGGL(k_wgrad_part, dim3((unsigned)chunks, (unsigned)ceil_div(cout, kWgCob)), dim3(kThreads), 0, s, x,
+                     dy, part, cin, cout, D, H, W, tx, ty);
   const int64_t n = (int64_t)cout * ((int64_t)cin * kTaps + 1);
   hipLaunchKernelGGL(k_wgrad_sum, dim3(blocks_for(n)), dim3(kThreads), 0, s, part, dw, db, chunks, cin, cout);
   return hipGetLastError();
@@ -400,6 +436,12 @@ hipError_t upsample_bwd(const float *dy, float *dx, int C, int d, int h, int w, 
 hipError_t add(const float *a, const float *b, float *y, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_add, dim3(blocks_for(n)), dim3(kThreads), 0, s, a, b, y, n);
+  return hipGetLastError();
+}
+
+hipError_t axpy(float a, const float *x, float *y, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpy, dim3(blocks_for(n)), dim3(kThreads), 0, s, a, x, y, n);
   return hipGetLastError();
 }
 

@@ -20,6 +20,7 @@ hipError_t pool_bwd(const float *dy, float *dx, int C, int D, int H, int W, hipS
 hipError_t upsample(const float *x, float *y, int C, int d, int h, int w, hipStream_t s);
 hipError_t upsample_bwd(const float *dy, float *dx, int C, int d, int h, int w, hipStream_t s);
 hipError_t add(const float *a, const float *b, float *y, int64_t n, hipStream_t s);
+hipError_t axpy(float a, const float *x, float *y, int64_t n, hipStream_t s);
 hipError_t mask(const float *x, const uint8_t *m, float *y, int64_t n, hipStream_t s);
 int64_t mse_parts(int64_t n);
 hipError_t mse(const float *y, const float *t, float *dy, double *part, double *loss, int64_t n, hipStream_t s);

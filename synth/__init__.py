@@ -287,6 +287,17 @@ def config(key: int, n: int | None = None) -> Config:
     return c
 
 
+def training_config(phantom_seed: int, n: int, block: int = 200_000, lam: float = 0.5) -> Config:
+    """A head phantom of the config-2/3 family with its own seed (phantom and
+    histories both seeded by phantom_seed), for the warm-start network's
+    training pairs: same grid, beam, block size and relaxation as the
+    workload it is evaluated on, so that its inputs look alike."""
+    g = Grid(200, 200, 40, 1.0, 1.0, 1.0, -100.0, -100.0, -20.0)
+    return Config(5, f"head-train-{phantom_seed}", g, _phantom_head(phantom_seed),
+                  Beam(180, 125.0, 25.0, 5e-3, -150.0, 150.0, step=2.0), int(n), seed=phantom_seed,
+                  perm_seed=phantom_seed + 100_000, algo="drop", sweeps=20, block=block, lam=lam, rows="f32")
+
+
 # ----------------------------------------------------------------- generation
 def _params_c(cfg: Config) -> _Params:
     b = cfg.beam

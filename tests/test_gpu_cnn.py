@@ -10,9 +10,9 @@ Tolerances (FP32 storage and accumulation against FP64):
   normwise <= 1e-4 (fourteen layers of FP32 rounding composed, and ReLU
   decisions on activations within rounding of zero may differ).
 Shapes are ragged on purpose: voxel counts that are not multiples of the
-256-thread workgroup or of the 2048-voxel weight-gradient chunk, output
-channel counts that leave partial channel blocks (1, 6, 17), and a volume one
-voxel thick.
+256-thread workgroup, extents that leave partial weight-gradient tiles
+(64 voxels along W x 16 rows x 16 planes), output channel counts that leave
+partial channel blocks (1, 6, 17), and a volume one voxel thick.
 """
 import sys
 
@@ -56,7 +56,7 @@ def _check(got, ref, absref=None, tol=NORM_TOL, what=""):
         assert not bad.any(), f"{what}: {bad.sum()} elements outside the elementwise bound"
 
 
-SHAPES = [(3, 1, 5, 7, 9), (3, 6, 17, 19, 13), (2, 17, 1, 9, 33), (16, 16, 8, 40, 40)]
+SHAPES = [(3, 1, 5, 7, 9), (3, 6, 17, 19, 13), (2, 17, 1, 9, 33), (16, 16, 8, 40, 40), (2, 5, 3, 18, 70)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -117,6 +117,8 @@ def test_elementwise_ops():
     relu_out = _f32(oc.relu(a))
     assert np.array_equal(_host(cnn.relu_bwd(_dev(relu_out), tb, dx)), oc.relu_bwd(relu_out, b))
     assert np.array_equal(_host(cnn.add(ta, tb, y)), _f32(a + b))
+    z = ta.clone()
+    _check(_host(cnn.axpy(-0.37, tb, z)), a + float(np.float32(-0.37)) * b, what="axpy")
     m = (r.random(n) < 0.4).astype(np.uint8)
     assert np.array_equal(_host(cnn.mask(ta, torch.from_numpy(m).cuda(), y)), np.where(m != 0, a, 0.0))
     # in place
@@ -164,16 +166,17 @@ def test_mse_and_adam():
     _check(_host(tw) - w, rw - w, tol=1e-4, what="adam w")
 
 
-@pytest.mark.parametrize("channels,dims", [([4, 8, 8], (8, 12, 16)), ([16, 32, 64, 64], (8, 16, 24))])
-def test_network_forward_backward(channels, dims):
-    _say(f"network {channels} on {dims}")
-    net = cnn.UNet3D(channels, seed=0)
-    params = oc.unet_init(channels, seed=21)
+@pytest.mark.parametrize("channels,dims,in_ch", [([4, 8, 8], (8, 12, 16), 1), ([16, 32, 64, 64], (8, 16, 24), 1),
+                                                 ([4, 8, 8], (4, 12, 72), 2)])
+def test_network_forward_backward(channels, dims, in_ch):
+    _say(f"network {channels} on {dims}, {in_ch} input channels")
+    net = cnn.UNet3D(channels, seed=0, in_channels=in_ch)
+    params = oc.unet_init(channels, seed=21, in_ch=in_ch)
     r = np.random.default_rng(22)
     params = [(_f32(w), _f32(r.normal(0, 0.05, size=b.shape))) for w, b in params]
     net.load_params(params)
-    x = _f32(r.uniform(0.0, 1.8, size=(1,) + dims))
-    t = _f32(x + r.normal(0, 0.1, size=x.shape))
+    x = _f32(r.uniform(0.0, 1.8, size=(in_ch,) + dims))
+    t = _f32(x[-1:] + r.normal(0, 0.1, size=(1,) + dims))
     y_ref, tape = oc.unet_forward(params, x, channels)
     y = net.forward(_dev(x), keep=True)
     _check(_host(y), y_ref, what="network output")
@@ -199,3 +202,27 @@ def test_training_reduces_loss():
         net.train_step(xs[step % 4], ts[step % 4], lr=3e-3)
     last = [float(net.loss_and_grad(xx, tt).item()) for xx, tt in zip(xs, ts)]
     assert np.mean(last) < 0.5 * np.mean(first), (first, last)
+
+
+def test_coarse_loss_gradient():
+    """The coarse term's gradient (two poolings, MSE, two pooling adjoints,
+    axpy) against the oracle composition of the same definitions."""
+    _say("coarse loss gradient")
+    r = np.random.default_rng(24)
+    channels, dims = [4, 8], (8, 8, 12)
+    net = cnn.UNet3D(channels, seed=0)
+    params = oc.unet_init(channels, seed=25)
+    params = [(_f32(w), _f32(r.normal(0, 0.05, size=b.shape))) for w, b in params]
+    net.load_params(params)
+    x = _f32(r.uniform(0.0, 1.8, size=(1,) + dims))
+    t = _f32(x + r.normal(0, 0.1, size=x.shape))
+    wc = 3.0
+    y_ref, tape = oc.unet_forward(params, x, channels)
+    _, g = oc.mse(y_ref, t)
+    _, gc = oc.mse(oc.pool(oc.pool(y_ref)), oc.pool(oc.pool(t)))
+    g = g + wc * oc.pool_bwd(oc.pool_bwd(gc))
+    grads = oc.unet_backward(params, x, channels, tape, g)
+    net.loss_and_grad(_dev(x), _dev(t), coarse_weight=wc)
+    for k, ((dw, db), gw, gb) in enumerate(zip(grads, net.dw, net.db)):
+        _check(_host(gw), dw, tol=NET_GRAD_TOL, what=f"layer {k} dw")
+        _check(_host(gb), db, tol=NET_GRAD_TOL, what=f"layer {k} db")

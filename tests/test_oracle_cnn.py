@@ -129,6 +129,7 @@ def test_unet_layer_shapes():
     assert oc.unet_layers([16, 32, 64, 64]) == [(1, 16), (16, 16), (16, 32), (32, 32), (32, 64), (64, 64),
                                                 (64, 64), (64, 64), (64, 64), (64, 32), (32, 32), (32, 16),
                                                 (16, 16), (16, 1)]
+    assert oc.unet_layers([4, 8], in_ch=2) == [(2, 4), (4, 4), (4, 8), (8, 4), (4, 4), (4, 1)]
 
 
 def _loss(params, x, t, ch):
@@ -136,16 +137,16 @@ def _loss(params, x, t, ch):
     return oc.mse(y, t)[0]
 
 
-@pytest.mark.parametrize("ch", [[2, 3], [2, 3, 4, 4]])
-def test_unet_gradients_finite_difference(ch):
+@pytest.mark.parametrize("ch,in_ch", [([2, 3], 1), ([2, 3, 4, 4], 1), ([2, 3, 3], 2)])
+def test_unet_gradients_finite_difference(ch, in_ch):
     """Analytic gradients of the whole network against central differences
     (h = 1e-6), relative error <= 1e-6 on every checked component."""
     r = _rng(8)
-    params = oc.unet_init(ch, seed=9)
+    params = oc.unet_init(ch, seed=9, in_ch=in_ch)
     # non-zero biases so that every bias gradient path is exercised
     params = [(w, r.normal(0, 0.1, size=b.shape)) for w, b in params]
-    x = r.uniform(0.0, 1.5, size=(1, 8, 8, 8))
-    t = x + r.normal(0, 0.1, size=x.shape)
+    x = r.uniform(0.0, 1.5, size=(in_ch, 8, 8, 8))
+    t = x[-1:] + r.normal(0, 0.1, size=(1,) + x.shape[1:])
     y, tape = oc.unet_forward(params, x, ch)
     _, dy = oc.mse(y, t)
     grads = oc.unet_backward(params, x, ch, tape, dy)
