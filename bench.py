@@ -64,12 +64,15 @@ def parse():
                          "the time to <= 1%% RSP error from the hull start and from the network's x0")
     ap.add_argument("--ws-train", type=int, default=24, help="training phantoms (seeds 1000, 1001, ...)")
     ap.add_argument("--ws-n", type=int, default=10_000_000, help="histories per phantom (training and evaluation)")
-    ap.add_argument("--ws-steps", type=int, default=600, help="Adam steps (one phantom per step)")
+    ap.add_argument("--ws-steps", type=int, default=2000, help="Adam steps (one phantom per step)")
     ap.add_argument("--ws-lr", type=float, default=1e-3)
-    ap.add_argument("--ws-variants", type=str, default="2:0",
-                    help="networks to compare: '<input sweeps joined by ->:<coarse-loss weight>', comma separated")
+    ap.add_argument("--ws-variants", type=str, default="1:0:truth,2:0:truth,2:0:out",
+                    help="networks to compare, comma separated: '<input sweeps joined by ->:<coarse-loss weight>"
+                         "[:out|truth]' (target: the image after --ws-out sweeps, or the phantom itself)")
     ap.add_argument("--ws-out", type=int, default=20, help="sweeps of the training target")
     ap.add_argument("--ws-channels", type=str, default="16,32,64,64")
+    ap.add_argument("--ws-eval-seeds", type=str, default="3,2,5000,5001,5002,5003",
+                    help="held-out phantoms (3: the 2e8 workload's phantom, 2: the 1e7 workload's)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this benchmark and exit")
     return ap.parse_args()
@@ -413,10 +416,11 @@ def warmstart_experiment(args):
     N = args.ws_n
     variants = []
     for v in args.ws_variants.split(","):
-        ins, w = v.split(":")
-        variants.append((tuple(int(q) for q in ins.split("-")), float(w)))
-    snaps_needed = sorted({q for ins, _ in variants for q in ins} | {args.ws_out})
-    last_in = max(q for ins, _ in variants for q in ins)
+        f = v.split(":")
+        variants.append((tuple(int(q) for q in f[0].split("-")), float(f[1]), f[2] if len(f) > 2 else "out"))
+    snaps_needed = sorted({q for ins, _, _ in variants for q in ins} | {args.ws_out})
+    last_in = max(q for ins, _, _ in variants for q in ins)
+    want_truth = any(tg == "truth" for _, _, tg in variants)
 
     def setup(cfg):
         g = cfg.grid
@@ -448,40 +452,32 @@ def warmstart_experiment(args):
         S = setup(cfg)
         x = S["mask"].to(torch.float32)
         train_snaps.append(wsm.sweep_snapshots(S["grid"], S["plan"], x, S["params"], snaps_needed))
+        if want_truth:
+            train_snaps[-1]["truth"] = torch.from_numpy(synth.truth_image(cfg)).to(dev)
         log(f"training phantom {i + 1}/{args.ws_train} (seed {1000 + i}): generated in {S['gen_s']:.1f} s")
         grid_t = S["grid"]
         del S, x
     data_s = time.time() - t_data
 
     channels = tuple(int(c) for c in args.ws_channels.split(","))
+    def mean_loss(net, pairs):
+        return float(np.mean([float(net.loss_and_grad(a, b).item()) for a, b in pairs]))
+
     nets = []
-    for ins, wc in variants:
-        pairs = [(wsm.net_input(sn, ins, grid_t), wsm.volume(sn[args.ws_out], grid_t)) for sn in train_snaps]
+    for ins, wc, tg in variants:
+        pairs = [(wsm.net_input(sn, ins, grid_t), wsm.volume(sn[args.ws_out if tg == "out" else "truth"], grid_t))
+                 for sn in train_snaps]
         net = cnn.UNet3D(channels, device=dev, seed=7, in_channels=len(ins))
+        loss0 = mean_loss(net, pairs)  # the untrained network is the identity on its last input
         losses, train_s = wsm.train(net, pairs, args.ws_steps, args.ws_lr, seed=11, coarse_weight=wc, log=log)
-        log(f"variant {ins}:{wc}: trained {args.ws_steps} steps in {train_s:.1f} s; loss {losses[0]:.3e} -> "
-            f"{np.mean(losses[-24:]):.3e}")
-        nets.append((ins, wc, net, losses, train_s))
+        loss1 = mean_loss(net, pairs)
+        log(f"variant {ins}:{wc}:{tg}: trained {args.ws_steps} steps in {train_s:.1f} s; mean training loss "
+            f"{loss0:.4e} (identity) -> {loss1:.4e}")
+        nets.append((ins, wc, tg, net, (loss0, loss1), train_s))
         del pairs
     del train_snaps
 
-    # ---- evaluation on the held-out phantom
-    cfg = synth.config(5, n=N)
-    S = setup(cfg)
-    grid, plan, params, mask = S["grid"], S["plan"], S["params"], S["mask"]
-    labels = torch.from_numpy(synth.roi_labels(cfg)).to(dev)
-    true_rsp = synth.insert_rsp(cfg)
-    truth = torch.from_numpy(synth.truth_image(cfg)).to(dev)
-    inside = mask.bool()
-
-    def rsp_err(x):
-        sums, cnts = api.roi_stats(x, labels, len(true_rsp))
-        means = (sums / cnts.clamp(min=1)).cpu().numpy()
-        return float(np.max(np.abs(means - true_rsp) / true_rsp))
-
-    def rel_l2(x):
-        return float(torch.linalg.vector_norm((x - truth)[inside]) / torch.linalg.vector_norm(truth[inside]))
-
+    # ---- evaluation on held-out phantoms (the first one: the 2e8 workload's phantom, seed 3)
     def timed(fn):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -489,73 +485,113 @@ def warmstart_experiment(args):
         torch.cuda.synchronize()
         return out, time.perf_counter() - t0
 
-    def sweeps_until(x, max_sweeps, t_start, errs):
-        t = t_start
-        for s in range(1, max_sweeps + 1):
+    def evaluate(cfg):
+        S = setup(cfg)
+        grid, plan, params, mask = S["grid"], S["plan"], S["params"], S["mask"]
+        labels = torch.from_numpy(synth.roi_labels(cfg)).to(dev)
+        true_rsp = synth.insert_rsp(cfg)
+        truth = torch.from_numpy(synth.truth_image(cfg)).to(dev)
+        inside = mask.bool()
+
+        def rsp_err(x):
+            sums, cnts = api.roi_stats(x, labels, len(true_rsp))
+            means = (sums / cnts.clamp(min=1)).cpu().numpy()
+            return float(np.max(np.abs(means - true_rsp) / true_rsp))
+
+        def rel_l2(x):
+            return float(torch.linalg.vector_norm((x - truth)[inside]) / torch.linalg.vector_norm(truth[inside]))
+
+        def sweeps_until(x, max_sweeps, t_start, errs):
+            t = t_start
+            for s in range(1, max_sweeps + 1):
+                _, dt = timed(lambda: api.plan_sweep(grid, plan, x, params))
+                t += dt
+                errs.append(rsp_err(x))
+                if errs[-1] <= 0.01:
+                    return s, t
+            return None, None
+
+        # hull start, keeping the snapshots the networks read
+        x = mask.to(torch.float32)
+        e_h = []
+        snaps = {}
+        t = S["setup_s"]
+        hit_h = t_h = None
+        t_at = {}
+        for s_ in range(1, max(args.max_sweeps_acc, args.ws_out) + 1):
             _, dt = timed(lambda: api.plan_sweep(grid, plan, x, params))
             t += dt
-            errs.append(rsp_err(x))
-            if errs[-1] <= 0.01:
-                return s, t
-        return None, None
+            t_at[s_] = t
+            e_h.append(rsp_err(x))
+            if s_ in snaps_needed:
+                snaps[s_] = x.clone()
+            if e_h[-1] <= 0.01 and hit_h is None:
+                hit_h, t_h = s_, t
+            if hit_h is not None and s_ >= max(last_in, args.ws_out):
+                break
+        hull = {"sweeps_to_1pct": hit_h, "time_to_1pct_s": round(t_h, 4) if t_h else None,
+                "rsp_err_per_sweep": [round(e, 5) for e in e_h],
+                "rel_l2_after_sweeps": {k: round(rel_l2(v), 5) for k, v in snaps.items()}}
+        res = []
+        for ins, wc, tg, net, _, _ in nets:
+            inp = wsm.net_input(snaps, ins, grid)
+            x0, t_net = timed(lambda: wsm.warm_start(net, inp, mask))
+            err_net = rsp_err(x0)
+            l2_net = rel_l2(x0)
+            t0 = t_at[max(ins)] + t_net
+            e_c = []
+            if err_net <= 0.01:
+                hit_c, t_c = 0, t0
+            else:
+                hit_c, t_c = sweeps_until(x0, args.max_sweeps_acc, t0, e_c)
+            res.append({"net_ms": round(t_net * 1e3, 3), "rsp_err_of_net_output": round(err_net, 5),
+                        "rel_l2_of_net_output": round(l2_net, 5), "sweeps_after_net_to_1pct": hit_c,
+                        "total_sweeps": (max(ins) + hit_c) if hit_c is not None else None,
+                        "time_to_1pct_s": round(t_c, 4) if t_c else None,
+                        "rsp_err_per_sweep_after_net": [round(e, 5) for e in e_c]})
+        del S
+        return hull, res
 
-    # hull start, with the snapshots the networks read
-    x = mask.to(torch.float32)
-    e_h = []
-    snaps = {}
-    t = S["setup_s"]
-    hit_h = t_h = None
-    t_at = {}
-    for s_ in range(1, args.max_sweeps_acc + 1):
-        _, dt = timed(lambda: api.plan_sweep(grid, plan, x, params))
-        t += dt
-        t_at[s_] = t
-        e_h.append(rsp_err(x))
-        if s_ in snaps_needed:
-            snaps[s_] = x.clone()
-        if e_h[-1] <= 0.01 and hit_h is None:
-            hit_h, t_h = s_, t
-        if hit_h is not None and s_ >= last_in:
-            break
-    l2_h = rel_l2(x)
-    hull = {"sweeps_to_1pct": hit_h, "time_to_1pct_s": round(t_h, 4) if t_h else None,
-            "rsp_err_per_sweep": [round(e, 5) for e in e_h[: hit_h or len(e_h)]],
-            "rel_l2_after_sweeps": {k: round(rel_l2(v), 5) for k, v in snaps.items()}}
-    results = []
-    for ins, wc, net, losses, train_s in nets:
-        inp = wsm.net_input(snaps, ins, grid)
-        x0, t_net = timed(lambda: wsm.warm_start(net, inp, mask))
-        err_net = rsp_err(x0)
-        l2_net = rel_l2(x0)
-        t0 = t_at[max(ins)] + t_net
-        e_c = []
-        if err_net <= 0.01:
-            hit_c, t_c = 0, t0
-        else:
-            hit_c, t_c = sweeps_until(x0, args.max_sweeps_acc, t0, e_c)
-        results.append({
-            "inputs_after_sweeps": list(ins), "coarse_loss_weight": wc, "net_ms": round(t_net * 1e3, 3),
-            "rsp_err_of_net_output": round(err_net, 5), "rel_l2_of_net_output": round(l2_net, 5),
-            "sweeps_after_net_to_1pct": hit_c,
-            "total_sweeps": (max(ins) + hit_c) if hit_c is not None else None,
-            "time_to_1pct_s": round(t_c, 4) if t_c else None,
-            "speedup_vs_hull_start": round(t_h / t_c, 3) if (t_h and t_c) else None,
-            "rsp_err_per_sweep_after_net": [round(e, 5) for e in e_c],
-            "train_s": round(train_s, 1), "train_ms_per_step": round(train_s * 1e3 / max(args.ws_steps, 1), 2),
-            "loss_first": losses[0], "loss_last24_mean": float(np.mean(losses[-24:]))})
-        log(f"variant {ins}:{wc}: {results[-1]}")
-    first = results[0]
+    eval_seeds = [int(q) for q in args.ws_eval_seeds.split(",")]
+    per_phantom = []
+    for k, seed in enumerate(eval_seeds):
+        cfg = synth.config(5, n=N) if seed == 3 else synth.training_config(seed, N)
+        hull, res = evaluate(cfg)
+        per_phantom.append({"phantom_seed": seed, "hull_start": hull, "warm_start": res})
+        log(f"held-out phantom {seed}: hull {hull['sweeps_to_1pct']} sweeps; networks "
+            f"{[r['total_sweeps'] for r in res]} sweeps, output RSP errors {[r['rsp_err_of_net_output'] for r in res]}")
+
+    def tot(xs):
+        return None if any(v is None for v in xs) else round(sum(xs), 4)
+
+    hull_t = tot([p["hull_start"]["time_to_1pct_s"] for p in per_phantom])
+    summary = []
+    for j, (ins, wc, tg, net, (loss0, loss1), train_s) in enumerate(nets):
+        tj = tot([p["warm_start"][j]["time_to_1pct_s"] for p in per_phantom])
+        summary.append({"inputs_after_sweeps": list(ins), "coarse_loss_weight": wc, "target": tg,
+                        "total_sweeps_per_phantom": [p["warm_start"][j]["total_sweeps"] for p in per_phantom],
+                        "time_to_1pct_s_total": tj,
+                        "speedup_vs_hull_start": round(hull_t / tj, 3) if (hull_t and tj) else None,
+                        "rel_l2_of_net_output_per_phantom": [p["warm_start"][j]["rel_l2_of_net_output"]
+                                                             for p in per_phantom],
+                        "train_s": round(train_s, 1),
+                        "train_ms_per_step": round(train_s * 1e3 / max(args.ws_steps, 1), 2),
+                        "train_loss_identity": loss0, "train_loss_trained": loss1})
     out = {
         "metric": "time to <= 1% RSP error (learned warm start vs hull start)",
-        "value": first["time_to_1pct_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
-        "speedup_vs_hull_start": first["speedup_vs_hull_start"],
+        "value": per_phantom[0]["warm_start"][0]["time_to_1pct_s"], "unit": "s", "n_gpus": 1,
+        "higher_is_better": False,
+        "hull_start_value": per_phantom[0]["hull_start"]["time_to_1pct_s"],
         "dtype": "f32", "data": "synthetic (seeded phantoms + Fermi-Eyges transport)",
-        "config": {"workload": f"held-out head phantom (seed 3), {N} histories, 200x200x40 voxels of 1 mm, "
-                               f"DROP blocks of {cfg.block}, lambda {cfg.lam}, rows cached (f32), tiled sweep plan",
+        "config": {"workload": f"held-out head phantoms (seeds {eval_seeds}; value: seed 3), {N} histories each, "
+                               f"200x200x40 voxels of 1 mm, DROP blocks of 200000, lambda 0.5, rows cached (f32), "
+                               f"tiled sweep plan",
                    "network": {"channels": list(channels), "train_phantoms": args.ws_train,
                                "train_steps": args.ws_steps, "lr": args.ws_lr, "target_sweeps": args.ws_out}},
-        "setup_s": round(S["setup_s"], 4), "training_data_s": round(data_s, 1),
-        "hull_start": hull, "warm_start": results,
+        "training_data_s": round(data_s, 1),
+        "hull_start_sweeps_per_phantom": [p["hull_start"]["sweeps_to_1pct"] for p in per_phantom],
+        "hull_start_time_to_1pct_s_total": hull_t,
+        "variants": summary, "per_phantom": per_phantom,
     }
     print(json.dumps(out), flush=True)
 

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "cnn_internal.h"
 #include "path_device.h"
 
@@ -104,6 +106,8 @@ __global__ void __launch_bounds__(kThreads) k_flip(const float *__restrict__ w, 
 // lane folds its rows into kWgCob x 27 register accumulators per input
 // channel; each wavefront then adds its lanes with DPP prefix sums and the
 // workgroup adds its wavefronts in order (fixed summation order throughout).
+// Small volumes also split the input channels over workgroups (grid z), so
+// that every level of the network fills the chip.
 constexpr int kWaves = kThreads / 64;
 constexpr int kWgCob = 4;
 constexpr int kTileY = 16, kTileZ = 16;
@@ -115,7 +119,7 @@ __device__ __forceinline__ float wave_total(float v) {
 
 __global__ void __launch_bounds__(kThreads) k_wgrad_part(const float *__restrict__ x, const float *__restrict__ dy,
                                                          float *__restrict__ part, int cin, int cout, int D, int H,
-                                                         int W, int tiles_x, int tiles_y) {
+                                                         int W, int tiles_x, int tiles_y, int ci_per_wg) {
   __shared__ float red[kWaves][kWgCob][kTaps + 1];
   const int tile = blockIdx.x;
   const int txi = tile % tiles_x, tyi = (tile / tiles_x) % tiles_y, tzi = tile / (tiles_x * tiles_y);
@@ -130,10 +134,13 @@ __global__ void __launch_bounds__(kThreads) k_wgrad_part(const float *__restrict
   const int nrows = ny * nz;
   const int64_t V = (int64_t)D * H * W;
   const int64_t stride = (int64_t)cin * kTaps + 1;
+  // input channels [ci0, ci1) of this workgroup; the bias gradient comes from
+  // the workgroups that start at channel 0
+  const int ci0 = blockIdx.z * ci_per_wg, ci1 = min(cin, ci0 + ci_per_wg);
   float gsum[kWgCob];
 #pragma unroll
   for (int c = 0; c < kWgCob; ++c) gsum[c] = 0.0f;
-  for (int ci = 0; ci < cin; ++ci) {
+  for (int ci = ci0; ci < ci1; ++ci) {
     const float *xch = x + (int64_t)ci * V;
     float acc[kWgCob][kTaps];
 #pragma unroll
@@ -376,6 +383,7 @@ hipError_t flip_weights(const float *w, float *wt, int cin, int cout, hipStream_
 }
 
 static inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+constexpr int64_t kWgradTargetWgs = 2048;  // workgroups wanted per weight-gradient launch
 
 int64_t wgrad_chunks(int D, int H, int W) {
   return (int64_t)ceil_div(W, 64) * ceil_div(H, kTileY) * ceil_div(D, kTileZ);
@@ -386,8 +394,11 @@ hipError_t conv3d_wgrad(const float *x, const float *dy, float *dw, float *db, f
   const int64_t chunks = wgrad_chunks(D, H, W);
   if (chunks <= 0 || cout <= 0) return hipSuccess;
   const int tx = ceil_div(W, 64), ty = ceil_div(H, kTileY);
-  hipLaunchKernelGGL(k_wgrad_part, dim3((unsigned)chunks, (unsigned)ceil_div(cout, kWgCob)), dim3(kThreads), 0, s, x,
-                     dy, part, cin, cout, D, H, W, tx, ty);
+  const int64_t wgs = chunks * ceil_div(cout, kWgCob);
+  const int splits = (int)std::min<int64_t>(cin, std::max<int64_t>(1, (kWgradTargetWgs + wgs - 1) / wgs));
+  const int ci_per = ceil_div(cin, splits);
+  hipLaunchKernelGGL(k_wgrad_part, dim3((unsigned)chunks, (unsigned)ceil_div(cout, kWgCob), (unsigned)ceil_div(cin, ci_per)),
+                     dim3(kThreads), 0, s, x, dy, part, cin, cout, D, H, W, tx, ty, ci_per);
   const int64_t n = (int64_t)cout * ((int64_t)cin * kTaps + 1);
   hipLaunchKernelGGL(k_wgrad_sum, dim3(blocks_for(n)), dim3(kThreads), 0, s, part, dw, db, chunks, cin, cout);
   return hipGetLastError();
