@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--warmstart", action="store_true",
                     help="learned warm start: train the 3D U-Net on solver pairs of seeded phantoms, then compare "
                          "the time to <= 1%% RSP error from the hull start and from the network's x0")
+    ap.add_argument("--cnn-timing", action="store_true",
+                    help="time the warm-start network's kernels on one 200x200x40 volume and exit")
     ap.add_argument("--ws-train", type=int, default=24, help="training phantoms (seeds 1000, 1001, ...)")
     ap.add_argument("--ws-n", type=int, default=10_000_000, help="histories per phantom (training and evaluation)")
     ap.add_argument("--ws-steps", type=int, default=2000, help="Adam steps (one phantom per step)")
@@ -174,6 +176,9 @@ def main():
         sys.exit(2)
     if args.warmstart:
         warmstart_experiment(args)
+        return
+    if args.cnn_timing:
+        cnn_timing(args)
         return
     import numpy as np
     import torch
@@ -388,6 +393,65 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    print(json.dumps(out), flush=True)
+
+
+def cnn_timing(args):
+    """Device time of the warm-start network on one 200 x 200 x 40 volume
+    (channels --ws-channels): inference, one training step, and each
+    convolution shape of the network's first three levels (forward, input
+    gradient, weight gradient) with its FP32 throughput (2 flops per
+    multiply-add of the 3x3x3 contraction).  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    from paper_1707_05014_amd import _lib, cnn
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    _lib.load()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    D, H, W = 40, 200, 200
+    channels = tuple(int(c) for c in args.ws_channels.split(","))
+    net = cnn.UNet3D(channels, device=dev, seed=0)
+    rng = np.random.default_rng(0)
+    x = torch.from_numpy(rng.uniform(0, 1.8, size=(1, D, H, W)).astype(np.float32)).to(dev)
+    t = torch.from_numpy(rng.uniform(0, 1.8, size=(1, D, H, W)).astype(np.float32)).to(dev)
+
+    def ms(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / n
+
+    out = {"metric": "warm-start network device time", "unit": "ms", "n_gpus": 1, "dtype": "f32",
+           "config": {"workload": f"one {W}x{H}x{D} volume, channels {list(channels)}"},
+           "inference_ms": round(ms(lambda: net.predict(x), args.steps * 3), 3),
+           "train_step_ms": round(ms(lambda: net.train_step(x, t, 1e-4), args.steps * 3), 3), "conv": []}
+    dims = (D, H, W)
+    for lvl, c in enumerate(channels[:3]):
+        a = torch.from_numpy(rng.normal(size=(c,) + dims).astype(np.float32)).to(dev)
+        w = torch.from_numpy(rng.normal(size=(c, c, 3, 3, 3)).astype(np.float32)).to(dev)
+        b = torch.zeros(c, dtype=torch.float32, device=dev)
+        y = torch.empty_like(a)
+        dx = torch.empty_like(a)
+        wt = torch.empty(c * c * 27, dtype=torch.float32, device=dev)
+        sc = torch.empty(cnn.wgrad_scratch(c, c, *dims), dtype=torch.float32, device=dev)
+        dw, db = torch.empty_like(w), torch.empty_like(b)
+        flops = 2.0 * dims[0] * dims[1] * dims[2] * c * c * 27
+        f = ms(lambda: cnn.conv3d(a, w, b, y), args.steps * 5)
+        bd = ms(lambda: cnn.conv3d_bwd_data(y, w, dx, wt), args.steps * 5)
+        bw = ms(lambda: cnn.conv3d_bwd_weight(a, y, dw, db, sc), args.steps * 5)
+        out["conv"].append({"level": lvl, "shape": f"{c}->{c} on {dims[2]}x{dims[1]}x{dims[0]}",
+                            "fwd_ms": round(f, 4), "bwd_data_ms": round(bd, 4), "bwd_weight_ms": round(bw, 4),
+                            "fwd_tflops": round(flops / f / 1e9, 2), "bwd_data_tflops": round(flops / bd / 1e9, 2),
+                            "bwd_weight_tflops": round(flops / bw / 1e9, 2)})
+        dims = tuple(d // 2 for d in dims)
     print(json.dumps(out), flush=True)
 
 
