@@ -225,6 +225,16 @@ def main():
 
     rows = None
     plan = None
+    nnz_est = None
+    if args.fused:
+        # entries per history, from a traced sample (the fused sweep never stores rows)
+        ns = min(N, 1_000_000)
+        Hs = api.Histories({k: v[:ns] for k, v in H.t.items()})
+        rs = api.mlp_trace(grid, geom, Hs)
+        torch.cuda.synchronize()
+        nnz_est = rs.nnz / ns * N
+        log(f"fused: ~{rs.nnz / ns:.1f} row entries per history (first {ns} histories)")
+        del Hs, rs
     if not args.fused:
         rows = api.mlp_trace(grid, geom, H, len_dtype=len_dtype)  # sizing + allocation
         torch.cuda.synchronize()
@@ -295,6 +305,14 @@ def main():
         # rows rebuilt in every block: the path work of the block's histories
         models["project"] = ("alu", PATH_FLOPS_PER_POINT * points / n_blocks, FP64_PEAK_TFLOPS, "TFLOP/s",
                              "pct::k_project_fused<float>" if args.path_fp32 else "pct::k_project_fused<double>")
+    fused_atomics = None
+    if args.fused and nnz_est:
+        # global float/int atomics of the fused projection per step: 2 per row
+        # entry in the first sweep (numerator and count), 1 in the later ones
+        # (the block counts are kept), or 2 in every sweep for one sweep
+        n_at = nnz_est * ((S + 1) if S >= 2 else 2 * S)
+        fused_atomics = {"per_step": round(n_at), "achieved_per_s": round(n_at / (prof["project"][1] / 1e3)),
+                         "entries_per_history": round(nnz_est / N, 2)}
     timing = dict(prof)
     timing["trace"] = prof["trace_path"]
     dom = max((k for k in models if timing.get(k, (0, 0.0))[0]), key=lambda k: timing[k][1])
@@ -386,6 +404,7 @@ def main():
             "residual_ms": round(residual_ms, 3),
             "kernel_ms": {k: [v[0], round(v[1], 3)] for k, v in prof.items()},
             "kernel_rates": others, "path_points": points,
+            "fused_atomics": fused_atomics,
             "accuracy": acc, "gen_s": round(gen_s, 1),
             "paper_context": "2e9 histories in under 10 min on the authors' earlier cluster (Sec. 1); "
                              "Table 1: 2.107e9 histories in 3:32 on 120 x (CPU core + Tesla GPU)",

@@ -155,7 +155,13 @@ typedef struct {
  * geom given and fused = 0 the size includes the row staging area of the
  * trace (up to 2^20 rows of the longest possible row, 8 bytes per entry); a
  * trace given less stages fewer rows at a time (PCT_ENOMEM below one row).
- * The same workspace may be reused by consecutive calls on one stream. */
+ * With fused = 1 and params of a DROP run of two or more sweeps the size
+ * includes the per-block voxel counts s_j (n_blocks x M x 2 bytes, kept up to
+ * 32 GiB): pct_reconstruct then forms them in its first sweep and reads them
+ * back in the later ones instead of counting again with atomics (the block
+ * composition is the same every sweep, Sec. 2.1); with a smaller workspace it
+ * counts in every sweep.  The same workspace may be reused by consecutive
+ * calls on one stream. */
 size_t pct_workspace_size(const pct_grid *grid, const pct_geom *geom, const pct_sweep_params *params,
                           int64_t n_hist, int32_t fused);
 

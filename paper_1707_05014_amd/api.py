@@ -138,12 +138,13 @@ _ws_cache: dict = {}
 
 
 def workspace(grid: pct_grid, n_hist: int, device=None, params: "SweepParams | None" = None,
-              geom: pct_geom | None = None) -> torch.Tensor:
+              geom: pct_geom | None = None, fused: bool = False) -> torch.Tensor:
     """Device scratch of pct_workspace_size bytes, cached per device and grown
-    on demand (geom given: includes the trace's row staging area)."""
+    on demand (geom given: includes the trace's row staging area; fused with
+    params of several DROP sweeps: includes the kept per-block counts)."""
     lib = _lib.load()
     nbytes = lib.pct_workspace_size(ctypes.byref(grid), ctypes.byref(geom) if geom is not None else None,
-                                    ctypes.byref(params.struct) if params else None, int(n_hist), 0)
+                                    ctypes.byref(params.struct) if params else None, int(n_hist), 1 if fused else 0)
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     ws = _ws_cache.get(dev)
     if ws is None or ws.numel() < nbytes:
@@ -259,7 +260,7 @@ def reconstruct(grid, geom, hist: Histories, params: SweepParams, x: torch.Tenso
     With a plan, its memory must already be allocated (plan_build sizes it)."""
     lib = _lib.load()
     _check_lengths(grid, hist, x, params)
-    ws = workspace(grid, hist.n, x.device, params, geom=geom if rows is not None else None)
+    ws = workspace(grid, hist.n, x.device, params, geom=geom if rows is not None else None, fused=rows is None)
     hs = hist.struct()
     rs = rows.struct() if rows is not None else None
     res = (ctypes.c_double * max(params.n_sweeps, 1))()

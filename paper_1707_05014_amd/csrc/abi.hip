@@ -263,7 +263,20 @@ pct_status do_trace(Ctx &c, const pct_grid *g, pct_rows *rows) {
   return status_to_code(st);
 }
 
-pct_status do_sweep(Ctx &c, const pct_grid *g, const pct_rows *rows, float *x, const pct_sweep_params *p) {
+// Elements of the per-block voxel counts that a fused DROP reconstruction of
+// several sweeps keeps (the block composition, hence s_j, is the same every
+// sweep): n_blocks x M, or 0 when not worth it or too large.
+int64_t fused_count_elems(int64_t M, int64_t n, const pct_sweep_params *p) {
+  if (!p || p->algo != 1 || p->block_size < 1 || p->n_sweeps < 2 || n <= 0) return 0;
+  const int64_t nb = (n + p->block_size - 1) / p->block_size;
+  if (nb > pct::kMaxBlkCntBytes / 2 / std::max<int64_t>(M, 1)) return 0;
+  return nb * M;
+}
+
+// count_mode 0: s_j formed with atomics in every block; 1: formed and stored
+// per block; 2: read from the stored counts
+pct_status do_sweep(Ctx &c, const pct_grid *g, const pct_rows *rows, float *x, const pct_sweep_params *p,
+                    int count_mode = 0) {
   HIPCHECK(pct::launch_mask(x, p->hull_mask, c.M, c.s));
   const float unit = len_unit(g);
   if (p->algo == 0) {
@@ -273,16 +286,18 @@ pct_status do_sweep(Ctx &c, const pct_grid *g, const pct_rows *rows, float *x, c
   }
   HIPCHECK(pct::launch_fill_f32(c.W.num, c.M, 0.f, c.s));
   HIPCHECK(pct::launch_fill_u32(c.W.cnt, c.M, 0u, c.s));
-  for (int64_t first = 0; first < c.n; first += p->block_size) {
+  if (rows || !c.W.blk_cnt) count_mode = 0;
+  for (int64_t first = 0, blk = 0; first < c.n; first += p->block_size, ++blk) {
     const int64_t count = std::min<int64_t>(p->block_size, c.n - first);
     if (rows)
       PROF(PCT_K_PROJECT, pct::launch_project_cached(rows->row_ptr, rows->idx, rows->len, rows->len_dtype, unit,
                                                      rows->norm2, c.H.wepl, p->order, first, count, c.n, c.M, x,
                                                      c.W.num, c.W.cnt, c.W.status, c.s));
     else
-      PROF(PCT_K_PROJECT, pct::launch_project_fused(c.P, c.H, p->order, first, count, c.n, x, c.W.num, c.W.cnt,
-                                                    c.W.status, c.s));
-    PROF(PCT_K_APPLY, pct::launch_apply(x, c.W.num, c.W.cnt, p->hull_mask, c.M, p->lambda, c.s));
+      PROF(PCT_K_PROJECT, pct::launch_project_fused(c.P, c.H, p->order, first, count, c.n, x, c.W.num,
+                                                    count_mode == 2 ? nullptr : c.W.cnt, c.W.status, c.s));
+    PROF(PCT_K_APPLY, pct::launch_apply_counts(x, c.W.num, c.W.cnt, count_mode ? c.W.blk_cnt + blk * c.M : nullptr,
+                                               count_mode, p->hull_mask, c.M, p->lambda, c.W.status, c.s));
   }
   return PCT_OK;
 }
@@ -572,7 +587,7 @@ namespace pct {
 // fixed part (status, DROP accumulators, partial sums, scan chunks) followed
 // by one shared tail: the plan sizing counters during a plan build, the
 // staged rows during a trace (never both at once)
-size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots) {
+size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots, int64_t blk_cnt_elems) {
   size_t b = align_up(4 * sizeof(uint32_t));
   b += align_up((size_t)M * sizeof(float));
   b += align_up((size_t)M * sizeof(uint32_t));
@@ -581,11 +596,12 @@ size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage
   const size_t plan_b = (size_t)(plan_bt > 0 ? plan_bt : 0) * sizeof(int64_t);
   const size_t stage_b = 2 * align_up((size_t)(stage_slots > 0 ? stage_slots : 0) * 4);
   b += align_up(std::max(plan_b, stage_b));
+  b += align_up((size_t)(blk_cnt_elems > 0 ? blk_cnt_elems : 0) * sizeof(uint16_t));
   return b;
 }
 
-Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots) {
-  (void)plan_bt;
+Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots,
+                          int64_t blk_cnt_elems) {
   char *p = static_cast<char *>(base);
   Workspace w;
   w.status = reinterpret_cast<uint32_t *>(p);
@@ -601,6 +617,10 @@ Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt
   w.plan_scratch = reinterpret_cast<int64_t *>(p);
   w.st_idx = reinterpret_cast<int32_t *>(p);
   w.st_len = reinterpret_cast<float *>(p + align_up((size_t)(stage_slots > 0 ? stage_slots : 0) * 4));
+  const size_t plan_b = (size_t)(plan_bt > 0 ? plan_bt : 0) * sizeof(int64_t);
+  const size_t stage_b = 2 * align_up((size_t)(stage_slots > 0 ? stage_slots : 0) * 4);
+  p += align_up(std::max(plan_b, stage_b));
+  w.blk_cnt = blk_cnt_elems > 0 ? reinterpret_cast<uint16_t *>(p) : nullptr;
   return w;
 }
 
@@ -618,7 +638,8 @@ size_t pct_workspace_size(const pct_grid *grid, const pct_geom *geom, const pct_
   pct::PathParams P;
   if (geom && !fused && make_params(grid, geom, P) == PCT_OK)
     stage = std::min<int64_t>(n_hist, pct::kStageRows) * P.emax;
-  return pct::workspace_bytes(grid_voxels(grid), n_hist, plan_bt, stage);
+  const int64_t blk = fused ? fused_count_elems(grid_voxels(grid), n_hist, params) : 0;
+  return pct::workspace_bytes(grid_voxels(grid), n_hist, plan_bt, stage, blk);
 }
 
 pct_status pct_mlp_trace(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist, pct_rows *rows,
@@ -726,10 +747,16 @@ pct_status pct_reconstruct(const pct_grid *grid, const pct_geom *geom, const pct
   if (plan && !plan->mem) return fail(PCT_EINVAL, "plan memory is NULL (size it with pct_plan_build first)");
   if (!x_inout) return fail(PCT_EINVAL, "x is NULL");
   pct_status trace_st = PCT_OK;
+  int count_mode = 0;  // fused sweeps: keep the per-block counts when the workspace holds them
   if (rows) {
     trace_st = do_trace(c, grid, rows);
     if (trace_st != PCT_OK && trace_st != PCT_ENONFINITE) return trace_st;
   } else {
+    const int64_t blk = fused_count_elems(c.M, c.n, params);
+    if (blk > 0 && pct::workspace_bytes(c.M, c.n, 0, 0, blk) <= ws_bytes) {
+      c.W = pct::carve_workspace(workspace, c.M, c.n, 0, 0, blk);
+      count_mode = 1;
+    }
     HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
   }
   pct::PlanView V;
@@ -743,8 +770,14 @@ pct_status pct_reconstruct(const pct_grid *grid, const pct_geom *geom, const pct
   for (int32_t sw = 0; sw < params->n_sweeps; ++sw) {
     if (plan) {
       if ((r = do_plan_sweep(c, plan, V, x_inout, params)) != PCT_OK) return r;
-    } else if ((r = do_sweep(c, grid, rows, x_inout, params)) != PCT_OK) {
+    } else if ((r = do_sweep(c, grid, rows, x_inout, params, count_mode)) != PCT_OK) {
       return r;
+    }
+    if (count_mode == 1) {
+      // the stored counts serve the later sweeps unless one of them overflowed 16 bits
+      uint32_t st = 0;
+      if ((r = read_status(c, &st)) != PCT_OK) return r;
+      count_mode = (st & pct::kStCountSat) ? 0 : 2;
     }
     if (resid_host) {
       // partial sums use the front of the array; the result sits in its last slot

@@ -19,6 +19,7 @@ constexpr uint32_t kStOverflow = 2u;
 constexpr uint32_t kStRowMismatch = 4u;
 constexpr uint32_t kStBadIndex = 8u;   // an order entry or a cached voxel index out of range
 constexpr uint32_t kStRowCap = 16u;    // the rows need more entries than their capacity
+constexpr uint32_t kStCountSat = 32u;  // a block count exceeded 16 bits (stored counts unusable; not an error)
 
 // Everything a path kernel needs, precomputed on the host and passed by value.
 struct PathParams {
@@ -58,13 +59,19 @@ struct Workspace {
   int64_t *scan;         // [scan_len]
   int32_t *st_idx;       // [stage_slots] staged row entries of one chunk of rows (trace)
   float *st_len;         // [stage_slots]
+  uint16_t *blk_cnt;     // [blk_cnt_elems] per-block voxel counts s_j of the fused sweep (or NULL)
 };
 constexpr int64_t kMaxPartials = 1 << 16;
 constexpr int64_t kScanChunk = 4096;
 constexpr int64_t kStageRows = 1 << 20;  // rows traced per staging chunk
 
-size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots = 0);
-Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots = 0);
+// the per-block counts of the fused sweep (n_blocks x M uint16) are kept only
+// up to this size; above it the counts are re-formed with atomics every sweep
+constexpr int64_t kMaxBlkCntBytes = int64_t(32) << 30;
+size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots = 0,
+                       int64_t blk_cnt_elems = 0);
+Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots = 0,
+                          int64_t blk_cnt_elems = 0);
 
 // ---- tiled sweep plan (cached rows regrouped by block and spatial tile)
 constexpr int kTX = 16, kTY = 16, kTZ = 8;           // tile of 2048 voxels
@@ -151,6 +158,10 @@ hipError_t launch_project_cached(const int64_t *row_ptr, const int32_t *idx, con
 hipError_t launch_project_fused(const PathParams &P, const HistPtrs &H, const int64_t *order, int64_t first,
                                 int64_t count, int64_t n, const float *x, float *num, uint32_t *cnt,
                                 uint32_t *status, hipStream_t s);
+// mode 0: counts from cnt (cleared); 1: also store them as uint16 into blk_cnt;
+// 2: counts read from blk_cnt (cnt unused)
+hipError_t launch_apply_counts(float *x, float *num, uint32_t *cnt, uint16_t *blk_cnt, int mode, const uint8_t *mask,
+                               int64_t M, float lambda, uint32_t *status, hipStream_t s);
 hipError_t launch_apply(float *x, float *num, uint32_t *cnt, const uint8_t *mask, int64_t M, float lambda,
                         hipStream_t s);
 hipError_t launch_art(const int64_t *row_ptr, const int32_t *idx, const void *len, int32_t len_dtype,

@@ -59,8 +59,10 @@ __global__ void __launch_bounds__(256) k_project_cached(const int64_t *__restric
   }
 }
 
-// one wavefront per proton of the block: the row is rebuilt in LDS
-template <typename R>
+// one wavefront per proton of the block: the row is rebuilt in LDS.  Without
+// COUNT the block's voxel counts s_j are not formed (they were stored by an
+// earlier sweep), which halves the global atomics.
+template <typename R, bool COUNT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_project_fused(PathParams P, HistPtrs H, const int64_t *__restrict__ order,
                                                        int64_t first, int64_t count, int64_t n,
                                                        const float *__restrict__ x, float *num, uint32_t *cnt,
@@ -97,7 +99,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     for (int e = lane; e < ne; e += kWave) {
       const int j = s_vox[e];
       atomicAdd(&num[j], r * s_len[e]);
-      atomicAdd(&cnt[j], 1u);
+      if constexpr (COUNT) atomicAdd(&cnt[j], 1u);
     }
   }
 }
@@ -115,6 +117,34 @@ __global__ void __launch_bounds__(256) k_apply(float *__restrict__ x, float *__r
       cnt[j] = 0u;
     }
   }
+}
+
+// k_apply with the block's counts stored (MODE 1: from cnt into blk_cnt, all
+// M voxels written) or read back (MODE 2: from blk_cnt, cnt untouched)
+template <int MODE>
+__global__ void __launch_bounds__(256) k_apply_counts(float *__restrict__ x, float *__restrict__ num,
+                                                      uint32_t *__restrict__ cnt, uint16_t *__restrict__ blk_cnt,
+                                                      const uint8_t *__restrict__ mask, int64_t M, float lambda,
+                                                      uint32_t *status) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool sat = false;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < M; j += stride) {
+    uint32_t c;
+    if constexpr (MODE == 1) {
+      c = cnt[j];
+      sat |= c > 0xffffu;
+      blk_cnt[j] = (uint16_t)(c > 0xffffu ? 0xffffu : c);
+    } else {
+      c = blk_cnt[j];
+    }
+    if (c) {
+      const float v = x[j] + lambda * num[j] / (float)c;
+      x[j] = (mask && !mask[j]) ? 0.0f : v;
+      num[j] = 0.0f;
+      if constexpr (MODE == 1) cnt[j] = 0u;
+    }
+  }
+  if (MODE == 1 && __ballot(sat) && wave_lane() == 0) atomicOr(status, kStCountSat);
 }
 
 __global__ void __launch_bounds__(256) k_mask(float *__restrict__ x, const uint8_t *__restrict__ mask, int64_t M) {
@@ -306,12 +336,34 @@ hipError_t launch_project_fused(const PathParams &P, const HistPtrs &H, const in
   if (count <= 0) return hipSuccess;
   const size_t lds = (size_t)P.waves_per_block * 3 * P.emax * sizeof(int);
   const unsigned grid = grid_for(count, P.waves_per_block, 1u << 20);
-  if (P.path_fp32)
-    hipLaunchKernelGGL(k_project_fused<float>, dim3(grid), dim3(P.waves_per_block * kWave), lds, s, P, H, order,
-                       first, count, n, x, num, cnt, status);
+  const dim3 g(grid), b(P.waves_per_block * kWave);
+  if (P.path_fp32) {
+    if (cnt)
+      hipLaunchKernelGGL((k_project_fused<float, true>), g, b, lds, s, P, H, order, first, count, n, x, num, cnt,
+                         status);
+    else
+      hipLaunchKernelGGL((k_project_fused<float, false>), g, b, lds, s, P, H, order, first, count, n, x, num, cnt,
+                         status);
+  } else {
+    if (cnt)
+      hipLaunchKernelGGL((k_project_fused<double, true>), g, b, lds, s, P, H, order, first, count, n, x, num, cnt,
+                         status);
+    else
+      hipLaunchKernelGGL((k_project_fused<double, false>), g, b, lds, s, P, H, order, first, count, n, x, num, cnt,
+                         status);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_counts(float *x, float *num, uint32_t *cnt, uint16_t *blk_cnt, int mode, const uint8_t *mask,
+                               int64_t M, float lambda, uint32_t *status, hipStream_t s) {
+  const dim3 g(grid_for(M, 256, 8192)), b(256);
+  if (mode == 0)
+    hipLaunchKernelGGL(k_apply, g, b, 0, s, x, num, cnt, mask, M, lambda);
+  else if (mode == 1)
+    hipLaunchKernelGGL(k_apply_counts<1>, g, b, 0, s, x, num, cnt, blk_cnt, mask, M, lambda, status);
   else
-    hipLaunchKernelGGL(k_project_fused<double>, dim3(grid), dim3(P.waves_per_block * kWave), lds, s, P, H, order,
-                       first, count, n, x, num, cnt, status);
+    hipLaunchKernelGGL(k_apply_counts<2>, g, b, 0, s, x, num, cnt, blk_cnt, mask, M, lambda, status);
   return hipGetLastError();
 }
 

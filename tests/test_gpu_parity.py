@@ -5,6 +5,7 @@ protons, with the voxels that differ carrying only slivers; path lengths
 within 1e-4 mm (1e-4 of the 1 mm voxel) on identical rows; ||a_i||^2 within
 1e-4 relative; images within 1e-3 relative L2 after a fixed number of sweeps.
 """
+import ctypes
 import sys
 
 import numpy as np
@@ -245,6 +246,33 @@ def test_fused_equals_cached_single_block(cfg1):
     xa, _ = _run_gpu(cfg, h, "drop", cfg.n, 1, order, mask, fused=False)
     xb, _ = _run_gpu(cfg, h, "drop", cfg.n, 1, order, mask, fused=True)
     assert _rel(xa, xb) <= 1e-6
+
+
+def test_fused_kept_counts_match_counting(cfg1):
+    """A fused reconstruction of several sweeps keeps each block's voxel
+    counts from its first sweep; one-sweep calls count with atomics every
+    time.  Both give the same image up to atomic summation order, and the
+    kept counts need the larger workspace (a smaller one falls back)."""
+    cfg, h, R = cfg1
+    _say("fused: kept block counts vs counting every sweep")
+    order = synth.block_order(cfg.n, cfg.perm_seed)
+    mask = synth.hull_mask(cfg)
+    xa, ra = _run_gpu(cfg, h, "drop", 7000, 4, order, mask, fused=True)
+    grid, geom = pct_args(cfg)
+    H = api.Histories.from_numpy(h)
+    x = torch.from_numpy(mask.astype(np.float32)).cuda()
+    p1 = api.sweep_params("drop", 7000, cfg.lam, 1, order=torch.from_numpy(order).cuda(),
+                          hull_mask=torch.from_numpy(mask).cuda())
+    for _ in range(4):
+        api.project_sweep(grid, geom, H, None, x, p1)
+    xb = x.cpu().numpy().astype(np.float64)
+    assert _rel(xa, xb) <= 1e-6
+    lib = _lib.load()
+    p4 = api.sweep_params("drop", 7000, cfg.lam, 4)
+    big = lib.pct_workspace_size(ctypes.byref(grid), None, ctypes.byref(p4.struct), cfg.n, 1)
+    small = lib.pct_workspace_size(ctypes.byref(grid), None, None, cfg.n, 1)
+    n_blocks = -(-cfg.n // 7000)
+    assert big - small >= n_blocks * cfg.grid.M * 2
 
 
 # ------------------------------------------------------------- tiled plan
