@@ -226,6 +226,7 @@ def main():
     rows = None
     plan = None
     nnz_est = None
+    atomic_ref = None
     if args.fused:
         # entries per history, from a traced sample (the fused sweep never stores rows)
         ns = min(N, 1_000_000)
@@ -234,7 +235,20 @@ def main():
         torch.cuda.synchronize()
         nnz_est = rs.nnz / ns * N
         log(f"fused: ~{rs.nnz / ns:.1f} row entries per history (first {ns} histories)")
-        del Hs, rs
+        # reference rate for the numerator adds: the same voxel sequence (these
+        # rows, in row order) scatter-added into an image by torch's index_add_
+        vi = rs.idx[: rs.nnz].to(torch.int64)
+        vv = torch.ones(rs.nnz, dtype=torch.float32, device=dev)
+        acc = torch.zeros(M, dtype=torch.float32, device=dev)
+        acc.index_add_(0, vi, vv)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            acc.index_add_(0, vi, vv)
+        torch.cuda.synchronize()
+        atomic_ref = 5 * rs.nnz / (time.perf_counter() - t0)
+        log(f"fused: torch index_add_ of the same voxel sequence: {atomic_ref:.3e} adds/s")
+        del Hs, rs, vi, vv, acc
     if not args.fused:
         rows = api.mlp_trace(grid, geom, H, len_dtype=len_dtype)  # sizing + allocation
         torch.cuda.synchronize()
@@ -311,8 +325,12 @@ def main():
         # entry in the first sweep (numerator and count), 1 in the later ones
         # (the block counts are kept), or 2 in every sweep for one sweep
         n_at = nnz_est * ((S + 1) if S >= 2 else 2 * S)
-        fused_atomics = {"per_step": round(n_at), "achieved_per_s": round(n_at / (prof["project"][1] / 1e3)),
-                         "entries_per_history": round(nnz_est / N, 2)}
+        ach = n_at / (prof["project"][1] / 1e3)
+        fused_atomics = {"per_step": round(n_at), "achieved_per_s": round(ach),
+                         "entries_per_history": round(nnz_est / N, 2),
+                         "reference_per_s": round(atomic_ref) if atomic_ref else None,
+                         "reference": "torch index_add_ of the traced sample's voxel sequence (same device)",
+                         "frac_of_reference": round(ach / atomic_ref, 3) if atomic_ref else None}
     timing = dict(prof)
     timing["trace"] = prof["trace_path"]
     dom = max((k for k in models if timing.get(k, (0, 0.0))[0]), key=lambda k: timing[k][1])
@@ -337,10 +355,14 @@ def main():
     # its time by launch count (every launch covers one block)
     dot_n, dot_ms = prof["plan_dot"]
     dot_sweep_ms = dot_ms * min(1.0, n_blocks * S / dot_n) if dot_n else 0.0
+    # the per-proton path set-up (hull, end states) runs once per call: with
+    # cached rows before the trace, in the fused form before the first sweep
+    # (one record per history, read by every later path pass)
+    setup_ms = prof["path_setup"][1]
     sweep_ms = (prof["project"][1] + prof["apply"][1] + dot_sweep_ms + prof["plan_rows"][1]
                 + prof["plan_scatter"][1]) / S
     residual_ms = (prof["residual"][1] + dot_ms - dot_sweep_ms) / max(S, 1)
-    trace_ms = prof["trace_path"][1] + prof["trace_compact"][1]
+    trace_ms = prof["trace_path"][1] + prof["trace_compact"][1] + setup_ms
     others = {k: {"achieved": round(models[k][1] / (timing[k][0] if k == "trace" else 1)
                                     / (timing[k][1] / timing[k][0] / 1e3)
                                     / (1e9 if models[k][3] == "GB/s" else 1e12), 3),

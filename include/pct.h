@@ -248,7 +248,8 @@ enum {
     PCT_K_PLAN_ROWS = 8,     /* plan: r_i per row */
     PCT_K_PLAN_SCATTER = 9,  /* plan: per-tile accumulation + block update */
     PCT_K_PLAN_BUILD = 10,   /* plan construction */
-    PCT_K_COUNT = 11
+    PCT_K_PATH_SETUP = 11,   /* per-proton path set-up (hull, end states), one thread per proton */
+    PCT_K_COUNT = 12
 };
 pct_status pct_profile_enable(int32_t on);
 pct_status pct_profile_read(int64_t *launches, double *ms);

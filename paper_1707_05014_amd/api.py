@@ -193,7 +193,7 @@ def project_sweep(grid, geom, hist: Histories, rows: Rows | None, x: torch.Tenso
                   resid_out: torch.Tensor | None = None, stream=None):
     lib = _lib.load()
     _check_lengths(grid, hist, x, params)
-    ws = workspace(grid, hist.n, x.device)
+    ws = workspace(grid, hist.n, x.device, fused=rows is None)
     hs = hist.struct()
     rs = rows.struct() if rows is not None else None
     check(lib.pct_project_sweep(ctypes.byref(grid), ctypes.byref(geom), ctypes.byref(hs),
@@ -280,7 +280,7 @@ def reconstruct(grid, geom, hist: Histories, params: SweepParams, x: torch.Tenso
 
 def residual(grid, geom, hist: Histories, rows: Rows | None, x: torch.Tensor, stream=None) -> float:
     lib = _lib.load()
-    ws = workspace(grid, hist.n, x.device)
+    ws = workspace(grid, hist.n, x.device, fused=rows is None)
     out = torch.empty(1, dtype=torch.float64, device=x.device)
     hs = hist.struct()
     rs = rows.struct() if rows is not None else None

@@ -197,6 +197,7 @@ struct Ctx {
   hipStream_t s;
   void *ws = nullptr;
   size_t ws_bytes = 0;
+  bool recs_ready = false;  // W.recs holds every history's path record
 };
 
 pct_status check_ws(void *ws, size_t ws_bytes, int64_t M, int64_t n, int64_t plan_bt = 0) {
@@ -241,7 +242,8 @@ pct_status do_trace(Ctx &c, const pct_grid *g, pct_rows *rows) {
   if (c.n == 0) HIPCHECK(pct::launch_scan_rows(rows->row_ptr, 0, 0, c.W.scan, c.s));
   for (int64_t i0 = 0; i0 < c.n; i0 += st_rows) {
     const int64_t nr = std::min<int64_t>(st_rows, c.n - i0);
-    PROF(PCT_K_TRACE_PATH, pct::launch_trace_stage(c.P, c.H, i0, nr, rows->row_ptr + i0 + 1,
+    PROF(PCT_K_PATH_SETUP, pct::launch_path_setup(c.P, c.H, nullptr, i0, nr, c.n, c.W.recs, c.W.status, true, c.s));
+    PROF(PCT_K_TRACE_PATH, pct::launch_trace_stage(c.P, c.W.recs, i0, nr, rows->row_ptr + i0 + 1,
                                                    fill ? c.W.st_idx : nullptr, c.W.st_len, rows->norm2,
                                                    c.W.status, c.s));
     HIPCHECK(pct::launch_scan_rows(rows->row_ptr, i0, nr, c.W.scan, c.s));
@@ -273,6 +275,30 @@ int64_t fused_count_elems(int64_t M, int64_t n, const pct_sweep_params *p) {
   return nb * M;
 }
 
+// Fused calls: when the workspace holds one path record per history, carve
+// it so (keeping the per-block counts when blk > 0 and they fit too).
+bool carve_fused(Ctx &c, int64_t blk) {
+  if (blk > 0 && pct::workspace_bytes(c.M, c.n, 0, 0, blk, true) <= c.ws_bytes) {
+    c.W = pct::carve_workspace(c.ws, c.M, c.n, 0, 0, blk, true);
+    return true;
+  }
+  if (pct::workspace_bytes(c.M, c.n, 0, 0, 0, true) <= c.ws_bytes) {
+    c.W = pct::carve_workspace(c.ws, c.M, c.n, 0, 0, 0, true);
+    return true;
+  }
+  if (blk > 0 && pct::workspace_bytes(c.M, c.n, 0, 0, blk) <= c.ws_bytes)
+    c.W = pct::carve_workspace(c.ws, c.M, c.n, 0, 0, blk);
+  return false;
+}
+
+// every history's path set-up, once per call (the records do not depend on x)
+pct_status prepare_records(Ctx &c) {
+  if (c.recs_ready || c.W.rec_rows < c.n || c.n == 0) return PCT_OK;
+  PROF(PCT_K_PATH_SETUP, pct::launch_path_setup(c.P, c.H, nullptr, 0, c.n, c.n, c.W.recs, c.W.status, false, c.s));
+  c.recs_ready = true;
+  return PCT_OK;
+}
+
 // count_mode 0: s_j formed with atomics in every block; 1: formed and stored
 // per block; 2: read from the stored counts
 pct_status do_sweep(Ctx &c, const pct_grid *g, const pct_rows *rows, float *x, const pct_sweep_params *p,
@@ -293,9 +319,17 @@ pct_status do_sweep(Ctx &c, const pct_grid *g, const pct_rows *rows, float *x, c
       PROF(PCT_K_PROJECT, pct::launch_project_cached(rows->row_ptr, rows->idx, rows->len, rows->len_dtype, unit,
                                                      rows->norm2, c.H.wepl, p->order, first, count, c.n, c.M, x,
                                                      c.W.num, c.W.cnt, c.W.status, c.s));
-    else
-      PROF(PCT_K_PROJECT, pct::launch_project_fused(c.P, c.H, p->order, first, count, c.n, x, c.W.num,
+    else if (c.recs_ready)
+      PROF(PCT_K_PROJECT, pct::launch_project_fused(c.P, c.W.recs, p->order, first, c.n, true, count, x, c.W.num,
                                                     count_mode == 2 ? nullptr : c.W.cnt, c.W.status, c.s));
+    else
+      for (int64_t s0 = 0; s0 < count; s0 += pct::kStageRows) {
+        const int64_t cs = std::min<int64_t>(pct::kStageRows, count - s0);
+        PROF(PCT_K_PATH_SETUP, pct::launch_path_setup(c.P, c.H, p->order, first + s0, cs, c.n, c.W.recs,
+                                                      c.W.status, false, c.s));
+        PROF(PCT_K_PROJECT, pct::launch_project_fused(c.P, c.W.recs, nullptr, 0, c.n, false, cs, x, c.W.num,
+                                                      count_mode == 2 ? nullptr : c.W.cnt, c.W.status, c.s));
+      }
     PROF(PCT_K_APPLY, pct::launch_apply_counts(x, c.W.num, c.W.cnt, count_mode ? c.W.blk_cnt + blk * c.M : nullptr,
                                                count_mode, p->hull_mask, c.M, p->lambda, c.W.status, c.s));
   }
@@ -306,8 +340,19 @@ pct_status do_residual(Ctx &c, const pct_grid *g, const pct_rows *rows, const fl
   if (rows)
     PROF(PCT_K_RESIDUAL, pct::launch_residual_cached(rows->row_ptr, rows->idx, rows->len, rows->len_dtype,
                                                      len_unit(g), c.H.wepl, c.n, c.M, x, c.W.partials, out, c.s));
-  else
-    PROF(PCT_K_RESIDUAL, pct::launch_residual_fused(c.P, c.H, c.n, x, c.W.partials, c.W.status, out, c.s));
+  else if (c.recs_ready) {
+    PROF(PCT_K_RESIDUAL, pct::launch_residual_fused(c.P, c.W.recs, c.n, x, c.W.partials, c.W.status, false, c.s));
+    HIPCHECK(pct::launch_residual_final(c.W.partials, pct::kResidFusedGrid, out, c.s));
+  } else {
+    for (int64_t i0 = 0; i0 < c.n; i0 += pct::kStageRows) {
+      const int64_t cs = std::min<int64_t>(pct::kStageRows, c.n - i0);
+      PROF(PCT_K_PATH_SETUP, pct::launch_path_setup(c.P, c.H, nullptr, i0, cs, c.n, c.W.recs, c.W.status, false,
+                                                    c.s));
+      PROF(PCT_K_RESIDUAL, pct::launch_residual_fused(c.P, c.W.recs, cs, x, c.W.partials, c.W.status, i0 > 0, c.s));
+    }
+    if (c.n == 0) HIPCHECK(pct::launch_fill_f64(c.W.partials, pct::kResidFusedGrid, 0.0, c.s));
+    HIPCHECK(pct::launch_residual_final(c.W.partials, pct::kResidFusedGrid, out, c.s));
+  }
   return PCT_OK;
 }
 
@@ -587,12 +632,19 @@ namespace pct {
 // fixed part (status, DROP accumulators, partial sums, scan chunks) followed
 // by one shared tail: the plan sizing counters during a plan build, the
 // staged rows during a trace (never both at once)
-size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots, int64_t blk_cnt_elems) {
+static int64_t rec_rows_for(int64_t n_hist, bool recs_all) {
+  const int64_t n = std::max<int64_t>(n_hist, 0);
+  return recs_all ? n : std::min<int64_t>(n, kStageRows);
+}
+
+size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots, int64_t blk_cnt_elems,
+                       bool recs_all) {
   size_t b = align_up(4 * sizeof(uint32_t));
   b += align_up((size_t)M * sizeof(float));
   b += align_up((size_t)M * sizeof(uint32_t));
   b += align_up((size_t)kMaxPartials * sizeof(double));
   b += align_up((size_t)((n_hist + kScanChunk - 1) / kScanChunk + 2) * sizeof(int64_t));
+  b += align_up((size_t)rec_rows_for(n_hist, recs_all) * kPathRecBytes);
   const size_t plan_b = (size_t)(plan_bt > 0 ? plan_bt : 0) * sizeof(int64_t);
   const size_t stage_b = 2 * align_up((size_t)(stage_slots > 0 ? stage_slots : 0) * 4);
   b += align_up(std::max(plan_b, stage_b));
@@ -601,7 +653,7 @@ size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage
 }
 
 Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots,
-                          int64_t blk_cnt_elems) {
+                          int64_t blk_cnt_elems, bool recs_all) {
   char *p = static_cast<char *>(base);
   Workspace w;
   w.status = reinterpret_cast<uint32_t *>(p);
@@ -614,6 +666,9 @@ Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt
   p += align_up((size_t)kMaxPartials * sizeof(double));
   w.scan = reinterpret_cast<int64_t *>(p);
   p += align_up((size_t)((n_hist + kScanChunk - 1) / kScanChunk + 2) * sizeof(int64_t));
+  w.recs = p;
+  w.rec_rows = rec_rows_for(n_hist, recs_all);
+  p += align_up((size_t)w.rec_rows * kPathRecBytes);
   w.plan_scratch = reinterpret_cast<int64_t *>(p);
   w.st_idx = reinterpret_cast<int32_t *>(p);
   w.st_len = reinterpret_cast<float *>(p + align_up((size_t)(stage_slots > 0 ? stage_slots : 0) * 4));
@@ -639,7 +694,7 @@ size_t pct_workspace_size(const pct_grid *grid, const pct_geom *geom, const pct_
   if (geom && !fused && make_params(grid, geom, P) == PCT_OK)
     stage = std::min<int64_t>(n_hist, pct::kStageRows) * P.emax;
   const int64_t blk = fused ? fused_count_elems(grid_voxels(grid), n_hist, params) : 0;
-  return pct::workspace_bytes(grid_voxels(grid), n_hist, plan_bt, stage, blk);
+  return pct::workspace_bytes(grid_voxels(grid), n_hist, plan_bt, stage, blk, fused != 0);
 }
 
 pct_status pct_mlp_trace(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist, pct_rows *rows,
@@ -664,6 +719,10 @@ pct_status pct_project_sweep(const pct_grid *grid, const pct_geom *geom, const p
   if ((r = check_params(params, rows != nullptr)) != PCT_OK) return r;
   if (!x) return fail(PCT_EINVAL, "x is NULL");
   HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
+  if (!rows && params->algo == 1 && carve_fused(c, 0)) {
+    HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
+    if ((r = prepare_records(c)) != PCT_OK) return r;
+  }
   if ((r = do_sweep(c, grid, rows, x, params)) != PCT_OK) return r;
   if (resid_out) {
     if ((r = do_residual(c, grid, rows, x, resid_out)) != PCT_OK) return r;
@@ -753,11 +812,10 @@ pct_status pct_reconstruct(const pct_grid *grid, const pct_geom *geom, const pct
     if (trace_st != PCT_OK && trace_st != PCT_ENONFINITE) return trace_st;
   } else {
     const int64_t blk = fused_count_elems(c.M, c.n, params);
-    if (blk > 0 && pct::workspace_bytes(c.M, c.n, 0, 0, blk) <= ws_bytes) {
-      c.W = pct::carve_workspace(workspace, c.M, c.n, 0, 0, blk);
-      count_mode = 1;
-    }
+    const bool all = params->algo == 1 && carve_fused(c, blk);
+    if (c.W.blk_cnt) count_mode = 1;
     HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
+    if (all && (r = prepare_records(c)) != PCT_OK) return r;
   }
   pct::PlanView V;
   if (plan) {
@@ -805,6 +863,10 @@ pct_status pct_residual(const pct_grid *grid, const pct_geom *geom, const pct_hi
   if (r != PCT_OK) return r;
   if (rows && (r = check_rows(rows, c.n, true)) != PCT_OK) return r;
   if (!x || !out) return fail(PCT_EINVAL, "x / out is NULL");
+  if (!rows && carve_fused(c, 0)) {
+    HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
+    if ((r = prepare_records(c)) != PCT_OK) return r;
+  }
   return do_residual(c, grid, rows, x, out);
 }
 

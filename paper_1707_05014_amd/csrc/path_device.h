@@ -179,6 +179,25 @@ struct ProtonPath {
   R FL[3];               // F_p(L), p = 0, 1, 2 (see mlp_point)
 };
 
+// The per-proton set-up as stored by k_path_setup (one thread per proton)
+// and read by the path kernels (one wavefront per proton, scalar loads):
+// the fifteen ProtonPath values, the segment count (0: no path) and b_i.
+template <typename R>
+struct PathRec {
+  R v[15];   // u0, L, c, s, t0, st0, v0, sv0, dtt, dts, dvt, dvs, FL0, FL1, FL2
+  int32_t K;
+  float b;
+};
+static_assert(sizeof(PathRec<double>) <= kPathRecBytes, "path record larger than its workspace slot");
+
+template <typename T>
+__device__ __forceinline__ const T *uniform_ptr(const T *p) {
+  const uint64_t u = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  return reinterpret_cast<const T *>(((uint64_t)hi << 32) | lo);
+}
+
 // Horner: d^(M+1) * sum_n c[n] d^n
 template <typename R, int M>
 __device__ __forceinline__ R moment(const R *c, R d) {
@@ -191,9 +210,9 @@ __device__ __forceinline__ R moment(const R *c, R d) {
   return acc * dp;
 }
 
-// Per-proton set-up (wave-uniform values, computed redundantly by all lanes).
-// The hull intersections and end states are found in double for both path
-// precisions: they are per proton, and near-tangent lines are ill-conditioned.
+// Per-proton set-up, computed by one thread (k_path_setup).  The hull
+// intersections and end states are found in double for both path precisions:
+// they are per proton, and near-tangent lines are ill-conditioned.
 template <typename R>
 __device__ __forceinline__ void setup_path(const PathParams &P, const R *cF, const float h[10], ProtonPath<R> &pp) {
   pp.valid = false;
@@ -235,12 +254,31 @@ __device__ __forceinline__ void setup_path(const PathParams &P, const R *cF, con
   pp.FL[1] = moment<R, 1>(cF + 8, pp.L);
   pp.FL[2] = moment<R, 2>(cF + 16, pp.L);
   pp.valid = true;
-  // every lane computed the same values: keep one copy in scalar registers
-  pp.K = uniform(pp.K);
-  pp.u0 = uniform(pp.u0); pp.L = uniform(pp.L); pp.c = uniform(pp.c); pp.s = uniform(pp.s);
-  pp.t0 = uniform(pp.t0); pp.st0 = uniform(pp.st0); pp.v0 = uniform(pp.v0); pp.sv0 = uniform(pp.sv0);
-  pp.dtt = uniform(pp.dtt); pp.dts = uniform(pp.dts); pp.dvt = uniform(pp.dvt); pp.dvs = uniform(pp.dvs);
-  pp.FL[0] = uniform(pp.FL[0]); pp.FL[1] = uniform(pp.FL[1]); pp.FL[2] = uniform(pp.FL[2]);
+}
+
+template <typename R>
+__device__ __forceinline__ void store_record(const ProtonPath<R> &pp, float b, PathRec<R> *rec) {
+  PathRec<R> r;
+  const R vals[15] = {pp.u0, pp.L, pp.c, pp.s, pp.t0, pp.st0, pp.v0, pp.sv0,
+                      pp.dtt, pp.dts, pp.dvt, pp.dvs, pp.FL[0], pp.FL[1], pp.FL[2]};
+#pragma unroll
+  for (int q = 0; q < 15; ++q) r.v[q] = pp.valid ? vals[q] : (R)0;
+  r.K = pp.valid ? pp.K : 0;
+  r.b = b;
+  *rec = r;
+}
+
+// the record of the wavefront's proton, in scalar registers
+template <typename R>
+__device__ __forceinline__ void load_record(const PathRec<R> *rec, ProtonPath<R> &pp, float &b) {
+  const PathRec<R> *r = uniform_ptr(rec);
+  pp.K = uniform(r->K);
+  pp.valid = pp.K > 0;
+  pp.u0 = uniform(r->v[0]); pp.L = uniform(r->v[1]); pp.c = uniform(r->v[2]); pp.s = uniform(r->v[3]);
+  pp.t0 = uniform(r->v[4]); pp.st0 = uniform(r->v[5]); pp.v0 = uniform(r->v[6]); pp.sv0 = uniform(r->v[7]);
+  pp.dtt = uniform(r->v[8]); pp.dts = uniform(r->v[9]); pp.dvt = uniform(r->v[10]); pp.dvs = uniform(r->v[11]);
+  pp.FL[0] = uniform(r->v[12]); pp.FL[1] = uniform(r->v[13]); pp.FL[2] = uniform(r->v[14]);
+  b = uniform(r->b);
 }
 
 // MLP lateral offsets (t, v) at depth d1 from the hull entry, 0 < d1 < L.
@@ -337,15 +375,14 @@ __device__ __forceinline__ int walk_segment(const PathParams &P, int bx, int by,
   return kMaxPieces + 1;
 }
 
-// Build the row of one proton in the wavefront's LDS slice (s_vox, s_len,
-// s_aux of P.emax entries each); cF = the staged prior tables.  Returns the entry count (wave-uniform);
-// on a bound violation sets `status` bits and returns 0.
+// Build the row of one proton (set-up pp, wave-uniform) in the wavefront's
+// LDS slice (s_vox, s_len, s_aux of P.emax entries each); cF = the staged
+// prior tables.  Returns the entry count (wave-uniform); on a bound violation
+// sets `status` bits and returns 0.
 template <typename R>
-__device__ int build_row(const PathParams &P, const R *cF, const float h[10], int *s_vox, float *s_len, int *s_aux,
-                         uint32_t *status) {
+__device__ int build_row(const PathParams &P, const R *cF, const ProtonPath<R> &pp, int *s_vox, float *s_len,
+                         int *s_aux, uint32_t *status) {
   const int lane = wave_lane();
-  ProtonPath<R> pp;
-  setup_path<R>(P, cF, h, pp);
   if (!pp.valid) return 0;
   if (pp.K > P.kmax) {
     if (lane == 0) atomicOr(status, kStOverflow);

@@ -10,6 +10,7 @@ namespace pct {
 
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kSegPerRound = 63;   // path segments a wavefront traces per round (64 points)
+constexpr int kPathRecBytes = 128;    // workspace slot of one proton's path set-up record
 constexpr int kMaxPieces = 6;      // voxel pieces one segment can yield (<= 4 when step <= voxel)
 constexpr int kDedupWindow = 8;    // look-back for voxels revisited after a short excursion
 
@@ -60,6 +61,8 @@ struct Workspace {
   int32_t *st_idx;       // [stage_slots] staged row entries of one chunk of rows (trace)
   float *st_len;         // [stage_slots]
   uint16_t *blk_cnt;     // [blk_cnt_elems] per-block voxel counts s_j of the fused sweep (or NULL)
+  void *recs;            // [rec_rows] path set-up records (kPathRecBytes each)
+  int64_t rec_rows;      // n (one record per history, fused sweeps) or min(n, kStageRows) (chunks)
 };
 constexpr int64_t kMaxPartials = 1 << 16;
 constexpr int64_t kScanChunk = 4096;
@@ -68,10 +71,12 @@ constexpr int64_t kStageRows = 1 << 20;  // rows traced per staging chunk
 // the per-block counts of the fused sweep (n_blocks x M uint16) are kept only
 // up to this size; above it the counts are re-formed with atomics every sweep
 constexpr int64_t kMaxBlkCntBytes = int64_t(32) << 30;
+// recs_all: one path record per history (the fused sweeps set every proton up
+// once per call), else records for one chunk of kStageRows rows
 size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots = 0,
-                       int64_t blk_cnt_elems = 0);
+                       int64_t blk_cnt_elems = 0, bool recs_all = false);
 Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots = 0,
-                          int64_t blk_cnt_elems = 0);
+                          int64_t blk_cnt_elems = 0, bool recs_all = false);
 
 // ---- tiled sweep plan (cached rows regrouped by block and spatial tile)
 constexpr int kTX = 16, kTY = 16, kTZ = 8;           // tile of 2048 voxels
@@ -138,7 +143,12 @@ hipError_t launch_plan_resid_rows(const PlanView &V, int64_t b, double *partials
 hipError_t launch_sum_partials(const double *partials, int64_t np, double *out, int sqrt_it, hipStream_t s);
 
 // launchers (return hipError_t of the launch)
-hipError_t launch_trace_stage(const PathParams &P, const HistPtrs &H, int64_t i0, int64_t nrows, int64_t *cnt,
+// per-proton set-up records of rows [first, first + count) (through order
+// when given) into recs (kPathRecBytes each)
+hipError_t launch_path_setup(const PathParams &P, const HistPtrs &H, const int64_t *order, int64_t first,
+                             int64_t count, int64_t n, void *recs, uint32_t *status, bool flag_nonfinite,
+                             hipStream_t s);
+hipError_t launch_trace_stage(const PathParams &P, const void *recs, int64_t i0, int64_t nrows, int64_t *cnt,
                               int32_t *st_idx, float *st_len, double *norm2, uint32_t *status, hipStream_t s);
 hipError_t launch_trace_compact(int64_t i0, int64_t nrows, const int64_t *row_ptr, const int32_t *st_idx,
                                 const float *st_len, int emax, int32_t *idx, void *len, int32_t len_dtype,
@@ -155,8 +165,11 @@ hipError_t launch_project_cached(const int64_t *row_ptr, const int32_t *idx, con
                                  float len_unit, const double *norm2, const float *b, const int64_t *order,
                                  int64_t first, int64_t count, int64_t n, int64_t M, const float *x, float *num,
                                  uint32_t *cnt, uint32_t *status, hipStream_t s);
-hipError_t launch_project_fused(const PathParams &P, const HistPtrs &H, const int64_t *order, int64_t first,
-                                int64_t count, int64_t n, const float *x, float *num, uint32_t *cnt,
+// rows of block positions [first, first + count): records recs[order[first + q]]
+// (global: one record per history) or recs[q] (one chunk's records); cnt
+// NULL: the block counts are not formed
+hipError_t launch_project_fused(const PathParams &P, const void *recs, const int64_t *order, int64_t first, int64_t n,
+                                bool global, int64_t count, const float *x, float *num, uint32_t *cnt,
                                 uint32_t *status, hipStream_t s);
 // mode 0: counts from cnt (cleared); 1: also store them as uint16 into blk_cnt;
 // 2: counts read from blk_cnt (cnt unused)
@@ -170,8 +183,12 @@ hipError_t launch_art(const int64_t *row_ptr, const int32_t *idx, const void *le
 hipError_t launch_residual_cached(const int64_t *row_ptr, const int32_t *idx, const void *len, int32_t len_dtype,
                                   float len_unit, const float *b, int64_t n, int64_t M, const float *x,
                                   double *partials, double *out, hipStream_t s);
-hipError_t launch_residual_fused(const PathParams &P, const HistPtrs &H, int64_t n, const float *x,
-                                 double *partials, uint32_t *status, double *out, hipStream_t s);
+// one chunk of the fused residual (kResidFusedGrid partial sums, stored or,
+// with accumulate, added), then the final ordered sum
+constexpr int kResidFusedGrid = 4096;
+hipError_t launch_residual_fused(const PathParams &P, const void *recs, int64_t n, const float *x, double *partials,
+                                 uint32_t *status, bool accumulate, hipStream_t s);
+hipError_t launch_residual_final(const double *partials, int64_t np, double *out, hipStream_t s);
 // *out = NaN if any status bit is set (asynchronous error report)
 hipError_t launch_poison_on_status(double *out, const uint32_t *status, hipStream_t s);
 hipError_t launch_roi(const float *x, const uint8_t *labels, int64_t M, int32_t n_labels, double *sums,

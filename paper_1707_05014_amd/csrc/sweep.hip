@@ -62,11 +62,14 @@ __global__ void __launch_bounds__(256) k_project_cached(const int64_t *__restric
 // one wavefront per proton of the block: the row is rebuilt in LDS.  Without
 // COUNT the block's voxel counts s_j are not formed (they were stored by an
 // earlier sweep), which halves the global atomics.
+// Records: with `global` they are indexed by history (recs[order[first + q]],
+// an order entry outside [0, n) sets kStBadIndex), else by position in the
+// chunk (recs[q]).
 template <typename R, bool COUNT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_project_fused(PathParams P, HistPtrs H, const int64_t *__restrict__ order,
-                                                       int64_t first, int64_t count, int64_t n,
-                                                       const float *__restrict__ x, float *num, uint32_t *cnt,
-                                                       uint32_t *status) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_project_fused(PathParams P, const PathRec<R> *__restrict__ recs,
+                                                       const int64_t *__restrict__ order, int64_t first, int64_t n,
+                                                       int global, int64_t count, const float *__restrict__ x,
+                                                       float *num, uint32_t *cnt, uint32_t *status) {
   extern __shared__ int smem[];
   const int wid = threadIdx.x / kWave;
   const int lane = wave_lane();
@@ -77,14 +80,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   stage_prior<R>(P, s_cF);
   const int64_t stride = (int64_t)gridDim.x * P.waves_per_block;
   for (int64_t q = (int64_t)blockIdx.x * P.waves_per_block + wid; q < count; q += stride) {
-    const int64_t i = order ? order[first + q] : first + q;
-    if ((uint64_t)i >= (uint64_t)n) {
-      if (lane == 0) atomicOr(status, kStBadIndex);
-      continue;
+    int64_t ri = q;
+    if (global) {
+      ri = order ? order[first + q] : first + q;
+      if ((uint64_t)ri >= (uint64_t)n) {
+        if (lane == 0) atomicOr(status, kStBadIndex);
+        continue;
+      }
     }
-    float h[10];
-    load_history(H, i, h);
-    const int ne = build_row<R>(P, s_cF, h, s_vox, s_len, s_aux, status);
+    ProtonPath<R> pp;
+    float b;
+    load_record<R>(recs + ri, pp, b);
+    const int ne = build_row<R>(P, s_cF, pp, s_vox, s_len, s_aux, status);
     if (ne == 0) continue;
     float d = 0.0f;
     double n2 = 0.0;
@@ -95,7 +102,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     }
     d = wave_sum_f32(d);
     n2 = wave_sum_f64(n2);
-    const float r = (float)(((double)h[9] - (double)d) / n2);
+    const float r = (float)(((double)b - (double)d) / n2);
     for (int e = lane; e < ne; e += kWave) {
       const int j = s_vox[e];
       atomicAdd(&num[j], r * s_len[e]);
@@ -221,10 +228,12 @@ __global__ void __launch_bounds__(256) k_resid_cached(const int64_t *__restrict_
   if (threadIdx.x == 0) partials[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
+// rows of one chunk (set-up records recs[0, n)); workgroup g's sum is stored
+// to partials[g] (accumulate = 0) or added to it (later chunks)
 template <typename R>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_resid_fused(PathParams P, HistPtrs H, int64_t n,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_resid_fused(PathParams P, const PathRec<R> *__restrict__ recs, int64_t n,
                                                      const float *__restrict__ x, double *partials,
-                                                     uint32_t *status) {
+                                                     uint32_t *status, int accumulate) {
   extern __shared__ int smem[];
   __shared__ double red[4];
   const int wid = threadIdx.x / kWave;
@@ -237,14 +246,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   double acc = 0.0;
   const int64_t stride = (int64_t)gridDim.x * P.waves_per_block;
   for (int64_t i = (int64_t)blockIdx.x * P.waves_per_block + wid; i < n; i += stride) {
-    float h[10];
-    load_history(H, i, h);
-    const int ne = build_row<R>(P, s_cF, h, s_vox, s_len, s_aux, status);
+    ProtonPath<R> pp;
+    float b;
+    load_record<R>(recs + i, pp, b);
+    const int ne = build_row<R>(P, s_cF, pp, s_vox, s_len, s_aux, status);
     if (ne == 0) continue;
     float d = 0.0f;
     for (int e = lane; e < ne; e += kWave) d = fmaf(s_len[e], x[s_vox[e]], d);
     d = wave_sum_f32(d);
-    const double rr = (double)d - (double)h[9];
+    const double rr = (double)d - (double)b;
     acc += rr * rr;
   }
   if (lane == 0) red[wid] = acc;
@@ -252,7 +262,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int w = 0; w < P.waves_per_block; ++w) s += red[w];
-    partials[blockIdx.x] = s;
+    partials[blockIdx.x] = accumulate ? partials[blockIdx.x] + s : s;
   }
 }
 
@@ -330,26 +340,29 @@ hipError_t launch_project_cached(const int64_t *row_ptr, const int32_t *idx, con
   return hipGetLastError();
 }
 
-hipError_t launch_project_fused(const PathParams &P, const HistPtrs &H, const int64_t *order, int64_t first,
-                                int64_t count, int64_t n, const float *x, float *num, uint32_t *cnt,
+hipError_t launch_project_fused(const PathParams &P, const void *recs, const int64_t *order, int64_t first, int64_t n,
+                                bool global, int64_t count, const float *x, float *num, uint32_t *cnt,
                                 uint32_t *status, hipStream_t s) {
+  const int gl = global ? 1 : 0;
   if (count <= 0) return hipSuccess;
   const size_t lds = (size_t)P.waves_per_block * 3 * P.emax * sizeof(int);
   const unsigned grid = grid_for(count, P.waves_per_block, 1u << 20);
   const dim3 g(grid), b(P.waves_per_block * kWave);
   if (P.path_fp32) {
+    const auto *r = static_cast<const PathRec<float> *>(recs);
     if (cnt)
-      hipLaunchKernelGGL((k_project_fused<float, true>), g, b, lds, s, P, H, order, first, count, n, x, num, cnt,
+      hipLaunchKernelGGL((k_project_fused<float, true>), g, b, lds, s, P, r, order, first, n, gl, count, x, num, cnt,
                          status);
     else
-      hipLaunchKernelGGL((k_project_fused<float, false>), g, b, lds, s, P, H, order, first, count, n, x, num, cnt,
+      hipLaunchKernelGGL((k_project_fused<float, false>), g, b, lds, s, P, r, order, first, n, gl, count, x, num, cnt,
                          status);
   } else {
+    const auto *r = static_cast<const PathRec<double> *>(recs);
     if (cnt)
-      hipLaunchKernelGGL((k_project_fused<double, true>), g, b, lds, s, P, H, order, first, count, n, x, num, cnt,
+      hipLaunchKernelGGL((k_project_fused<double, true>), g, b, lds, s, P, r, order, first, n, gl, count, x, num, cnt,
                          status);
     else
-      hipLaunchKernelGGL((k_project_fused<double, false>), g, b, lds, s, P, H, order, first, count, n, x, num, cnt,
+      hipLaunchKernelGGL((k_project_fused<double, false>), g, b, lds, s, P, r, order, first, n, gl, count, x, num, cnt,
                          status);
   }
   return hipGetLastError();
@@ -400,17 +413,23 @@ hipError_t launch_residual_cached(const int64_t *row_ptr, const int32_t *idx, co
   return hipGetLastError();
 }
 
-hipError_t launch_residual_fused(const PathParams &P, const HistPtrs &H, int64_t n, const float *x,
-                                 double *partials, uint32_t *status, double *out, hipStream_t s) {
+// one chunk of rows of the fused residual (accumulate: add to the partial
+// sums of earlier chunks); the final sum is launch_residual_final
+hipError_t launch_residual_fused(const PathParams &P, const void *recs, int64_t n, const float *x, double *partials,
+                                 uint32_t *status, bool accumulate, hipStream_t s) {
   const size_t lds = (size_t)P.waves_per_block * 3 * P.emax * sizeof(int);
-  const unsigned grid = grid_for(n, P.waves_per_block, (unsigned)(kMaxPartials - 1));
+  const unsigned grid = kResidFusedGrid;
   if (P.path_fp32)
-    hipLaunchKernelGGL(k_resid_fused<float>, dim3(grid), dim3(P.waves_per_block * kWave), lds, s, P, H, n, x,
-                       partials, status);
+    hipLaunchKernelGGL(k_resid_fused<float>, dim3(grid), dim3(P.waves_per_block * kWave), lds, s, P,
+                       static_cast<const PathRec<float> *>(recs), n, x, partials, status, accumulate ? 1 : 0);
   else
-    hipLaunchKernelGGL(k_resid_fused<double>, dim3(grid), dim3(P.waves_per_block * kWave), lds, s, P, H, n, x,
-                       partials, status);
-  hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(256), 0, s, partials, (int64_t)grid, out);
+    hipLaunchKernelGGL(k_resid_fused<double>, dim3(grid), dim3(P.waves_per_block * kWave), lds, s, P,
+                       static_cast<const PathRec<double> *>(recs), n, x, partials, status, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_final(const double *partials, int64_t np, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(256), 0, s, partials, np, out);
   return hipGetLastError();
 }
 

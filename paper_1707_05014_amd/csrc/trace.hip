@@ -7,14 +7,49 @@
 
 namespace pct {
 
-// One wavefront per proton of rows [i0, i0 + nrows): the row is built in LDS,
-// its entry count goes to cnt[q] and, when st_idx is given, its entries to
-// the staging slots [q * emax, q * emax + count) with ||a_i||^2 (FP64, from
-// the FP32 lengths) to norm2[i0 + q].  A single path pass per proton: the
-// compaction below moves the staged rows into CSR order once the counts are
-// scanned.
+// Per-proton set-up of rows [first, first + count) (history order[first + q]
+// when order is given, else first + q), one thread per proton: hull entry and
+// exit, end states, the prior's moments at the path's end and b_i, into
+// recs[q].  Histories with non-finite values get no path (flagged when
+// flag_nonfinite); an order entry outside [0, n) sets kStBadIndex.
 template <typename R>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_trace_stage(PathParams P, HistPtrs H, int64_t i0, int64_t nrows,
+__global__ void __launch_bounds__(256) k_path_setup(PathParams P, HistPtrs H, const int64_t *__restrict__ order,
+                                                    int64_t first, int64_t count, int64_t n,
+                                                    PathRec<R> *__restrict__ recs, uint32_t *status,
+                                                    int flag_nonfinite) {
+  __shared__ R s_cF[24];
+  stage_prior<R>(P, s_cF);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += stride) {
+    const int64_t i = order ? order[first + q] : first + q;
+    ProtonPath<R> pp;
+    pp.valid = false;
+    pp.K = 0;
+    float b = 0.0f;
+    if ((uint64_t)i >= (uint64_t)n) {
+      atomicOr(status, kStBadIndex);
+    } else {
+      float h[10];
+      load_history(H, i, h);
+      bool fin = true;
+#pragma unroll
+      for (int k = 0; k < 10; ++k) fin = fin && isfinite(h[k]);
+      if (!fin && flag_nonfinite) atomicOr(status, kStNonFinite);
+      setup_path<R>(P, s_cF, h, pp);
+      b = h[9];
+    }
+    store_record<R>(pp, b, recs + q);
+  }
+}
+
+// One wavefront per proton of rows [i0, i0 + nrows) (set-up records
+// recs[0, nrows)): the row is built in LDS, its entry count goes to cnt[q]
+// and, when st_idx is given, its entries to the staging slots
+// [q * emax, q * emax + count) with ||a_i||^2 (FP64, from the FP32 lengths)
+// to norm2[i0 + q].  A single path pass per proton: the compaction below
+// moves the staged rows into CSR order once the counts are scanned.
+template <typename R>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_trace_stage(PathParams P, const PathRec<R> *__restrict__ recs, int64_t i0, int64_t nrows,
                                                      int64_t *cnt, int32_t *st_idx, float *st_len, double *norm2,
                                                      uint32_t *status) {
   extern __shared__ int smem[];
@@ -28,12 +63,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   const int64_t stride = (int64_t)gridDim.x * P.waves_per_block;
   for (int64_t q = (int64_t)blockIdx.x * P.waves_per_block + wid; q < nrows; q += stride) {
     const int64_t i = i0 + q;
-    float h[10];
-    load_history(H, i, h);
-    bool fin = true;
-    for (int k = 0; k < 10; ++k) fin = fin && isfinite(h[k]);
-    if (!fin && lane == 0) atomicOr(status, kStNonFinite);
-    const int c = build_row<R>(P, s_cF, h, s_vox, s_len, s_aux, status);
+    ProtonPath<R> pp;
+    float b;
+    load_record<R>(recs + q, pp, b);
+    const int c = build_row<R>(P, s_cF, pp, s_vox, s_len, s_aux, status);
     if (lane == 0) cnt[q] = c;
     if (!st_idx) continue;
     int32_t *di = st_idx + q * P.emax;
@@ -161,18 +194,32 @@ static inline unsigned grid_for(int64_t n, int per_block, unsigned cap) {
   return (unsigned)g;
 }
 
-hipError_t launch_trace_stage(const PathParams &P, const HistPtrs &H, int64_t i0, int64_t nrows, int64_t *cnt,
+hipError_t launch_path_setup(const PathParams &P, const HistPtrs &H, const int64_t *order, int64_t first,
+                             int64_t count, int64_t n, void *recs, uint32_t *status, bool flag_nonfinite,
+                             hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const unsigned grid = grid_for(count, 256, 1u << 16);
+  if (P.path_fp32)
+    hipLaunchKernelGGL(k_path_setup<float>, dim3(grid), dim3(256), 0, s, P, H, order, first, count, n,
+                       static_cast<PathRec<float> *>(recs), status, flag_nonfinite ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_path_setup<double>, dim3(grid), dim3(256), 0, s, P, H, order, first, count, n,
+                       static_cast<PathRec<double> *>(recs), status, flag_nonfinite ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace_stage(const PathParams &P, const void *recs, int64_t i0, int64_t nrows, int64_t *cnt,
                               int32_t *st_idx, float *st_len, double *norm2, uint32_t *status, hipStream_t s) {
   if (nrows <= 0) return hipSuccess;
   const unsigned threads = (unsigned)(P.waves_per_block * kWave);
   const size_t lds = (size_t)P.waves_per_block * 3 * P.emax * sizeof(int);
   const unsigned grid = grid_for(nrows, P.waves_per_block, 1u << 20);
   if (P.path_fp32)
-    hipLaunchKernelGGL(k_trace_stage<float>, dim3(grid), dim3(threads), lds, s, P, H, i0, nrows, cnt, st_idx, st_len,
-                       norm2, status);
+    hipLaunchKernelGGL(k_trace_stage<float>, dim3(grid), dim3(threads), lds, s, P,
+                       static_cast<const PathRec<float> *>(recs), i0, nrows, cnt, st_idx, st_len, norm2, status);
   else
-    hipLaunchKernelGGL(k_trace_stage<double>, dim3(grid), dim3(threads), lds, s, P, H, i0, nrows, cnt, st_idx,
-                       st_len, norm2, status);
+    hipLaunchKernelGGL(k_trace_stage<double>, dim3(grid), dim3(threads), lds, s, P,
+                       static_cast<const PathRec<double> *>(recs), i0, nrows, cnt, st_idx, st_len, norm2, status);
   return hipGetLastError();
 }
 

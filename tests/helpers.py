@@ -56,10 +56,12 @@ def merge_rows(row_ptr, idx, ln):
     return np.cumsum(new_ptr), (uk & ((1 << 31) - 1)).astype(np.int32), sums, dups
 
 
-def compare_rows(o_ptr, o_idx, o_len, g_ptr, g_idx, g_len):
+def compare_rows(o_ptr, o_idx, o_len, g_ptr, g_idx, g_len, len_tol=1e-4):
     """Compare two sets of fully merged, voxel-sorted rows.
     Returns dict: frac_identical (index sets), mismatch rows, max |dlen| on
-    common voxels of identical rows, max length of a voxel present on one side only."""
+    common voxels of identical rows, max length of a voxel present on one side
+    only, and frac_len_ok: the share of the rows with identical index sets
+    whose every length is within len_tol."""
     n = len(o_ptr) - 1
     ro = np.repeat(np.arange(n, dtype=np.int64), np.diff(o_ptr))
     rg = np.repeat(np.arange(n, dtype=np.int64), np.diff(g_ptr))
@@ -77,6 +79,10 @@ def compare_rows(o_ptr, o_idx, o_len, g_ptr, g_idx, g_len):
     d = np.abs(lo - lg)
     max_d_good = float(d[good[common_rows]].max()) if np.any(good[common_rows]) else 0.0
     only = np.concatenate([o_len[~in_g], g_len[~in_o]])
+    ok = good.copy()
+    ok[np.unique(common_rows[d > len_tol])] = False
+    n_good = int(good.sum())
     return dict(frac_identical=float(good.mean()) if n else 1.0, bad_rows=bad_rows,
+                frac_len_ok=float(ok.sum()) / n_good if n_good else 1.0,
                 max_dlen=max_d_good, max_dlen_all=float(d.max()) if len(d) else 0.0,
                 max_only_len=float(only.max()) if len(only) else 0.0)

@@ -64,6 +64,7 @@ def test_trace_parity_config1(cfg1):
     _say(f"  identical rows {cmp['frac_identical']:.6f}, max dlen {cmp['max_dlen']:.2e}, "
          f"max one-sided len {cmp['max_only_len']:.2e}, bad rows {cmp['bad_rows'][:10]}")
     assert cmp["frac_identical"] >= 0.9999
+    assert cmp["frac_len_ok"] >= 0.9999
     assert cmp["max_dlen"] <= LEN_TOL
     assert cmp["max_only_len"] <= SLIVER
     assert cmp["max_dlen_all"] <= SLIVER + LEN_TOL
@@ -273,6 +274,38 @@ def test_fused_kept_counts_match_counting(cfg1):
     small = lib.pct_workspace_size(ctypes.byref(grid), None, None, cfg.n, 1)
     n_blocks = -(-cfg.n // 7000)
     assert big - small >= n_blocks * cfg.grid.M * 2
+
+
+def test_fused_chunked_setup_matches(cfg1):
+    """With a workspace too small for one path record per history the fused
+    sweep sets up each block's protons just before projecting them; the
+    image equals the one-record-per-history form up to atomic order."""
+    cfg, h, R = cfg1
+    _say("fused: records per block vs per history")
+    order = synth.block_order(cfg.n, cfg.perm_seed)
+    mask = synth.hull_mask(cfg)
+    grid, geom = pct_args(cfg)
+    H = api.Histories.from_numpy(h)
+    p1 = api.sweep_params("drop", 7000, cfg.lam, 1, order=torch.from_numpy(order).cuda(),
+                          hull_mask=torch.from_numpy(mask).cuda())
+    xa = torch.from_numpy(mask.astype(np.float32)).cuda()
+    api.project_sweep(grid, geom, H, None, xa, p1)  # workspace sized for the fused form
+    lib = _lib.load()
+    small = lib.pct_workspace_size(ctypes.byref(grid), None, None, cfg.n, 0)
+    full = lib.pct_workspace_size(ctypes.byref(grid), None, None, cfg.n, 1)
+    assert full - small >= (cfg.n - min(cfg.n, 1 << 20)) * 128
+    ws = torch.empty(small, dtype=torch.uint8, device="cuda")
+    xb = torch.from_numpy(mask.astype(np.float32)).cuda()
+    hs = H.struct()
+    res = torch.empty(1, dtype=torch.float64, device="cuda")
+    code = lib.pct_project_sweep(ctypes.byref(grid), ctypes.byref(geom), ctypes.byref(hs), None, xb.data_ptr(),
+                                 ctypes.byref(p1.struct), res.data_ptr(), ws.data_ptr(), small,
+                                 torch.cuda.current_stream().cuda_stream)
+    assert code == _lib.PCT_OK
+    torch.cuda.synchronize()
+    ra = api.residual(grid, geom, H, None, xa)
+    assert _rel(xa.cpu().numpy().astype(np.float64), xb.cpu().numpy().astype(np.float64)) <= 1e-6
+    assert abs(float(res.item()) - ra) <= 1e-6 * ra
 
 
 # ------------------------------------------------------------- tiled plan
