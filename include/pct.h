@@ -155,7 +155,11 @@ typedef struct {
  * geom given and fused = 0 the size includes the row staging area of the
  * trace (up to 2^20 rows of the longest possible row, 8 bytes per entry); a
  * trace given less stages fewer rows at a time (PCT_ENOMEM below one row).
- * With fused = 1 and params of a DROP run of two or more sweeps the size
+ * With fused = 1 the size includes one path set-up record per history (128
+ * bytes: hull entry and exit, end states, the prior's moments at the exit,
+ * b_i), formed once per call and read by every later path pass; a fused call
+ * given less sets up each block's histories just before projecting them.
+ * With fused = 1 and params of a DROP run of two or more sweeps the size also
  * includes the per-block voxel counts s_j (n_blocks x M x 2 bytes, kept up to
  * 32 GiB): pct_reconstruct then forms them in its first sweep and reads them
  * back in the later ones instead of counting again with atomics (the block
