@@ -73,6 +73,8 @@ def parse():
                          "[:out|truth]' (target: the image after --ws-out sweeps, or the phantom itself)")
     ap.add_argument("--ws-out", type=int, default=20, help="sweeps of the training target")
     ap.add_argument("--ws-channels", type=str, default="16,32,64,64")
+    ap.add_argument("--ws-eval-2e8", action="store_true",
+                    help="also compare the starts on the 2e8-history workload (needs a network on the 1-sweep image)")
     ap.add_argument("--ws-eval-seeds", type=str, default="3,2,5000,5001,5002,5003",
                     help="held-out phantoms (3: the 2e8 workload's phantom, 2: the 1e7 workload's)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
@@ -698,7 +700,107 @@ def warmstart_experiment(args):
         "hull_start_time_to_1pct_s_total": hull_t,
         "variants": summary, "per_phantom": per_phantom,
     }
+    if args.ws_eval_2e8:
+        out["config3"] = warmstart_at_scale(args, nets, N)
     print(json.dumps(out), flush=True)
+
+
+def warmstart_at_scale(args, nets, n_train):
+    """The 2e8-history workload (phantom seed 3, rows rebuilt in every block)
+    from the hull start and from the warm start.  The first n_train histories
+    of the block order form the same number of blocks of the same size as one
+    whole sweep of a training phantom, so the network that reads the image
+    after one sweep reads the image after that first stretch here.  RSP error
+    checked after every tenth of a sweep (and at the network's output); time
+    = device time of the sweeps, the path set-up and the network."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1707_05014_amd import api
+    from paper_1707_05014_amd import warmstart as wsm
+
+    pick = [k for k, nt in enumerate(nets) if tuple(nt[0]) == (1,)]
+    if not pick:
+        return {"skipped": "no network reads the image after one sweep"}
+    net = nets[pick[0]][3]
+    dev = torch.device("cuda", 0)
+    cfg = synth.config(3)
+    N = cfg.n
+    g = cfg.grid
+    b = cfg.phantom.body
+    t0 = time.time()
+    h = synth.generate(cfg)
+    log(f"config 3: generated {N} histories in {time.time() - t0:.1f} s")
+    grid = api.make_grid(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.ox, g.oy, g.oz)
+    geom = api.make_geom(cfg.beam.u_in, cfg.beam.u_out, b.ax[0], b.ax[1], b.z0, b.z1, min(g.dx, g.dy, g.dz),
+                         synth.prior_poly(cfg.beam.E_kin))
+    H = api.Histories.from_numpy(h, device=dev)
+    del h
+    order = torch.from_numpy(synth.block_order(N, cfg.perm_seed)).to(dev)
+    Hp = H.permuted(order)  # block order made contiguous: stretches of it are plain slices
+    del H, order
+    mask = torch.from_numpy(synth.hull_mask(cfg)).to(dev)
+    labels = torch.from_numpy(synth.roi_labels(cfg)).to(dev)
+    true_rsp = synth.insert_rsp(cfg)
+    params = api.sweep_params("drop", cfg.block, cfg.lam, 1, hull_mask=mask)
+    tenth = N // 10
+
+    def rsp_err(x):
+        sums, cnts = api.roi_stats(x, labels, len(true_rsp))
+        means = (sums / cnts.clamp(min=1)).cpu().numpy()
+        return float(np.max(np.abs(means - true_rsp) / true_rsp))
+
+    def stretch(x, a, b_):
+        sub = api.Histories({k: v[a:b_] for k, v in Hp.t.items()})
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        api.project_sweep(grid, geom, sub, None, x, params)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    def run(x, start, t_start, errs, max_tenths=20):
+        t = t_start
+        pos = start
+        for k in range(max_tenths):
+            a = pos % N
+            b_ = min(a + tenth - (a % tenth), N)  # to the next tenth of the sweep
+            t += stretch(x, a, b_)
+            pos += b_ - a
+            errs.append([round(pos / N, 3), round(rsp_err(x), 5)])
+            if errs[-1][1] <= 0.01:
+                return pos / N, t
+        return None, None
+
+    x = mask.to(torch.float32)
+    e_h = []
+    f_h, t_h = run(x, 0, 0.0, e_h)
+    x = mask.to(torch.float32)
+    t_in = stretch(x, 0, n_train)
+    e_in = rsp_err(x)
+    snaps = {1: x}
+    inp = wsm.net_input(snaps, (1,), grid)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    x0 = wsm.warm_start(net, inp, mask)
+    torch.cuda.synchronize()
+    t_net = time.perf_counter() - t
+    e_net = rsp_err(x0)
+    e_w = []
+    if e_net <= 0.01:
+        f_w, t_w = n_train / N, t_in + t_net
+    else:
+        f_w, t_w = run(x0, n_train, t_in + t_net, e_w)
+    res = {"workload": f"config 3: {N} histories, phantom seed 3, blocks of {cfg.block}, rows rebuilt in every block",
+           "hull_start": {"sweeps_to_1pct": f_h, "time_to_1pct_s": round(t_h, 4) if t_h else None,
+                          "rsp_err_by_sweep_fraction": e_h},
+           "warm_start": {"histories_before_net": n_train, "rsp_err_before_net": round(e_in, 5),
+                          "net_ms": round(t_net * 1e3, 3), "rsp_err_of_net_output": round(e_net, 5),
+                          "sweeps_to_1pct": f_w, "time_to_1pct_s": round(t_w, 4) if t_w else None,
+                          "rsp_err_by_sweep_fraction": e_w},
+           "speedup_vs_hull_start": round(t_h / t_w, 3) if (t_h and t_w) else None}
+    log(f"config 3 warm start: {res}")
+    return res
 
 
 def cpu_baseline(cfg, n_sample):
