@@ -117,3 +117,49 @@ def test_roi_args_rejected():
     lib = _lib.load()
     assert lib.pct_roi_stats(None, None, 10, 3, None, None, None) == _lib.PCT_EINVAL
     assert lib.pct_roi_stats(None, None, 0, 0, None, None, None) == _lib.PCT_EINVAL
+
+
+def test_cnn_args_rejected_on_host():
+    """The warm-start network's entry points check sizes and pointers on the
+    host (nothing is launched for a bad call)."""
+    lib = _lib.load()
+    p = ctypes.c_void_p(1)  # never dereferenced: every call below fails validation first
+    E = _lib.PCT_EINVAL
+    assert lib.pct_cnn_conv3d(None, p, None, p, 1, 1, 4, 4, 4, None) == E
+    assert lib.pct_cnn_conv3d(p, p, None, p, 0, 1, 4, 4, 4, None) == E
+    assert lib.pct_cnn_conv3d(p, p, None, p, 1, 0, 4, 4, 4, None) == E
+    assert lib.pct_cnn_conv3d(p, p, None, p, 1, 1, 0, 4, 4, None) == E
+    assert lib.pct_cnn_conv3d_bwd_data(p, p, p, None, 1, 1, 4, 4, 4, None) == E
+    assert lib.pct_cnn_conv3d_bwd_weight(p, p, p, None, None, 1, 1, 4, 4, 4, None) == E
+    assert lib.pct_cnn_pool(p, p, 1, 3, 4, 4, None) == E  # odd depth
+    assert lib.pct_cnn_pool_bwd(p, p, 1, 4, 5, 4, None) == E
+    assert lib.pct_cnn_upsample(None, p, 1, 2, 2, 2, None) == E
+    assert lib.pct_cnn_relu(p, p, -1, None) == E
+    assert lib.pct_cnn_add(p, None, p, 10, None) == E
+    assert lib.pct_cnn_axpy(1.0, None, p, 10, None) == E
+    assert lib.pct_cnn_mask(p, None, p, 10, None) == E
+    assert lib.pct_cnn_mse(p, p, None, None, p, 10, None) == E
+    assert lib.pct_cnn_adam(p, p, p, p, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == E  # step < 1
+    assert lib.pct_cnn_adam(p, p, p, p, 10, -1.0, 0.9, 0.999, 1e-8, 1, None) == E
+    assert lib.pct_cnn_adam(p, p, p, p, 10, 1e-3, 1.0, 0.999, 1e-8, 1, None) == E
+    # zero-sized elementwise calls are valid no-ops
+    assert lib.pct_cnn_relu(None, None, 0, None) == _lib.PCT_OK
+    assert lib.pct_cnn_add(None, None, None, 0, None) == _lib.PCT_OK
+    # scratch sizes
+    assert lib.pct_cnn_wgrad_scratch(2, 3, 5, 18, 70) == 2 * 2 * 1 * 3 * (2 * 27 + 1)  # 2 x 2 x 1 tiles
+    assert lib.pct_cnn_wgrad_scratch(0, 3, 5, 18, 70) == 0
+    assert lib.pct_cnn_mse_scratch(257) == 2
+
+
+def test_workspace_grows_for_fused_records():
+    """A fused workspace holds one 128-byte path record per history (and,
+    for a DROP run of several sweeps, the per-block voxel counts)."""
+    lib = _lib.load()
+    g = _grid()
+    n = 3 << 20
+    cached = lib.pct_workspace_size(ctypes.byref(g), None, None, n, 0)
+    fused = lib.pct_workspace_size(ctypes.byref(g), None, None, n, 1)
+    assert fused - cached >= (n - (1 << 20)) * 128
+    p = api.sweep_params("drop", 1 << 20, 0.5, 4)
+    kept = lib.pct_workspace_size(ctypes.byref(g), None, ctypes.byref(p.struct), n, 1)
+    assert kept - fused >= 3 * g.nx * g.ny * g.nz * 2
