@@ -237,6 +237,47 @@ def test_edge_cases():
     assert torch.equal(small.row_ptr, full.row_ptr)
 
 
+def test_fused_edge_cases():
+    """Fused (rows rebuilt every sweep) with no histories, with an order
+    entry out of range, and with non-finite histories (no path; the image
+    stays finite)."""
+    _say("fused edge cases")
+    cfg = synth.config(1, n=3000)
+    h = synth.generate(cfg)
+    grid, geom = pct_args(cfg)
+    mask = synth.hull_mask(cfg)
+    tmask = torch.from_numpy(mask).cuda()
+    # no histories: the sweeps leave the hull start, the residuals are 0
+    H0 = api.Histories({k: torch.empty(0, dtype=torch.float32, device="cuda") for k in api.FIELDS})
+    x = torch.from_numpy(mask.astype(np.float32)).cuda()
+    res = api.reconstruct(grid, geom, H0, api.sweep_params("drop", 100, 0.5, 2, hull_mask=tmask), x)
+    assert res == [0.0, 0.0]
+    assert torch.equal(x, torch.from_numpy(mask.astype(np.float32)).cuda())
+    # an order entry out of range is reported (the sweep reads the records through the order)
+    H = api.Histories.from_numpy(h)
+    bad = torch.arange(cfg.n, dtype=torch.int64, device="cuda")
+    bad[17] = cfg.n + 5
+    pb = api.sweep_params("drop", 1000, 0.5, 2, order=bad, hull_mask=tmask)
+    with pytest.raises(_lib.PctError) as ei:
+        api.reconstruct(grid, geom, H, pb, torch.from_numpy(mask.astype(np.float32)).cuda())
+    assert ei.value.code == _lib.PCT_EINVAL
+    # non-finite histories get no path: same image as without them
+    hn = {k: v.copy() for k, v in h.items()}
+    hn["wepl"][5:9] = np.nan
+    hn["phi"][20] = np.inf
+    keep = np.ones(cfg.n, bool)
+    keep[[5, 6, 7, 8, 20]] = False
+    xa = torch.from_numpy(mask.astype(np.float32)).cuda()
+    api.reconstruct(grid, geom, api.Histories.from_numpy(hn), api.sweep_params("drop", cfg.n, 0.5, 1, hull_mask=tmask),
+                    xa)
+    xb = torch.from_numpy(mask.astype(np.float32)).cuda()
+    api.reconstruct(grid, geom, api.Histories.from_numpy({k: v[keep].copy() for k, v in h.items()}),
+                    api.sweep_params("drop", cfg.n, 0.5, 1, hull_mask=tmask), xb)
+    torch.cuda.synchronize()
+    assert torch.isfinite(xa).all()
+    assert _rel(xa.cpu().numpy().astype(np.float64), xb.cpu().numpy().astype(np.float64)) <= 1e-6
+
+
 def test_fused_equals_cached_single_block(cfg1):
     """The fused sweep and the cached sweep see the same rows: one DROP block
     over every proton gives the same update up to atomic summation order."""
