@@ -380,12 +380,6 @@ hipError_t launch_apply_counts(float *x, float *num, uint32_t *cnt, uint16_t *bl
   return hipGetLastError();
 }
 
-hipError_t launch_apply(float *x, float *num, uint32_t *cnt, const uint8_t *mask, int64_t M, float lambda,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_apply, dim3(grid_for(M, 256, 8192)), dim3(256), 0, s, x, num, cnt, mask, M, lambda);
-  return hipGetLastError();
-}
-
 hipError_t launch_art(const int64_t *row_ptr, const int32_t *idx, const void *len, int32_t len_dtype,
                       float len_unit, const double *norm2, const float *b, const int64_t *order, int64_t n,
                       int64_t M, float *x, const uint8_t *mask, float lambda, uint32_t *status, hipStream_t s) {
