@@ -349,6 +349,44 @@ def test_fused_chunked_setup_matches(cfg1):
     assert abs(float(res.item()) - ra) <= 1e-6 * ra
 
 
+def test_fused_workspace_forms_agree():
+    """pct_reconstruct (fused, 2 sweeps) with three workspace sizes: one path
+    record per history and the kept block counts; the counts but per-block
+    set-up (the records do not fit); neither.  Same image up to atomic
+    order.  Needs more than 2^20 histories so that the forms differ."""
+    n = (1 << 20) + 150_000
+    _say(f"fused workspace forms: {n} histories on the small grid")
+    cfg = synth.config(1, n=n)
+    h = synth.generate(cfg)
+    grid, geom = pct_args(cfg)
+    H = api.Histories.from_numpy(h)
+    mask = synth.hull_mask(cfg)
+    order = torch.from_numpy(synth.block_order(n, cfg.perm_seed)).cuda()
+    p = api.sweep_params("drop", 200_000, 0.5, 2, order=order, hull_mask=torch.from_numpy(mask).cuda())
+    lib = _lib.load()
+    full = lib.pct_workspace_size(ctypes.byref(grid), None, ctypes.byref(p.struct), n, 1)
+    counts_only = full - (n - (1 << 20)) * 128
+    minimal = lib.pct_workspace_size(ctypes.byref(grid), None, None, n, 0)
+    assert minimal < counts_only < full
+    images, resids = [], []
+    for size in (full, counts_only, minimal):
+        ws = torch.empty(size, dtype=torch.uint8, device="cuda")
+        x = torch.from_numpy(mask.astype(np.float32)).cuda()
+        res = (ctypes.c_double * 2)()
+        hs = H.struct()
+        code = lib.pct_reconstruct(ctypes.byref(grid), ctypes.byref(geom), ctypes.byref(hs), ctypes.byref(p.struct),
+                                   None, None, x.data_ptr(), res, ws.data_ptr(), size,
+                                   torch.cuda.current_stream().cuda_stream)
+        assert code == _lib.PCT_OK, lib.pct_last_error()
+        torch.cuda.synchronize()
+        images.append(x.cpu().numpy().astype(np.float64))
+        resids.append([res[0], res[1]])
+        del ws
+    for im, rs in zip(images[1:], resids[1:]):
+        assert _rel(im, images[0]) <= 1e-6
+        assert np.allclose(rs, resids[0], rtol=1e-6)
+
+
 # ------------------------------------------------------------- tiled plan
 def _plan_run(cfg, h, block, sweeps, order, mask, len_dtype=0, via_reconstruct=True):
     grid, geom = pct_args(cfg)
