@@ -2,18 +2,22 @@
 // spatial tiles of 16 x 16 x 8 voxels, so that one DROP block (paper Sec. 2.1)
 // runs without global atomics:
 //
-//   k_plan_dot     one wavefront per 64-entry chunk of a tile's list: gathers
-//                  x, multiplies by the lengths and sums each row's piece with a
-//                  segmented wave scan -> one partial dot product per piece;
+//   k_plan_dot     workgroups per (block, tile) list, x of the tile staged in
+//                  LDS: each 64-entry chunk multiplies lengths by x and sums
+//                  each piece (a run of one row's entries) with a segmented
+//                  wave scan -> one partial dot product per piece end, stored
+//                  next to the other partials of its row;
 //   k_plan_rows    one thread per row of the block: adds the row's partials in
-//                  path order (deterministic) -> r_i = (b_i - a_i.x)/||a_i||^2;
-//   k_plan_scatter one workgroup per tile: accumulates r_i a_ij and the row
-//                  counts s_j of the block in LDS, then applies
-//                  x_j += lambda num_j / s_j to the tile and writes it back.
+//                  a fixed order -> r_i = (b_i - a_i.x)/||a_i||^2;
+//   k_plan_scatter workgroups per (block, tile) list, r of the list's piece
+//                  ends staged in LDS: the voxel-sorted copy of the list gives
+//                  each voxel's run, reduced by segmented wave scans into
+//                  num_j and s_j, then x_j += lambda num_j / s_j.
 //
-// Entries are packed in 32 bits (row in block, voxel in tile, two flags) next
-// to their lengths (float32 or float16), so both passes stream the lists with
-// coalesced loads.
+// Entries are packed in 16 bits (voxel in tile, valid and piece-closing
+// flags) next to their lengths (float32 or float16), so both passes stream the
+// lists with coalesced loads; the scatter reads a voxel-sorted copy whose
+// 32-bit codes also carry the entry's piece-end ordinal.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -56,6 +60,7 @@ __device__ __forceinline__ int piece_end_lane(uint64_t starts, int s, int nv) {
 // the global counters once per workgroup.
 constexpr int kCountRows = 1024;
 constexpr int kCountHist = 4096;
+constexpr int kCountWin = 4;
 
 __global__ void __launch_bounds__(256) k_plan_count(const int64_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ idx,
@@ -84,30 +89,38 @@ __global__ void __launch_bounds__(256) k_plan_count(const int64_t *__restrict__ 
     }
     const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
     int64_t pieces = 0;
-    for (int64_t w = e0; w < e1; w += kWave) {
-      const int64_t e = w + lane;
-      const bool valid = e < e1;
-      int t = -1, local = 0;
-      if (valid) {
-        const int j = idx[e];
-        if ((uint32_t)j >= (uint64_t)M)
-          atomicOr(status, kStBadIndex);
-        else
-          t = voxel_tile(j, V, local);
+    // kCountWin windows of 64 entries per round, their loads issued together
+    for (int64_t w0 = e0; w0 < e1; w0 += kCountWin * kWave) {
+      int jv[kCountWin];
+#pragma unroll
+      for (int k = 0; k < kCountWin; ++k) {
+        const int64_t e = w0 + k * kWave + lane;
+        jv[k] = e < e1 ? idx[e] : -1;
       }
-      int tp = lane_prev(t);
-      if (lane == 0) tp = -2;
-      const bool start = valid && (lane == 0 || t != tp);
-      const uint64_t starts = __ballot(start);
-      const int nv = __popcll(__ballot(valid));
-      if (start && t >= 0) {
-        const int end = piece_end_lane(starts, lane, nv);
-        if (use_lds)
-          atomicAdd(&s_hist[t], (uint32_t)(end - lane));
-        else
-          atomicAdd((unsigned long long *)&bt_cnt[b * V.T + t], (unsigned long long)(end - lane));
+#pragma unroll
+      for (int k = 0; k < kCountWin; ++k) {
+        const bool valid = w0 + k * kWave + lane < e1;
+        int t = -1, local = 0;
+        if (valid) {
+          if ((uint32_t)jv[k] >= (uint64_t)M)
+            atomicOr(status, kStBadIndex);
+          else
+            t = voxel_tile(jv[k], V, local);
+        }
+        int tp = lane_prev(t);
+        if (lane == 0) tp = -2;
+        const bool start = valid && (lane == 0 || t != tp);
+        const uint64_t starts = __ballot(start);
+        const int nv = __popcll(__ballot(valid));
+        if (start && t >= 0) {
+          const int end = piece_end_lane(starts, lane, nv);
+          if (use_lds)
+            atomicAdd(&s_hist[t], (uint32_t)(end - lane));
+          else
+            atomicAdd((unsigned long long *)&bt_cnt[b * V.T + t], (unsigned long long)(end - lane));
+        }
+        pieces += __popcll(starts);
       }
-      pieces += __popcll(starts);
     }
     if (lane == 0) {
       if (row_cap) row_cap[q + 1] = 2 * pieces;
@@ -136,9 +149,14 @@ __global__ void k_copy_i64_u64(unsigned long long *dst, const int64_t *src, int6
 
 // Fill pass: place each piece in its (block, tile) list, record where each
 // row's pieces end, gather b and ||a||^2 into block order.  Wavefronts walk
-// the rows of the block order (persistent grid); the next rows' history
-// indices and CSR bounds are loaded a row ahead so their latency overlaps
-// the current row.
+// the rows of the block order (persistent grid).  A row is taken kFillWin
+// windows of 64 entries at a time: the windows' entry loads are issued
+// together, then their list reservations (one returning atomic per piece),
+// then their stores, so a row costs one load and one atomic round trip per
+// kFillWin windows instead of per window; the next row's history index and
+// CSR bounds are loaded while the current row is placed.
+constexpr int kFillWin = 4;
+
 template <int LDI>
 __device__ __forceinline__ void fill_row(const int32_t *__restrict__ idx, const void *__restrict__ len_in, int64_t M,
                                          const PlanView &V, uint32_t *status, int64_t q, int64_t e0, int64_t e1,
@@ -146,67 +164,87 @@ __device__ __forceinline__ void fill_row(const int32_t *__restrict__ idx, const 
   const int64_t b = q / V.B;
   const int64_t rbase = V.ref_base[q], rcap = V.ref_base[q + 1] - rbase;
   int64_t nref = 0;
-  for (int64_t w = e0; w < e1; w += kWave) {
-    const int64_t e = w + lane;
-    const bool valid = e < e1;
-    int t = -1, local = 0;
-    float l = 0.f;
-    __half lh = __float2half(0.f);
-    if (valid) {
-      const int j = idx[e];
-      if (LDI == 0)
-        l = reinterpret_cast<const float *>(len_in)[e];
-      else
-        lh = reinterpret_cast<const __half *>(len_in)[e];
-      if ((uint32_t)j < (uint64_t)M) t = voxel_tile(j, V, local);
+  for (int64_t w0 = e0; w0 < e1; w0 += kFillWin * kWave) {
+    int jv[kFillWin];
+    float l[kFillWin];
+    __half lh[kFillWin];
+#pragma unroll
+    for (int k = 0; k < kFillWin; ++k) {
+      const int64_t e = w0 + k * kWave + lane;
+      jv[k] = -1;
+      l[k] = 0.f;
+      lh[k] = __float2half(0.f);
+      if (e < e1) {
+        jv[k] = idx[e];
+        if (LDI == 0)
+          l[k] = reinterpret_cast<const float *>(len_in)[e];
+        else
+          lh[k] = reinterpret_cast<const __half *>(len_in)[e];
+      }
     }
-    int tp = lane_prev(t);
-    if (lane == 0) tp = -2;
-    const bool start = valid && (lane == 0 || t != tp);
-    const uint64_t starts = __ballot(start);
-    const int nv = __popcll(__ballot(valid));
-    unsigned long long pos = 0;
-    int end = 0;
-    bool ok = true;
-    if (start && t >= 0) {
-      end = piece_end_lane(starts, lane, nv);
-      const int64_t bt = b * V.T + t;
-      pos = atomicAdd(&V.bt_cur[bt], (unsigned long long)(end - lane));
-      ok = (int64_t)pos + (end - lane) <= V.bt_off[bt + 1];
+    int t[kFillWin], local[kFillWin], end[kFillWin], nv[kFillWin];
+    uint64_t starts[kFillWin];
+    unsigned long long pos[kFillWin];
+    int64_t lim[kFillWin];
+#pragma unroll
+    for (int k = 0; k < kFillWin; ++k) {
+      const bool valid = w0 + k * kWave + lane < e1;
+      t[k] = -1;
+      local[k] = 0;
+      if (valid && (uint32_t)jv[k] < (uint64_t)M) t[k] = voxel_tile(jv[k], V, local[k]);
+      int tp = lane_prev(t[k]);
+      if (lane == 0) tp = -2;
+      const bool start = valid && (lane == 0 || t[k] != tp);
+      starts[k] = __ballot(start);
+      nv[k] = __popcll(__ballot(valid));
+      pos[k] = 0;
+      end[k] = 0;
+      lim[k] = 0;
+      if (start && t[k] >= 0) {
+        end[k] = piece_end_lane(starts[k], lane, nv[k]);
+        pos[k] = atomicAdd(&V.bt_cur[b * V.T + t[k]], (unsigned long long)(end[k] - lane));
+        lim[k] = V.bt_off[b * V.T + t[k] + 1];
+      }
     }
-    const int s = valid ? piece_start_lane(starts, lane) : 0;
-    const unsigned long long ps = __shfl(pos, s, kWave);
-    const int pe = __shfl(end, s, kWave);
-    const bool pok = __shfl((int)ok, s, kWave) != 0;
-    const int ts = __shfl(t, s, kWave);
-    const int64_t p = (int64_t)ps + (lane - s);
-    const bool write = valid && ts >= 0 && pok;
-    if (valid && !pok && lane == s) atomicOr(status, kStOverflow);
-    const bool last = lane == pe - 1;
-    bool is_ref = false;
-    if (write) {
-      V.packed[p] = pack_entry(last ? 1u : 0u, (uint32_t)local);
-      if (V.len_dtype == 0)
-        reinterpret_cast<float *>(V.len)[p] = LDI == 0 ? l : __half2float(lh) * V.len_unit;
-      else
-        reinterpret_cast<__half *>(V.len)[p] = LDI == 1 ? lh : __float2half(l / V.len_unit);
-      is_ref = last || ((p & (kWave - 1)) == kWave - 1);
+#pragma unroll
+    for (int k = 0; k < kFillWin; ++k) {
+      if (nv[k] == 0) break;  // wave-uniform: no entries from this window on
+      const bool valid = lane < nv[k];
+      const bool ok = end[k] == 0 || (int64_t)pos[k] + (end[k] - lane) <= lim[k];
+      const int s = valid ? piece_start_lane(starts[k], lane) : 0;
+      const unsigned long long ps = __shfl(pos[k], s, kWave);
+      const int pe = __shfl(end[k], s, kWave);
+      const bool pok = __shfl((int)ok, s, kWave) != 0;
+      const int ts = __shfl(t[k], s, kWave);
+      const int64_t p = (int64_t)ps + (lane - s);
+      const bool write = valid && ts >= 0 && pok;
+      if (valid && !pok && lane == s) atomicOr(status, kStOverflow);
+      const bool last = lane == pe - 1;
+      bool is_ref = false;
+      if (write) {
+        V.packed[p] = pack_entry(last ? 1u : 0u, (uint32_t)local[k]);
+        if (V.len_dtype == 0)
+          reinterpret_cast<float *>(V.len)[p] = LDI == 0 ? l[k] : __half2float(lh[k]) * V.len_unit;
+        else
+          reinterpret_cast<__half *>(V.len)[p] = LDI == 1 ? lh[k] : __float2half(l[k] / V.len_unit);
+        is_ref = last || ((p & (kWave - 1)) == kWave - 1);
+      }
+      const uint64_t rm = __ballot(is_ref);
+      if (is_ref) {
+        const int64_t kk = nref + __popcll(rm & ((1ull << lane) - 1));
+        if (kk < rcap)
+          V.refs[rbase + kk] = (uint32_t)p;
+        else
+          atomicOr(status, kStOverflow);
+      }
+      nref += __popcll(rm);
     }
-    const uint64_t rm = __ballot(is_ref);
-    if (is_ref) {
-      const int64_t k = nref + __popcll(rm & ((1ull << lane) - 1));
-      if (k < rcap)
-        V.refs[rbase + k] = (uint32_t)p;
-      else
-        atomicOr(status, kStOverflow);
-    }
-    nref += __popcll(rm);
   }
   if (lane == 0) V.ref_cnt[q] = (int32_t)(nref < rcap ? nref : rcap);
 }
 
 template <int LDI>
-__global__ void __launch_bounds__(256) k_plan_fill(const int64_t *__restrict__ row_ptr,
+__global__ void __launch_bounds__(256, 8) k_plan_fill(const int64_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ idx, const void *__restrict__ len_in,
                                                    const int64_t *__restrict__ order, const float *__restrict__ wepl,
                                                    const double *__restrict__ norm2, int64_t M, PlanView V,
@@ -215,27 +253,38 @@ __global__ void __launch_bounds__(256) k_plan_fill(const int64_t *__restrict__ r
   const int64_t nw = (int64_t)gridDim.x * 4;
   int64_t q = (int64_t)blockIdx.x * 4 + uniform((int)(threadIdx.x / kWave));
   if (q >= V.n) return;
-  // history index of row q, and of the row after it
+  // history index and CSR bounds of row q; history index of the row after it
   int64_t i = order ? order[q] : q;
   int64_t i_next = q + nw < V.n ? (order ? order[q + nw] : q + nw) : 0;
+  bool bad = (uint64_t)i >= (uint64_t)V.n;
+  int64_t e0 = bad ? 0 : row_ptr[i], e1 = bad ? 0 : row_ptr[i + 1];
   for (; q < V.n; q += nw) {
-    const bool bad = (uint64_t)i >= (uint64_t)V.n;
-    int64_t e0 = 0, e1 = 0;
-    if (!bad) {
-      e0 = row_ptr[i];
-      e1 = row_ptr[i + 1];
-      if (lane == 0) {
-        V.b_perm[q] = wepl[i];
-        V.n2_perm[q] = norm2[i];
-      }
-    } else if (lane == 0) {
-      atomicOr(status, kStBadIndex);
-    }
+    // loads for the next row, in flight while this one is placed
+    const bool has_next = q + nw < V.n;
+    const bool bad_next = !has_next || (uint64_t)i_next >= (uint64_t)V.n;
+    const int64_t e0n = bad_next ? 0 : row_ptr[i_next], e1n = bad_next ? 0 : row_ptr[i_next + 1];
     const int64_t q2 = q + 2 * nw;
     const int64_t i_next2 = q2 < V.n ? (order ? order[q2] : q2) : 0;
+    float bq = 0.f;
+    double nq = 0.0;
+    if (!bad && lane == 0) {
+      bq = wepl[i];
+      nq = norm2[i];
+    }
     if (!bad) fill_row<LDI>(idx, len_in, M, V, status, q, e0, e1, lane);
+    if (lane == 0) {
+      if (!bad) {
+        V.b_perm[q] = bq;
+        V.n2_perm[q] = nq;
+      } else {
+        atomicOr(status, kStBadIndex);
+      }
+    }
     i = i_next;
     i_next = i_next2;
+    bad = bad_next;
+    e0 = e0n;
+    e1 = e1n;
   }
 }
 
