@@ -311,7 +311,7 @@ def main():
         # and reads and writes x (8 B/voxel)
         ends_pb = ps.ends / n_blocks
         models["plan_dot"] = ("hbm", ((2 + lbp) * ps.entries + 8 * ps.chunks) / n_blocks + 8 * ends_pb + 4 * M,
-                              HBM_PEAK_GBS, "GB/s", "pct::k_plan_dot<1>" if lbp == 2 else "pct::k_plan_dot<0>")
+                              HBM_PEAK_GBS, "GB/s", "pct::k_plan_dot<1, false>" if lbp == 2 else "pct::k_plan_dot<0, false>")
         models["plan_scatter"] = ("hbm", (4 + lbp) * nnz / n_blocks + 4 * ends_pb + 8 * M, HBM_PEAK_GBS, "GB/s",
                                   "pct::k_plan_scatter<1>" if lbp == 2 else "pct::k_plan_scatter<0>")
     if rows is not None and plan is None:
@@ -353,17 +353,16 @@ def main():
     roofline = {"kernel": kname, "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4), "traffic": traffic, "avg_launch_ms": round(avg_ms, 4),
                 "work_per_launch": int(work), "work_unit": "bytes" if unit == "GB/s" else "FP64 flops"}
-    # the dot kernel serves both the sweeps and the per-sweep residual: split
-    # its time by launch count (every launch covers one block)
-    dot_n, dot_ms = prof["plan_dot"]
-    dot_sweep_ms = dot_ms * min(1.0, n_blocks * S / dot_n) if dot_n else 0.0
+    # the plan_dot class holds the sweeps' dot launches (one block each); the
+    # residual's dot pass over every block is counted in the residual class
+    dot_sweep_ms = prof["plan_dot"][1]
     # the per-proton path set-up (hull, end states) runs once per call: with
     # cached rows before the trace, in the fused form before the first sweep
     # (one record per history, read by every later path pass)
     setup_ms = prof["path_setup"][1]
     sweep_ms = (prof["project"][1] + prof["apply"][1] + dot_sweep_ms + prof["plan_rows"][1]
                 + prof["plan_scatter"][1]) / S
-    residual_ms = (prof["residual"][1] + dot_ms - dot_sweep_ms) / max(S, 1)
+    residual_ms = prof["residual"][1] / max(S, 1)
     trace_ms = prof["trace_path"][1] + prof["trace_compact"][1] + setup_ms
     others = {k: {"achieved": round(models[k][1] / (timing[k][0] if k == "trace" else 1)
                                     / (timing[k][1] / timing[k][0] / 1e3)

@@ -395,20 +395,18 @@ int64_t plan_scratch_len(const PlanDims &d) { return d.nb * d.T + d.nb + 8; }
 
 enum {
   L_REFBASE, L_BT_OFF, L_BT_CUR, L_RORD, L_ORDROW, L_RVALS, L_EMASK, L_CFE, L_PACKED, L_LEN, L_REFCNT, L_REFS, L_BPERM, L_N2PERM,
-  L_PARTIAL, L_RESPART, L_BLKRES, L_SCANTMP, L_ENDSLOT, L_GRPOFF, L_PACKEDB, L_LENB, L_TMPB, L_TMPLENB, L_COUNT
+  L_PARTIAL, L_RESPART, L_SCANTMP, L_ENDSLOT, L_GRPOFF, L_PACKEDB, L_LENB, L_TMPB, L_TMPLENB, L_COUNT
 };
 
 size_t plan_layout(const pct_plan *p, size_t off[L_COUNT]) {
   const int64_t nbT = p->n_blocks * p->n_tiles;
-  const int64_t G = (p->block_size + 255) / 256;
   const size_t lb = p->len_dtype == 0 ? 4 : 2;
   const size_t sz[L_COUNT] = {(size_t)(p->n + 1) * 8,   (size_t)(nbT + 1) * 8,   (size_t)nbT * 8,
                               (size_t)p->max_ends * 4, (size_t)p->refs * 4, (size_t)p->block_size * 4,
                               (size_t)p->chunks * 8,   (size_t)(p->chunks + 1) * 8,
                               (size_t)p->entries * 2,  (size_t)p->entries * lb, (size_t)p->n * 4,
                               (size_t)p->refs * 4,     (size_t)p->n * 4,         (size_t)p->n * 8,
-                              (size_t)p->max_ends * 4, (size_t)G * 8,
-                              (size_t)p->n_blocks * 8,
+                              (size_t)p->max_ends * 4, (size_t)pct::kResidAllGrid * 8,
                               (size_t)((p->chunks + pct::kScanChunk - 1) / pct::kScanChunk + 2) * 8,
                               (size_t)p->refs * 4,
                               (size_t)(nbT * pct::kGroups + 1) * 8,
@@ -465,7 +463,6 @@ pct::PlanView plan_view(const pct_plan *p, float len_unit) {
   V.n2_perm = reinterpret_cast<double *>(m + off[L_N2PERM]);
   V.partial = reinterpret_cast<float *>(m + off[L_PARTIAL]);
   V.res_part = reinterpret_cast<double *>(m + off[L_RESPART]);
-  V.blk_res = reinterpret_cast<double *>(m + off[L_BLKRES]);
   V.end_slot = reinterpret_cast<uint32_t *>(m + off[L_ENDSLOT]);
   V.grp_off = reinterpret_cast<int64_t *>(m + off[L_GRPOFF]);
   V.packedB = reinterpret_cast<uint32_t *>(m + off[L_PACKEDB]);
@@ -614,14 +611,13 @@ pct_status do_plan_sweep(Ctx &c, const pct_plan *plan, const pct::PlanView &V, f
   return PCT_OK;
 }
 
+// ||Ax - b|| over every block with one dot pass (its partials at the rows'
+// absolute slots) and one pass over the rows
 pct_status do_plan_residual(Ctx &c, const pct_plan *plan, const pct::PlanView &V, const float *x, double *out) {
-  const int64_t G = (plan->block_size + 255) / 256;
-  for (int64_t b = 0; b < plan->n_blocks; ++b) {
-    PROF(PCT_K_PLAN_DOT, pct::launch_plan_dot(V, b, x, c.s));
-    PROF(PCT_K_RESIDUAL, pct::launch_plan_resid_rows(V, b, V.res_part, c.s));
-    PROF(PCT_K_RESIDUAL, pct::launch_sum_partials(V.res_part, G, V.blk_res + b, 0, c.s));
-  }
-  PROF(PCT_K_RESIDUAL, pct::launch_sum_partials(V.blk_res, plan->n_blocks, out, 1, c.s));
+  (void)plan;
+  PROF(PCT_K_RESIDUAL, pct::launch_plan_dot_all(V, x, c.s));
+  PROF(PCT_K_RESIDUAL, pct::launch_plan_resid_all(V, V.res_part, c.s));
+  PROF(PCT_K_RESIDUAL, pct::launch_sum_partials(V.res_part, pct::kResidAllGrid, out, 1, c.s));
   return PCT_OK;
 }
 

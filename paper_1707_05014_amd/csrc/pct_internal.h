@@ -110,8 +110,7 @@ struct PlanView {
   float *b_perm;            // [n] b in block order
   double *n2_perm;          // [n] ||a||^2 in block order
   float *partial;           // [P] per-piece partial dot products of one block, in row order
-  double *res_part;         // [ceil(B/256)] residual partial sums of one block
-  double *blk_res;          // [nb] squared residual per block
+  double *res_part;         // [kResidAllGrid] residual partial sums (one per workgroup)
   // voxel-major copy for the scatter: per (block, tile, group of 64 tile-local
   // voxels) the entries sorted by voxel; packed: bit 0 valid, bit 1 last entry
   // of its voxel, bits 2..7 voxel in group, bits 8..31 offset of the entry's
@@ -124,6 +123,7 @@ struct PlanView {
   void *tmp_lenB;           // [EB]
 };
 constexpr int kGroups = kTileVox / 64;  // 64-voxel groups per tile
+constexpr int kResidAllGrid = 1024;     // workgroups of the whole-plan residual rows pass
 
 hipError_t launch_plan_count(const int64_t *row_ptr, const int32_t *idx, const int64_t *order, int64_t n, int64_t B,
                              int64_t M, const PlanView &V, int64_t *bt_cnt, int64_t *row_cap, int64_t *blk_cap,
@@ -139,7 +139,8 @@ hipError_t launch_plan_dot(const PlanView &V, int64_t b, const float *x, hipStre
 hipError_t launch_plan_rows(const PlanView &V, int64_t b, hipStream_t s);
 hipError_t launch_plan_scatter(const PlanView &V, int64_t b, float *x, const uint8_t *mask, float lambda, hipStream_t s);
 hipError_t launch_plan_build_voxel_major(const PlanView &V, hipStream_t s);
-hipError_t launch_plan_resid_rows(const PlanView &V, int64_t b, double *partials, hipStream_t s);
+hipError_t launch_plan_dot_all(const PlanView &V, const float *x, hipStream_t s);
+hipError_t launch_plan_resid_all(const PlanView &V, double *partials, hipStream_t s);
 hipError_t launch_sum_partials(const double *partials, int64_t np, double *out, int sqrt_it, hipStream_t s);
 
 // launchers (return hipError_t of the launch)

@@ -339,6 +339,7 @@ constexpr int kDotBatch = PCT_DOT_BATCH;
 constexpr int kPlanWaves = 8;
 constexpr int kPlanThreads = kPlanWaves * kWave;
 constexpr int kDotSplit = 4;   // workgroups per (block, tile) list, each on a quarter of its chunks
+constexpr int64_t kDotAllMaxWgs = int64_t(1) << 20;  // workgroups per launch of the whole-plan dot
 
 struct DotStageA {
   uint32_t v[kDotBatch];  // entry codes (0 past the share's end)
@@ -394,12 +395,21 @@ __device__ __forceinline__ void stage_tile_x(const PlanView &V, int64_t t, const
   for (int u = 0; u < kPer; ++u) s_x[(int)threadIdx.x + u * kPlanThreads] = in[u] ? xv[u] : 0.0f;
 }
 
-template <int LD>
-__global__ void __launch_bounds__(kPlanThreads) k_plan_dot(PlanView V, int64_t b, const float *__restrict__ x) {
+// ALL: one launch over the lists of blocks b0, b0 + 1, ... (kDotSplit x T
+// workgroups per block), each block's partials stored at its rows' absolute
+// slots in the build-only reference array (free once the plan is built), so
+// that a residual pass over every block needs one launch instead of one per
+// block.
+template <int LD, bool ALL>
+__global__ void __launch_bounds__(kPlanThreads) k_plan_dot(PlanView V, int64_t b0, const float *__restrict__ x) {
   __shared__ float s_x[kTileVox];
   const int lane = wave_lane();
-  const int64_t t = blockIdx.x / kDotSplit;
-  const int part = blockIdx.x % kDotSplit;
+  const int64_t per_blk = V.T * kDotSplit;
+  const int64_t b = ALL ? b0 + (int64_t)blockIdx.x / per_blk : b0;
+  const int64_t w = ALL ? (int64_t)blockIdx.x % per_blk : (int64_t)blockIdx.x;
+  const int64_t t = w / kDotSplit;
+  const int part = (int)(w % kDotSplit);
+  float *__restrict__ out = ALL ? reinterpret_cast<float *>(V.refs) + V.ref_base[b * V.B] : V.partial;
   const int64_t lk = b * V.T + t;
   const int64_t la = V.bt_off[lk] / kWave, lb = V.bt_off[lk + 1] / kWave;
   const int64_t ca = la + (lb - la) * part / kDotSplit, cb = la + (lb - la) * (part + 1) / kDotSplit;
@@ -437,7 +447,7 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan_dot(PlanView V, int64_t b
       const float Sp = __shfl(S, prev, kWave);
       // the end_slot entry of this chunk's n-th piece end sits in lane n
       const uint32_t slot = (uint32_t)__shfl((int)e0[k], __popcll(below), kWave);
-      if (close) V.partial[slot] = below ? S - Sp : S;
+      if (close) out[slot] = below ? S - Sp : S;
     }
     if (j1 > jlast) break;
     j = j1;
@@ -486,11 +496,10 @@ __global__ void __launch_bounds__(256) k_plan_ref_ordinals(PlanView V) {
   }
 }
 
-// sum of a row's piece partials; four references per step so that their
-// loads overlap (fixed summation order, so results are reproducible)
-__device__ __forceinline__ float row_dot(const PlanView &V, int64_t q, int64_t rb, int &nref) {
-  const float *p = V.partial + (V.ref_base[q] - rb);
-  nref = V.ref_cnt[q];
+// sum of a row's piece partials (p: its first slot); four references per step
+// so that their loads overlap (fixed summation order, so results are
+// reproducible)
+__device__ __forceinline__ float row_dot(const float *p, int nref) {
   float d = 0.0f;
   int k = 0;
   for (; k + 4 <= nref; k += 4) d += (p[k] + p[k + 1]) + (p[k + 2] + p[k + 3]);
@@ -503,8 +512,8 @@ __global__ void __launch_bounds__(256) k_plan_rows(PlanView V, int64_t b) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t q = b * V.B + r;
   if (r >= V.B || q >= V.n) return;
-  int nref;
-  const float d = row_dot(V, q, V.ref_base[b * V.B], nref);
+  const int nref = V.ref_cnt[q];
+  const float d = row_dot(V.partial + (V.ref_base[q] - V.ref_base[b * V.B]), nref);
   V.rvals[r] = nref ? (float)(((double)V.b_perm[q] - (double)d) / V.n2_perm[q]) : 0.0f;
 }
 
@@ -519,18 +528,19 @@ __global__ void __launch_bounds__(256) k_plan_expand(PlanView V, int64_t b) {
     V.r_ord[o - ob] = V.rvals[V.ord_row[o]];
 }
 
-// squared residuals of block b's rows: per-workgroup FP64 sums
-__global__ void __launch_bounds__(256) k_plan_resid_rows(PlanView V, int64_t b, double *partials) {
+// squared residuals of every row from the partials of a whole-plan dot pass
+// (absolute slots): rows q = blockIdx.x * 256 + threadIdx.x + k * gridDim.x *
+// 256, one FP64 sum per workgroup (fixed grid, so a fixed summation order)
+__global__ void __launch_bounds__(256) k_plan_resid_all(PlanView V, double *partials) {
   __shared__ double red[256];
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t q = b * V.B + r;
+  const float *part = reinterpret_cast<const float *>(V.refs);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   double acc = 0.0;
-  if (r < V.B && q < V.n) {
-    int nref;
-    const float d = row_dot(V, q, V.ref_base[b * V.B], nref);
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < V.n; q += stride) {
+    const int nref = V.ref_cnt[q];
     if (nref) {
-      const double rr = (double)d - (double)V.b_perm[q];
-      acc = rr * rr;
+      const double rr = (double)row_dot(part + V.ref_base[q], nref) - (double)V.b_perm[q];
+      acc += rr * rr;
     }
   }
   red[threadIdx.x] = acc;
@@ -1003,10 +1013,27 @@ hipError_t launch_plan_chunks(const PlanView &V, hipStream_t s) {
 hipError_t launch_plan_dot(const PlanView &V, int64_t b, const float *x, hipStream_t s) {
   if (V.T <= 0) return hipSuccess;
   if (V.len_dtype == 0)
-    hipLaunchKernelGGL(k_plan_dot<0>, dim3((unsigned)(V.T * kDotSplit)), dim3(kPlanThreads), 0, s, V, b, x);
+    hipLaunchKernelGGL((k_plan_dot<0, false>), dim3((unsigned)(V.T * kDotSplit)), dim3(kPlanThreads), 0, s, V, b, x);
   else
-    hipLaunchKernelGGL(k_plan_dot<1>, dim3((unsigned)(V.T * kDotSplit)), dim3(kPlanThreads), 0, s, V, b, x);
+    hipLaunchKernelGGL((k_plan_dot<1, false>), dim3((unsigned)(V.T * kDotSplit)), dim3(kPlanThreads), 0, s, V, b, x);
   return hipGetLastError();
+}
+
+hipError_t launch_plan_dot_all(const PlanView &V, const float *x, hipStream_t s) {
+  if (V.T <= 0 || V.nb <= 0) return hipSuccess;
+  const int64_t per_blk = V.T * kDotSplit;
+  const int64_t blk_per_launch = (kDotAllMaxWgs / per_blk) > 0 ? kDotAllMaxWgs / per_blk : 1;
+  for (int64_t b0 = 0; b0 < V.nb; b0 += blk_per_launch) {
+    const int64_t nbl = V.nb - b0 < blk_per_launch ? V.nb - b0 : blk_per_launch;
+    const dim3 grid((unsigned)(nbl * per_blk));
+    if (V.len_dtype == 0)
+      hipLaunchKernelGGL((k_plan_dot<0, true>), grid, dim3(kPlanThreads), 0, s, V, b0, x);
+    else
+      hipLaunchKernelGGL((k_plan_dot<1, true>), grid, dim3(kPlanThreads), 0, s, V, b0, x);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_plan_rows(const PlanView &V, int64_t b, hipStream_t s) {
@@ -1015,8 +1042,9 @@ hipError_t launch_plan_rows(const PlanView &V, int64_t b, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_plan_resid_rows(const PlanView &V, int64_t b, double *partials, hipStream_t s) {
-  hipLaunchKernelGGL(k_plan_resid_rows, dim3(grid_for(V.B, 256, 0x7fffffffu)), dim3(256), 0, s, V, b, partials);
+hipError_t launch_plan_resid_all(const PlanView &V, double *partials, hipStream_t s) {
+  if (V.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_plan_resid_all, dim3((unsigned)kResidAllGrid), dim3(256), 0, s, V, partials);
   return hipGetLastError();
 }
 
