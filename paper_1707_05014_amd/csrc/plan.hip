@@ -693,9 +693,22 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan_group_bucket(PlanView V) 
   }
 }
 
-constexpr int kSortChunks = 8;     // chunks whose loads k_plan_voxel_sort issues together
-constexpr int kSortWindow = 2048;  // output entries a wavefront assembles in LDS before writing them out
-constexpr int kSortWaves = 4;
+#ifndef PCT_SORT_CHUNKS
+#define PCT_SORT_CHUNKS 16
+#endif
+#ifndef PCT_SORT_WINDOW
+#define PCT_SORT_WINDOW 4096
+#endif
+#ifndef PCT_SORT_WAVES
+#define PCT_SORT_WAVES 2
+#endif
+constexpr int kSortChunks = PCT_SORT_CHUNKS;  // chunks whose loads k_plan_voxel_sort issues together
+constexpr int kSortWindow = PCT_SORT_WINDOW;  // output entries a wavefront assembles in LDS before writing them out
+constexpr int kSortWaves = PCT_SORT_WAVES;
+// workgroups that one CU holds at once (160 KB of LDS, 8 B per window slot)
+constexpr int kSortWgsPerCu = (160 * 1024) / (8 * kSortWaves * kSortWindow) > 0
+                                  ? (160 * 1024) / (8 * kSortWaves * kSortWindow)
+                                  : 1;
 
 // One (block, tile, group) list: sweep A counts entries per voxel; sweep B
 // places them (stable), through an LDS window of kSortWindow output slots
@@ -1063,7 +1076,7 @@ hipError_t launch_plan_scatter(const PlanView &V, int64_t b, float *x, const uin
 hipError_t launch_plan_build_voxel_major(const PlanView &V, hipStream_t s) {
   if (V.nb * V.T <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_plan_group_bucket, dim3((unsigned)(V.nb * V.T)), dim3(kPlanThreads), 0, s, V);
-  hipLaunchKernelGGL(k_plan_voxel_sort, dim3(grid_for(V.nb * V.T * kGroups, kSortWaves, 256 * 2)),
+  hipLaunchKernelGGL(k_plan_voxel_sort, dim3(grid_for(V.nb * V.T * kGroups, kSortWaves, 256 * kSortWgsPerCu)),
                      dim3(kSortWaves * kWave), 0, s, V);
   return hipGetLastError();
 }
