@@ -155,7 +155,16 @@ __global__ void k_copy_i64_u64(unsigned long long *dst, const int64_t *src, int6
 // then their stores, so a row costs one load and one atomic round trip per
 // kFillWin windows instead of per window; the next row's history index and
 // CSR bounds are loaded while the current row is placed.
-constexpr int kFillWin = 4;
+#ifndef PCT_FILL_WIN
+#define PCT_FILL_WIN 3
+#endif
+#ifndef PCT_FILL_MINW
+#define PCT_FILL_MINW 8
+#endif
+#ifndef PCT_FILL_WGS_PER_CU
+#define PCT_FILL_WGS_PER_CU 8
+#endif
+constexpr int kFillWin = PCT_FILL_WIN;
 
 template <int LDI>
 __device__ __forceinline__ void fill_row(const int32_t *__restrict__ idx, const void *__restrict__ len_in, int64_t M,
@@ -244,7 +253,7 @@ __device__ __forceinline__ void fill_row(const int32_t *__restrict__ idx, const 
 }
 
 template <int LDI>
-__global__ void __launch_bounds__(256, 8) k_plan_fill(const int64_t *__restrict__ row_ptr,
+__global__ void __launch_bounds__(256, PCT_FILL_MINW) k_plan_fill(const int64_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ idx, const void *__restrict__ len_in,
                                                    const int64_t *__restrict__ order, const float *__restrict__ wepl,
                                                    const double *__restrict__ norm2, int64_t M, PlanView V,
@@ -321,11 +330,11 @@ __device__ __forceinline__ float plan_len(const PlanView &V, int64_t p) {
 }
 
 // Partial dot products of every piece of block b.  kDotSplit workgroups of
-// kPlanWaves wavefronts per (block, tile) list, each on an equal share of
+// kDotWaves wavefronts per (block, tile) list, each on an equal share of
 // its chunks (many more workgroups than CUs can hold at once, so the work
 // spreads evenly): x of the tile is staged in LDS (the entries then read it
 // with LDS gathers instead of L1/L2 gathers).  A wavefront walks batches of
-// kDotBatch consecutive chunks (batch j, j + kPlanWaves, ...) in a
+// kDotBatch consecutive chunks (batch j, j + kDotWaves, ...) in a
 // three-stage software pipeline: stage A loads a batch's entries, lengths and
 // per-chunk piece-end ordinals; stage B loads the end_slot slices of the
 // batch's chunks (it needs stage A's ordinals); stage C reduces the batch.
@@ -336,9 +345,18 @@ __device__ __forceinline__ float plan_len(const PlanView &V, int64_t p) {
 #define PCT_DOT_BATCH 4
 #endif
 constexpr int kDotBatch = PCT_DOT_BATCH;
+#ifndef PCT_DOT_SPLIT
+#define PCT_DOT_SPLIT 4
+#endif
+#ifndef PCT_DOT_WAVES
+#define PCT_DOT_WAVES 8
+#endif
 constexpr int kPlanWaves = 8;
 constexpr int kPlanThreads = kPlanWaves * kWave;
-constexpr int kDotSplit = 4;   // workgroups per (block, tile) list, each on a quarter of its chunks
+constexpr int kDotSplit = PCT_DOT_SPLIT;  // workgroups per (block, tile) list, each on an equal share of its chunks
+constexpr int kDotWaves = PCT_DOT_WAVES;  // wavefronts per dot workgroup
+constexpr int kDotThreads = kDotWaves * kWave;
+static_assert(kTileVox % kDotThreads == 0, "a dot workgroup stages the tile's x in whole rounds");
 constexpr int64_t kDotAllMaxWgs = int64_t(1) << 20;  // workgroups per launch of the whole-plan dot
 
 struct DotStageA {
@@ -377,22 +395,22 @@ __device__ __forceinline__ void dot_stage_b(const PlanView &V, const DotStageA &
 }
 
 // x of tile t (2048 voxels, zero outside the grid) -> s_x; every thread
-// issues its kTileVox / kPlanThreads loads before storing any (voxels outside
+// issues its kTileVox / kDotThreads loads before storing any (voxels outside
 // the grid load voxel 0 and store 0)
 __device__ __forceinline__ void stage_tile_x(const PlanView &V, int64_t t, const float *__restrict__ x, float *s_x) {
-  constexpr int kPer = kTileVox / kPlanThreads;
+  constexpr int kPer = kTileVox / kDotThreads;
   const int tx = (int)(t % V.ntx), r = (int)(t / V.ntx), ty = r % V.nty, tz = r / V.nty;
   float xv[kPer];
   bool in[kPer];
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
-    const int i = (int)threadIdx.x + u * kPlanThreads;
+    const int i = (int)threadIdx.x + u * kDotThreads;
     const int ix = tx * kTX + (i & 15), iy = ty * kTY + ((i >> 4) & 15), iz = tz * kTZ + (i >> 8);
     in[u] = ix < V.nx && iy < V.ny && iz < V.nz;
     xv[u] = x[in[u] ? ((int64_t)iz * V.ny + iy) * V.nx + ix : 0];
   }
 #pragma unroll
-  for (int u = 0; u < kPer; ++u) s_x[(int)threadIdx.x + u * kPlanThreads] = in[u] ? xv[u] : 0.0f;
+  for (int u = 0; u < kPer; ++u) s_x[(int)threadIdx.x + u * kDotThreads] = in[u] ? xv[u] : 0.0f;
 }
 
 // ALL: one launch over the lists of blocks b0, b0 + 1, ... (kDotSplit x T
@@ -401,7 +419,7 @@ __device__ __forceinline__ void stage_tile_x(const PlanView &V, int64_t t, const
 // that a residual pass over every block needs one launch instead of one per
 // block.
 template <int LD, bool ALL>
-__global__ void __launch_bounds__(kPlanThreads) k_plan_dot(PlanView V, int64_t b0, const float *__restrict__ x) {
+__global__ void __launch_bounds__(kDotThreads) k_plan_dot(PlanView V, int64_t b0, const float *__restrict__ x) {
   __shared__ float s_x[kTileVox];
   const int lane = wave_lane();
   const int64_t per_blk = V.T * kDotSplit;
@@ -420,14 +438,14 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan_dot(PlanView V, int64_t b
   int64_t j = uniform((int)(threadIdx.x / kWave));
   if (j >= nbat) return;
   // batches past the last are loaded as the last one again (never reduced)
-  const int64_t jlast = j + (nbat - 1 - j) / kPlanWaves * kPlanWaves;
+  const int64_t jlast = j + (nbat - 1 - j) / kDotWaves * kDotWaves;
   DotStageA a0, a1, a2;
   uint32_t e0[kDotBatch], e1[kDotBatch];
   dot_stage_a<LD>(V, ca, cb, j, lane, a0);
-  dot_stage_a<LD>(V, ca, cb, j + kPlanWaves <= jlast ? j + kPlanWaves : jlast, lane, a1);
+  dot_stage_a<LD>(V, ca, cb, j + kDotWaves <= jlast ? j + kDotWaves : jlast, lane, a1);
   dot_stage_b(V, a0, lane, e0);
   for (;;) {
-    const int64_t j1 = j + kPlanWaves, j2 = j + 2 * kPlanWaves;
+    const int64_t j1 = j + kDotWaves, j2 = j + 2 * kDotWaves;
     dot_stage_b(V, a1, lane, e1);
     dot_stage_a<LD>(V, ca, cb, j2 <= jlast ? j2 : jlast, lane, a2);
     const int nc = (int)(cb - (ca + j * kDotBatch) < kDotBatch ? cb - (ca + j * kDotBatch) : kDotBatch);
@@ -458,11 +476,31 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan_dot(PlanView V, int64_t b
   }
 }
 
+// Per chunk, its piece-end mask and first ordinal side by side (16 B), so
+// that k_plan_ref_ordinals, which visits chunks in row order (scattered),
+// fetches one cache line per reference instead of two.  Kept in the
+// build-only tmpB area, which is free until the voxel-major copy is built.
+struct __align__(16) ChunkMeta {
+  uint64_t mask;
+  int64_t first;
+};
+
+__global__ void __launch_bounds__(256) k_plan_chunk_meta(PlanView V, ChunkMeta *meta) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < V.C; c += stride) {
+    ChunkMeta m;
+    m.mask = V.end_mask[c];
+    m.first = V.chunk_first_end[c];
+    meta[c] = m;
+  }
+}
+
 // references hold entry positions after the fill pass; record, for every
 // piece end (global ordinal in chunk order), the row-ordered slot of its
 // reference, so k_plan_dot can store each partial next to the other partials
 // of its row, and its row in the block, so k_plan_expand can give it r
-__global__ void __launch_bounds__(256) k_plan_ref_ordinals(PlanView V) {
+template <bool META>
+__global__ void __launch_bounds__(256) k_plan_ref_ordinals(PlanView V, const ChunkMeta *__restrict__ meta) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= V.n) return;
   const int64_t b = q / V.B;
@@ -481,8 +519,14 @@ __global__ void __launch_bounds__(256) k_plan_ref_ordinals(PlanView V) {
       em[u] = 0ull;
       fe[u] = 0;
       if (k + u < nref) {
-        em[u] = V.end_mask[p[u] / kWave];
-        fe[u] = V.chunk_first_end[p[u] / kWave];
+        if (META) {
+          const ChunkMeta m = meta[p[u] / kWave];
+          em[u] = m.mask;
+          fe[u] = m.first;
+        } else {
+          em[u] = V.end_mask[p[u] / kWave];
+          fe[u] = V.chunk_first_end[p[u] / kWave];
+        }
       }
     }
 #pragma unroll
@@ -833,15 +877,23 @@ __device__ __forceinline__ void scatter_level1(const PlanView &V, int64_t wb, in
 // voxel of the group (every voxel has exactly one run per list).  After the
 // group, lane l applies x_j += lambda num_j / s_j to voxel l of the group.
 // No atomics.
+#ifndef PCT_SCAT_SPLIT
+#define PCT_SCAT_SPLIT 2
+#endif
+#ifndef PCT_SCAT_WAVES
+#define PCT_SCAT_WAVES 16
+#endif
 constexpr int kStageOrd = 12288;
-constexpr int kScatSplit = 4;  // workgroups per (block, tile), each on a quarter of its voxel groups
+constexpr int kScatSplit = PCT_SCAT_SPLIT;  // workgroups per (block, tile), each on an equal share of its voxel groups
+constexpr int kScatWaves = PCT_SCAT_WAVES;  // wavefronts per scatter workgroup
+constexpr int kScatThreads = kScatWaves * kWave;
 
 template <int LD>
-__global__ void __launch_bounds__(kPlanThreads) k_plan_scatter(PlanView V, int64_t b, float *__restrict__ x,
+__global__ void __launch_bounds__(kScatThreads) k_plan_scatter(PlanView V, int64_t b, float *__restrict__ x,
                                                                const uint8_t *__restrict__ mask, float lambda) {
   __shared__ float s_r[kStageOrd];
-  __shared__ float s_num[kPlanWaves][kWave];
-  __shared__ uint32_t s_cnt[kPlanWaves][kWave];
+  __shared__ float s_num[kScatWaves][kWave];
+  __shared__ uint32_t s_cnt[kScatWaves][kWave];
   const int lane = wave_lane();
   const int wid = uniform((int)(threadIdx.x / kWave));
   const int64_t t = blockIdx.x / kScatSplit;
@@ -857,23 +909,23 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan_scatter(PlanView V, int64
     // kStageLoads loads per thread in flight before any store (indices past
     // the list read its last value and store nothing)
     constexpr int kStageLoads = 8;
-    for (int64_t i0 = threadIdx.x; i0 < nord; i0 += (int64_t)kPlanThreads * kStageLoads) {
+    for (int64_t i0 = threadIdx.x; i0 < nord; i0 += (int64_t)kScatThreads * kStageLoads) {
       float rv[kStageLoads];
 #pragma unroll
       for (int u = 0; u < kStageLoads; ++u) {
-        const int64_t i = i0 + (int64_t)u * kPlanThreads;
+        const int64_t i = i0 + (int64_t)u * kScatThreads;
         rv[u] = r_list[i < nord ? i : nord - 1];
       }
 #pragma unroll
       for (int u = 0; u < kStageLoads; ++u) {
-        const int64_t i = i0 + (int64_t)u * kPlanThreads;
+        const int64_t i = i0 + (int64_t)u * kScatThreads;
         if (i < nord) s_r[i] = rv[u];
       }
     }
   }
   __syncthreads();
   constexpr int kGroupsPerPart = kGroups / kScatSplit;
-  for (int grp = part * kGroupsPerPart + wid; grp < (part + 1) * kGroupsPerPart; grp += kPlanWaves) {
+  for (int grp = part * kGroupsPerPart + wid; grp < (part + 1) * kGroupsPerPart; grp += kScatWaves) {
     const int64_t gi = lk * kGroups + grp;
     const int64_t e0 = V.grp_off[gi], e1 = V.grp_off[gi + 1];
     if (e0 == e1) continue;
@@ -1001,7 +1053,7 @@ hipError_t launch_plan_fill(const int64_t *row_ptr, const int32_t *idx, const vo
                             const int64_t *order, const float *wepl, const double *norm2, int64_t M,
                             const PlanView &V, uint32_t *status, hipStream_t s) {
   if (V.n <= 0) return hipSuccess;
-  const unsigned g = grid_for(V.n, 4, 256 * 8);
+  const unsigned g = grid_for(V.n, 4, 256 * PCT_FILL_WGS_PER_CU);
   if (len_in_dtype == 0)
     hipLaunchKernelGGL(k_plan_fill<0>, dim3(g), dim3(256), 0, s, row_ptr, idx, len_in, order, wepl, norm2, M, V,
                        status);
@@ -1013,7 +1065,15 @@ hipError_t launch_plan_fill(const int64_t *row_ptr, const int32_t *idx, const vo
 
 hipError_t launch_plan_ref_ordinals(const PlanView &V, hipStream_t s) {
   if (V.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_plan_ref_ordinals, dim3(grid_for(V.n, 256, 0x7fffffffu)), dim3(256), 0, s, V);
+  const dim3 grid(grid_for(V.n, 256, 0x7fffffffu));
+  // the chunk records fit the tmpB area unless padding is most of the plan
+  if (V.C > 0 && (uint64_t)V.C * sizeof(ChunkMeta) <= (uint64_t)V.EB * sizeof(uint32_t)) {
+    ChunkMeta *meta = reinterpret_cast<ChunkMeta *>(V.tmpB);
+    hipLaunchKernelGGL(k_plan_chunk_meta, dim3(grid_for(V.C, 256, 8192)), dim3(256), 0, s, V, meta);
+    hipLaunchKernelGGL(k_plan_ref_ordinals<true>, grid, dim3(256), 0, s, V, meta);
+  } else {
+    hipLaunchKernelGGL(k_plan_ref_ordinals<false>, grid, dim3(256), 0, s, V, nullptr);
+  }
   return hipGetLastError();
 }
 
@@ -1026,9 +1086,9 @@ hipError_t launch_plan_chunks(const PlanView &V, hipStream_t s) {
 hipError_t launch_plan_dot(const PlanView &V, int64_t b, const float *x, hipStream_t s) {
   if (V.T <= 0) return hipSuccess;
   if (V.len_dtype == 0)
-    hipLaunchKernelGGL((k_plan_dot<0, false>), dim3((unsigned)(V.T * kDotSplit)), dim3(kPlanThreads), 0, s, V, b, x);
+    hipLaunchKernelGGL((k_plan_dot<0, false>), dim3((unsigned)(V.T * kDotSplit)), dim3(kDotThreads), 0, s, V, b, x);
   else
-    hipLaunchKernelGGL((k_plan_dot<1, false>), dim3((unsigned)(V.T * kDotSplit)), dim3(kPlanThreads), 0, s, V, b, x);
+    hipLaunchKernelGGL((k_plan_dot<1, false>), dim3((unsigned)(V.T * kDotSplit)), dim3(kDotThreads), 0, s, V, b, x);
   return hipGetLastError();
 }
 
@@ -1040,9 +1100,9 @@ hipError_t launch_plan_dot_all(const PlanView &V, const float *x, hipStream_t s)
     const int64_t nbl = V.nb - b0 < blk_per_launch ? V.nb - b0 : blk_per_launch;
     const dim3 grid((unsigned)(nbl * per_blk));
     if (V.len_dtype == 0)
-      hipLaunchKernelGGL((k_plan_dot<0, true>), grid, dim3(kPlanThreads), 0, s, V, b0, x);
+      hipLaunchKernelGGL((k_plan_dot<0, true>), grid, dim3(kDotThreads), 0, s, V, b0, x);
     else
-      hipLaunchKernelGGL((k_plan_dot<1, true>), grid, dim3(kPlanThreads), 0, s, V, b0, x);
+      hipLaunchKernelGGL((k_plan_dot<1, true>), grid, dim3(kDotThreads), 0, s, V, b0, x);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -1065,10 +1125,10 @@ hipError_t launch_plan_scatter(const PlanView &V, int64_t b, float *x, const uin
                                hipStream_t s) {
   if (V.T <= 0) return hipSuccess;
   if (V.len_dtype == 0)
-    hipLaunchKernelGGL(k_plan_scatter<0>, dim3((unsigned)(V.T * kScatSplit)), dim3(kPlanThreads), 0, s, V, b, x,
+    hipLaunchKernelGGL(k_plan_scatter<0>, dim3((unsigned)(V.T * kScatSplit)), dim3(kScatThreads), 0, s, V, b, x,
                        mask, lambda);
   else
-    hipLaunchKernelGGL(k_plan_scatter<1>, dim3((unsigned)(V.T * kScatSplit)), dim3(kPlanThreads), 0, s, V, b, x,
+    hipLaunchKernelGGL(k_plan_scatter<1>, dim3((unsigned)(V.T * kScatSplit)), dim3(kScatThreads), 0, s, V, b, x,
                        mask, lambda);
   return hipGetLastError();
 }
