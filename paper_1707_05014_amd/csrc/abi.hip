@@ -157,7 +157,7 @@ pct_status make_params(const pct_grid *g, const pct_geom *G, pct::PathParams &P)
   const double reach = 2.0 * std::max(G->hull_a, G->hull_b);
   P.kmax = (int32_t)std::ceil(reach / G->step_mm) + 2;
   P.emax = 4 * (P.kmax + 1) + 16;
-  const size_t per_wave = (size_t)P.emax * 3 * sizeof(int);
+  const size_t per_wave = pct::row_buf_bytes(P.emax);
   P.waves_per_block = (int32_t)std::min<size_t>(4, 65536 / per_wave);
   if (P.waves_per_block < 1)
     return fail(PCT_EINVAL, "hull too long for the sample step (row buffer exceeds the LDS budget)");

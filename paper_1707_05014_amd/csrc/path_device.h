@@ -375,13 +375,25 @@ __device__ __forceinline__ int walk_segment(const PathParams &P, int bx, int by,
   return kMaxPieces + 1;
 }
 
+// the row buffer of wavefront wid in the dynamic LDS area (see row_buf_bytes)
+struct RowBuf {
+  int *vox;
+  float *len;
+  int16_t *aux;
+};
+__device__ __forceinline__ RowBuf row_buf(void *smem, int wid, int emax) {
+  char *base = static_cast<char *>(smem) + (size_t)wid * row_buf_bytes(emax);
+  return {reinterpret_cast<int *>(base), reinterpret_cast<float *>(base + 4 * (size_t)emax),
+          reinterpret_cast<int16_t *>(base + 8 * (size_t)emax)};
+}
+
 // Build the row of one proton (set-up pp, wave-uniform) in the wavefront's
 // LDS slice (s_vox, s_len, s_aux of P.emax entries each); cF = the staged
 // prior tables.  Returns the entry count (wave-uniform); on a bound violation
 // sets `status` bits and returns 0.
 template <typename R>
 __device__ int build_row(const PathParams &P, const R *cF, const ProtonPath<R> &pp, int *s_vox, float *s_len,
-                         int *s_aux, uint32_t *status) {
+                         int16_t *s_aux, uint32_t *status) {
   const int lane = wave_lane();
   if (!pp.valid) return 0;
   if (pp.K > P.kmax) {
@@ -475,7 +487,7 @@ __device__ int build_row(const PathParams &P, const R *cF, const ProtonPath<R> &
       const int lo = e - kDedupWindow > 0 ? e - kDedupWindow : 0;
       for (int f = lo; f <= e - 2; ++f)
         if (s_vox[f] == v) { m = f; break; }
-      s_aux[e] = m;
+      s_aux[e] = (int16_t)m;
     }
     any = any || (__ballot(m >= 0) != 0);
   }

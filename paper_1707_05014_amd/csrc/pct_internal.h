@@ -14,6 +14,11 @@ constexpr int kPathRecBytes = 128;    // workspace slot of one proton's path set
 constexpr int kMaxPieces = 6;      // voxel pieces one segment can yield (<= 4 when step <= voxel)
 constexpr int kDedupWindow = 8;    // look-back for voxels revisited after a short excursion
 
+// LDS row buffer of one wavefront: voxel (int32), length (float32) and dedup
+// link (int16: an entry index, below emax <= 6553 since a buffer holds at
+// most 64 KiB) of up to emax entries, padded to 4 bytes
+__host__ __device__ inline size_t row_buf_bytes(int emax) { return ((size_t)emax * 10 + 3) & ~(size_t)3; }
+
 // status word bits (device)
 constexpr uint32_t kStNonFinite = 1u;
 constexpr uint32_t kStOverflow = 2u;

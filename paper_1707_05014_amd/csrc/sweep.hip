@@ -73,9 +73,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   extern __shared__ int smem[];
   const int wid = threadIdx.x / kWave;
   const int lane = wave_lane();
-  int *s_vox = smem + wid * 3 * P.emax;
-  float *s_len = reinterpret_cast<float *>(s_vox + P.emax);
-  int *s_aux = s_vox + 2 * P.emax;
+  const RowBuf rb = row_buf(smem, wid, P.emax);
+  int *s_vox = rb.vox;
+  float *s_len = rb.len;
+  int16_t *s_aux = rb.aux;
   __shared__ R s_cF[24];
   stage_prior<R>(P, s_cF);
   const int64_t stride = (int64_t)gridDim.x * P.waves_per_block;
@@ -238,9 +239,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   __shared__ double red[4];
   const int wid = threadIdx.x / kWave;
   const int lane = wave_lane();
-  int *s_vox = smem + wid * 3 * P.emax;
-  float *s_len = reinterpret_cast<float *>(s_vox + P.emax);
-  int *s_aux = s_vox + 2 * P.emax;
+  const RowBuf rb = row_buf(smem, wid, P.emax);
+  int *s_vox = rb.vox;
+  float *s_len = rb.len;
+  int16_t *s_aux = rb.aux;
   __shared__ R s_cF[24];
   stage_prior<R>(P, s_cF);
   double acc = 0.0;
@@ -345,7 +347,7 @@ hipError_t launch_project_fused(const PathParams &P, const void *recs, const int
                                 uint32_t *status, hipStream_t s) {
   const int gl = global ? 1 : 0;
   if (count <= 0) return hipSuccess;
-  const size_t lds = (size_t)P.waves_per_block * 3 * P.emax * sizeof(int);
+  const size_t lds = (size_t)P.waves_per_block * row_buf_bytes(P.emax);
   const unsigned grid = grid_for(count, P.waves_per_block, 1u << 20);
   const dim3 g(grid), b(P.waves_per_block * kWave);
   if (P.path_fp32) {
@@ -411,7 +413,7 @@ hipError_t launch_residual_cached(const int64_t *row_ptr, const int32_t *idx, co
 // sums of earlier chunks); the final sum is launch_residual_final
 hipError_t launch_residual_fused(const PathParams &P, const void *recs, int64_t n, const float *x, double *partials,
                                  uint32_t *status, bool accumulate, hipStream_t s) {
-  const size_t lds = (size_t)P.waves_per_block * 3 * P.emax * sizeof(int);
+  const size_t lds = (size_t)P.waves_per_block * row_buf_bytes(P.emax);
   const unsigned grid = kResidFusedGrid;
   if (P.path_fp32)
     hipLaunchKernelGGL(k_resid_fused<float>, dim3(grid), dim3(P.waves_per_block * kWave), lds, s, P,

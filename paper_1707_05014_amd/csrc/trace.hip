@@ -55,9 +55,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   extern __shared__ int smem[];
   const int wid = threadIdx.x / kWave;
   const int lane = wave_lane();
-  int *s_vox = smem + wid * 3 * P.emax;
-  float *s_len = reinterpret_cast<float *>(s_vox + P.emax);
-  int *s_aux = s_vox + 2 * P.emax;
+  const RowBuf rb = row_buf(smem, wid, P.emax);
+  int *s_vox = rb.vox;
+  float *s_len = rb.len;
+  int16_t *s_aux = rb.aux;
   __shared__ R s_cF[24];
   stage_prior<R>(P, s_cF);
   const int64_t stride = (int64_t)gridDim.x * P.waves_per_block;
@@ -212,7 +213,7 @@ hipError_t launch_trace_stage(const PathParams &P, const void *recs, int64_t i0,
                               int32_t *st_idx, float *st_len, double *norm2, uint32_t *status, hipStream_t s) {
   if (nrows <= 0) return hipSuccess;
   const unsigned threads = (unsigned)(P.waves_per_block * kWave);
-  const size_t lds = (size_t)P.waves_per_block * 3 * P.emax * sizeof(int);
+  const size_t lds = (size_t)P.waves_per_block * row_buf_bytes(P.emax);
   const unsigned grid = grid_for(nrows, P.waves_per_block, 1u << 20);
   if (P.path_fp32)
     hipLaunchKernelGGL(k_trace_stage<float>, dim3(grid), dim3(threads), lds, s, P,
