@@ -156,7 +156,13 @@ pct_status make_params(const pct_grid *g, const pct_geom *G, pct::PathParams &P)
   P.eps_len = 1e-6f * dmin;
   const double reach = 2.0 * std::max(G->hull_a, G->hull_b);
   P.kmax = (int32_t)std::ceil(reach / G->step_mm) + 2;
-  P.emax = 4 * (P.kmax + 1) + 16;
+  // Entries of a row: at most one more than the voxel faces its path crosses.
+  // A smooth path of arc length s crosses at most sqrt(3) s / dmin faces plus
+  // a few per turning point of each coordinate; s is at most the sample
+  // spacing (<= dmin, checked above) times the segment count, stretched a
+  // little by the lateral offsets, so 2 entries per sample bound it with room
+  // to spare.  A row that still does not fit is reported (kStOverflow).
+  P.emax = 2 * (P.kmax + 1) + 16;
   const size_t per_wave = pct::row_buf_bytes(P.emax);
   P.waves_per_block = (int32_t)std::min<size_t>(4, 65536 / per_wave);
   if (P.waves_per_block < 1)

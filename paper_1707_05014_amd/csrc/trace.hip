@@ -48,8 +48,11 @@ __global__ void __launch_bounds__(256) k_path_setup(PathParams P, HistPtrs H, co
 // [q * emax, q * emax + count) with ||a_i||^2 (FP64, from the FP32 lengths)
 // to norm2[i0 + q].  A single path pass per proton: the compaction below
 // moves the staged rows into CSR order once the counts are scanned.
+#ifndef PCT_TRACE_WAVES
+#define PCT_TRACE_WAVES 6
+#endif
 template <typename R>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_trace_stage(PathParams P, const PathRec<R> *__restrict__ recs, int64_t i0, int64_t nrows,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PCT_TRACE_WAVES))) k_trace_stage(PathParams P, const PathRec<R> *__restrict__ recs, int64_t i0, int64_t nrows,
                                                      int64_t *cnt, int32_t *st_idx, float *st_len, double *norm2,
                                                      uint32_t *status) {
   extern __shared__ int smem[];
