@@ -117,3 +117,37 @@ def test_outside_grid_skipped():
     assert len(idx) == 4 and np.allclose(ln, 1.0)
     idx, ln, _ = oracle.polyline_row(grid, [[-3.0, 9.5, 1.5], [7.0, 9.5, 1.5]])
     assert len(idx) == 0
+
+
+def test_row_length_bound():
+    """The path kernels size each wavefront's row buffer for 2 entries per path
+    sample plus 16.  What fixes that: a row has at most one more entry than
+    the voxel faces its path crosses, and along each axis a path crosses at
+    most (its total variation along the axis) / (voxel size) faces plus one
+    per monotone stretch; an MLP path has at most three monotone stretches per
+    coordinate, and the total variations add up to at most sqrt(3) times the
+    arc length s.  So entries <= sqrt(3) s / dmin + 10, checked on the
+    oracle's rows of seeded phantoms (s = the row's total length), and the
+    longest row against the buffer size the kernels reserve."""
+    import sys
+
+    sys.path.insert(0, os.path.dirname(__file__))
+    import synth
+    from helpers import oracle_geom, oracle_grid
+
+    for which in (1, 2):
+        cfg = synth.config(which, n=20000)
+        h = synth.generate(cfg)
+        R = oracle.trace(oracle_grid(cfg), oracle_geom(cfg), h)
+        cnt = np.diff(R.row_ptr)
+        ok = cnt > 0
+        s = np.add.reduceat(R.len, R.row_ptr[:-1][ok])
+        g = cfg.grid
+        dmin = min(g.dx, g.dy, g.dz)
+        assert np.all(cnt[ok] <= math.sqrt(3.0) * s / dmin + 10)
+        b = cfg.phantom.body
+        kmax = math.ceil(2 * max(b.ax[0], b.ax[1]) / dmin) + 2
+        emax = 2 * (kmax + 1) + 16
+        print(f"config {which}: longest row {cnt.max()} entries, buffer {emax}; "
+              f"max entries / (sqrt(3) s / dmin + 10) = {np.max(cnt[ok] / (math.sqrt(3.0) * s / dmin + 10)):.3f}")
+        assert cnt.max() <= emax
