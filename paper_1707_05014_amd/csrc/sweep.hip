@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(256) k_project_cached(const int64_t *__restric
 // an order entry outside [0, n) sets kStBadIndex), else by position in the
 // chunk (recs[q]).
 template <typename R, bool COUNT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_project_fused(PathParams P, const PathRec<R> *__restrict__ recs,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k_project_fused(PathParams P, const PathRec<R> *__restrict__ recs,
                                                        const int64_t *__restrict__ order, int64_t first, int64_t n,
                                                        int global, int64_t count, const float *__restrict__ x,
                                                        float *num, uint32_t *cnt, uint32_t *status) {
@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(256) k_resid_cached(const int64_t *__restrict_
 // rows of one chunk (set-up records recs[0, n)); workgroup g's sum is stored
 // to partials[g] (accumulate = 0) or added to it (later chunks)
 template <typename R>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_resid_fused(PathParams P, const PathRec<R> *__restrict__ recs, int64_t n,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k_resid_fused(PathParams P, const PathRec<R> *__restrict__ recs, int64_t n,
                                                      const float *__restrict__ x, double *partials,
                                                      uint32_t *status, int accumulate) {
   extern __shared__ int smem[];
