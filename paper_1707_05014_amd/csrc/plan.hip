@@ -342,7 +342,7 @@ __device__ __forceinline__ float plan_len(const PlanView &V, int64_t p) {
 // flight.  Every load is issued unconditionally (addresses clamped into the
 // list, results masked), so the wait counts stay static.
 #ifndef PCT_DOT_BATCH
-#define PCT_DOT_BATCH 4
+#define PCT_DOT_BATCH 3
 #endif
 constexpr int kDotBatch = PCT_DOT_BATCH;
 #ifndef PCT_DOT_SPLIT
