@@ -153,7 +153,8 @@ typedef struct {
 /* Bytes of scratch that the calls below need for a grid, solver and history
  * count.  `fused` = 1 when rows are recomputed in every sweep (no plan).  With
  * geom given and fused = 0 the size includes the row staging area of the
- * trace (up to 2^20 rows of the longest possible row, 8 bytes per entry); a
+ * trace (up to 2^20 rows of the longest possible row: 2 entries per path
+ * sample + 16, 8 bytes per entry); a
  * trace given less stages fewer rows at a time (PCT_ENOMEM below one row).
  * With fused = 1 the size includes one path set-up record per history (128
  * bytes: hull entry and exit, end states, the prior's moments at the exit,
