@@ -12,6 +12,9 @@ The arithmetic lives in ``oracle.c`` (plain FP64 C):
                         per proton, path lengths in the voxels it touches);
   * ``drop``         -- block-iterative row projections (DROP, Sec. 2.1), ART
                         as block size 1;
+  * ``drop_recompute`` -- the same DROP with no stored A: each block's rows are
+                        traced, projected and dropped (A too large to keep,
+                        Sec. 2 and Sec. 4.1);
   * ``residual``     -- ||Ax - b||_2.
 ``roi_means`` is the ROI analysis of Sec. 3.2 / 4.2 (mean RSP per insert).
 ``oracle.cnn`` (NumPy, FP64) holds the operations and gradients of the
@@ -82,6 +85,11 @@ def _load():
         lib.orc_drop.argtypes = [ctypes.c_int64, _i64p, _i32p, _dp, _dp, _dp, _i64p, ctypes.c_int64,
                                  ctypes.c_double, ctypes.POINTER(ctypes.c_uint8), ctypes.c_int64, ctypes.c_int32,
                                  _dp, _dp, ctypes.c_int32]
+        lib.orc_drop_recompute.restype = ctypes.c_int
+        lib.orc_drop_recompute.argtypes = [ctypes.POINTER(OrcGrid), ctypes.POINTER(OrcGeom), ctypes.c_int64,
+                                           ctypes.POINTER(ctypes.POINTER(ctypes.c_float)), _i64p, ctypes.c_int64,
+                                           ctypes.c_double, ctypes.POINTER(ctypes.c_uint8), ctypes.c_int64,
+                                           ctypes.c_int32, _dp, _dp, ctypes.c_int32]
         _lib = lib
     return _lib
 
@@ -209,6 +217,33 @@ def drop(rows: Rows, b, x0, order, block: int, lam: float, sweeps: int, mask=Non
                       rows.len.ctypes.data_as(_dp), rows.norm2.ctypes.data_as(_dp), b.ctypes.data_as(_dp),
                       order.ctypes.data_as(_i64p), block, lam, mptr, len(x), sweeps, x.ctypes.data_as(_dp),
                       res.ctypes.data_as(_dp), _threads(threads))
+    if rc != 0:
+        raise ValueError("bad block size")
+    return x, res[:sweeps]
+
+
+def drop_recompute(grid: OrcGrid, geom: OrcGeom, hist: dict, x0, order, block: int, lam: float, sweeps: int,
+                   mask=None, threads: int | None = None) -> tuple[np.ndarray, np.ndarray]:
+    """DROP with no stored rows: each block's rows are traced just before the
+    block is projected and then dropped (the case of A too large to keep,
+    Sec. 2 and Sec. 4.1); the residual after each sweep traces every row
+    again.  Same rows and summation order as ``drop(trace(...), ...)``.
+    Returns (x, residual per sweep)."""
+    lib = _load()
+    arrs, ptrs = _hist_ptrs(hist)
+    n = len(arrs[0])
+    x = np.array(x0, dtype=np.float64, copy=True)
+    order = np.ascontiguousarray(order, dtype=np.int64)
+    if len(order) != n:
+        raise ValueError("order must be a permutation of all histories")
+    res = np.empty(max(sweeps, 1))
+    mptr = None
+    if mask is not None:
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        mptr = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    rc = lib.orc_drop_recompute(ctypes.byref(grid), ctypes.byref(geom), n, ptrs, order.ctypes.data_as(_i64p), block,
+                                lam, mptr, len(x), sweeps, x.ctypes.data_as(_dp), res.ctypes.data_as(_dp),
+                                _threads(threads))
     if rc != 0:
         raise ValueError("bad block size")
     return x, res[:sweeps]

@@ -480,3 +480,136 @@ int orc_drop(int64_t n, const int64_t *row_ptr, const int32_t *idx, const double
     free(r);
     return 0;
 }
+
+/* --------------------------------------------------- DROP without stored A */
+/*
+ * The same block-iterative projections as orc_drop, for the case the paper
+ * raises in Sec. 2 and Sec. 4.1 (A of 10^8-10^9 rows too large to keep): each
+ * block's rows are traced from the histories just before the block is
+ * projected and then discarded, and the residual after a sweep traces every
+ * row once more.  Every row is the same as orc_trace makes it and every sum
+ * runs in the same order as orc_drop's (entries by ascending voxel, rows in
+ * block order for the scatter, rows by index for the residual), so given the
+ * same histories the result equals orc_drop on orc_trace's rows.
+ */
+typedef struct { int32_t *idx; double *len; int64_t cnt; double n2; } orc_row_t;
+
+/* row of history i, in freshly allocated arrays (caller frees) */
+static void trace_owned(const orc_grid *gr, const orc_geom *g, const float *const *hist, int64_t i, orc_row_t *r,
+                        double **wk, int *wcap) {
+    double h[H_NF];
+    for (int f = 0; f < H_NF; ++f) h[f] = (double)hist[f][i];
+    int64_t cap = 512;
+    for (;;) {
+        r->idx = (int32_t *)malloc((size_t)cap * sizeof(int32_t));
+        r->len = (double *)malloc((size_t)cap * sizeof(double));
+        r->cnt = trace_one(gr, g, h, r->idx, r->len, cap, &r->n2, wk, wcap);
+        if (r->cnt <= cap) return;
+        free(r->idx);
+        free(r->len);
+        cap = r->cnt;
+    }
+}
+
+int orc_drop_recompute(const orc_grid *gr, const orc_geom *g, int64_t n, const float *const *hist,
+                       const int64_t *order, int64_t block, double lambda, const uint8_t *mask, int64_t M,
+                       int32_t sweeps, double *x, double *resid, int32_t nthreads) {
+    if (block < 1) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    double *num = (double *)calloc((size_t)M, sizeof(double));
+    int64_t *cnt = (int64_t *)calloc((size_t)M, sizeof(int64_t));
+    int32_t *touched = (int32_t *)malloc((size_t)M * sizeof(int32_t));
+    double *r = (double *)malloc((size_t)block * sizeof(double));
+    orc_row_t *rows = (orc_row_t *)calloc((size_t)block, sizeof(orc_row_t));
+    if (mask)
+        for (int64_t j = 0; j < M; ++j)
+            if (!mask[j]) x[j] = 0.0;
+    for (int32_t sw = 0; sw < sweeps; ++sw) {
+        for (int64_t b0 = 0; b0 < n; b0 += block) {
+            int64_t nb = (n - b0 < block) ? n - b0 : block;
+            /* trace the block's rows, then project them against x at block start */
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+            {
+                int wcap = 512;
+                double *wk[3];
+                for (int q = 0; q < 3; ++q) wk[q] = (double *)malloc((size_t)wcap * sizeof(double));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 64)
+#endif
+                for (int64_t q = 0; q < nb; ++q) {
+                    int64_t i = order[b0 + q];
+                    trace_owned(gr, g, hist, i, &rows[q], wk, &wcap);
+                    if (rows[q].cnt == 0) { r[q] = 0.0; continue; }
+                    double d = 0.0;
+                    for (int64_t e = 0; e < rows[q].cnt; ++e) d += rows[q].len[e] * x[rows[q].idx[e]];
+                    r[q] = ((double)hist[H_WEPL][i] - d) / rows[q].n2;
+                }
+                for (int q = 0; q < 3; ++q) free(wk[q]);
+            }
+            /* accumulate in block order, then update */
+            int64_t nt = 0;
+            for (int64_t q = 0; q < nb; ++q) {
+                for (int64_t e = 0; e < rows[q].cnt; ++e) {
+                    int32_t j = rows[q].idx[e];
+                    if (cnt[j] == 0) touched[nt++] = j;
+                    num[j] += r[q] * rows[q].len[e];
+                    cnt[j] += 1;
+                }
+                free(rows[q].idx);
+                free(rows[q].len);
+                rows[q].idx = NULL;
+                rows[q].len = NULL;
+            }
+            for (int64_t q = 0; q < nt; ++q) {
+                int32_t j = touched[q];
+                if (!mask || mask[j]) x[j] += lambda * num[j] / (double)cnt[j];
+                num[j] = 0.0;
+                cnt[j] = 0;
+            }
+        }
+        if (resid) {
+            /* (a_i . x - b_i)^2 per row with its row traced again, summed by row index */
+            double *sq = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+            {
+                int wcap = 512;
+                double *wk[3];
+                for (int q = 0; q < 3; ++q) wk[q] = (double *)malloc((size_t)wcap * sizeof(double));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 64)
+#endif
+                for (int64_t i = 0; i < n; ++i) {
+                    orc_row_t rw;
+                    trace_owned(gr, g, hist, i, &rw, wk, &wcap);
+                    sq[i] = -1.0;
+                    if (rw.cnt > 0) {
+                        double d = 0.0;
+                        for (int64_t e = 0; e < rw.cnt; ++e) d += rw.len[e] * x[rw.idx[e]];
+                        double dd = d - (double)hist[H_WEPL][i];
+                        sq[i] = dd * dd;
+                    }
+                    free(rw.idx);
+                    free(rw.len);
+                }
+                for (int q = 0; q < 3; ++q) free(wk[q]);
+            }
+            double acc = 0.0;
+            for (int64_t i = 0; i < n; ++i)
+                if (sq[i] >= 0.0) acc += sq[i];
+            resid[sw] = sqrt(acc);
+            free(sq);
+        }
+    }
+    free(rows);
+    free(num);
+    free(cnt);
+    free(touched);
+    free(r);
+    return 0;
+}
