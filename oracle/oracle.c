@@ -426,6 +426,70 @@ double orc_residual(int64_t n, const int64_t *row_ptr, const int32_t *idx, const
     return residual_norm(n, row_ptr, idx, len, b, x);
 }
 
+/*
+ * The update of one block of nb rows (entries by ascending voxel):
+ *   num_j = sum_q r_q a_qj,  s_j = #{q : a_qj > 0},  x_j += lambda num_j / s_j
+ * for s_j > 0 and mask_j = 1; num and cnt are left at zero.  Threads own
+ * disjoint voxel ranges and each walks the rows in block order, so every
+ * voxel's sums run in block order whatever the thread count (the result is
+ * that of the plain sequential loop).
+ */
+static void scatter_apply(int64_t nb, int32_t *const *ridx, double *const *rlen, const int64_t *rcnt,
+                          const double *r, double lambda, const uint8_t *mask, int64_t M, double *x, double *num,
+                          int64_t *cnt) {
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+    {
+        int T = 1, t = 0;
+#ifdef _OPENMP
+        T = omp_get_num_threads();
+        t = omp_get_thread_num();
+#endif
+        int64_t j0 = M * t / T, j1 = M * (t + 1) / T;
+        for (int64_t q = 0; q < nb; ++q) {
+            const int32_t *ix = ridx[q];
+            int64_t lo = 0, hi = rcnt[q];
+            while (lo < hi) {   /* first entry with voxel >= j0 */
+                int64_t mid = (lo + hi) / 2;
+                if (ix[mid] < j0) lo = mid + 1; else hi = mid;
+            }
+            for (int64_t e = lo; e < rcnt[q] && ix[e] < j1; ++e) {
+                num[ix[e]] += r[q] * rlen[q][e];
+                cnt[ix[e]] += 1;
+            }
+        }
+        for (int64_t j = j0; j < j1; ++j) {
+            if (cnt[j] == 0) continue;
+            if (!mask || mask[j]) x[j] += lambda * num[j] / (double)cnt[j];
+            num[j] = 0.0;
+            cnt[j] = 0;
+        }
+    }
+}
+
+/* ||Ax - b||_2 over the non-empty rows: squares per row (in parallel), summed
+ * by row index */
+static double residual_norm_par(int64_t n, const int64_t *row_ptr, const int32_t *idx, const double *len,
+                                const double *b, const double *x) {
+    double *sq = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        sq[i] = -1.0;
+        if (row_ptr[i + 1] == row_ptr[i]) continue;
+        double d = 0.0;
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) d += len[e] * x[idx[e]];
+        sq[i] = (d - b[i]) * (d - b[i]);
+    }
+    double acc = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        if (sq[i] >= 0.0) acc += sq[i];
+    free(sq);
+    return sqrt(acc);
+}
+
 int orc_drop(int64_t n, const int64_t *row_ptr, const int32_t *idx, const double *len, const double *norm2,
              const double *b, const int64_t *order, int64_t block, double lambda, const uint8_t *mask, int64_t M,
              int32_t sweeps, double *x, double *resid, int32_t nthreads) {
@@ -435,8 +499,10 @@ int orc_drop(int64_t n, const int64_t *row_ptr, const int32_t *idx, const double
 #endif
     double *num = (double *)calloc((size_t)M, sizeof(double));
     int64_t *cnt = (int64_t *)calloc((size_t)M, sizeof(int64_t));
-    int32_t *touched = (int32_t *)malloc((size_t)M * sizeof(int32_t));
     double *r = (double *)malloc((size_t)block * sizeof(double));
+    int32_t **ridx = (int32_t **)malloc((size_t)block * sizeof(int32_t *));
+    double **rlen = (double **)malloc((size_t)block * sizeof(double *));
+    int64_t *rcnt = (int64_t *)malloc((size_t)block * sizeof(int64_t));
     if (mask)
         for (int64_t j = 0; j < M; ++j)
             if (!mask[j]) x[j] = 0.0;
@@ -449,35 +515,24 @@ int orc_drop(int64_t n, const int64_t *row_ptr, const int32_t *idx, const double
 #endif
             for (int64_t q = 0; q < nb; ++q) {
                 int64_t i = order[b0 + q];
-                if (row_ptr[i + 1] == row_ptr[i]) { r[q] = 0.0; continue; }
+                ridx[q] = (int32_t *)idx + row_ptr[i];
+                rlen[q] = (double *)len + row_ptr[i];
+                rcnt[q] = row_ptr[i + 1] - row_ptr[i];
+                if (rcnt[q] == 0) { r[q] = 0.0; continue; }
                 double d = 0.0;
                 for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) d += len[e] * x[idx[e]];
                 r[q] = (b[i] - d) / norm2[i];
             }
-            /* accumulate in block order */
-            int64_t nt = 0;
-            for (int64_t q = 0; q < nb; ++q) {
-                int64_t i = order[b0 + q];
-                for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-                    int32_t j = idx[e];
-                    if (cnt[j] == 0) touched[nt++] = j;
-                    num[j] += r[q] * len[e];
-                    cnt[j] += 1;
-                }
-            }
-            for (int64_t q = 0; q < nt; ++q) {
-                int32_t j = touched[q];
-                if (!mask || mask[j]) x[j] += lambda * num[j] / (double)cnt[j];
-                num[j] = 0.0;
-                cnt[j] = 0;
-            }
+            scatter_apply(nb, ridx, rlen, rcnt, r, lambda, mask, M, x, num, cnt);
         }
-        if (resid) resid[sw] = residual_norm(n, row_ptr, idx, len, b, x);
+        if (resid) resid[sw] = residual_norm_par(n, row_ptr, idx, len, b, x);
     }
     free(num);
     free(cnt);
-    free(touched);
     free(r);
+    free(ridx);
+    free(rlen);
+    free(rcnt);
     return 0;
 }
 
@@ -520,8 +575,10 @@ int orc_drop_recompute(const orc_grid *gr, const orc_geom *g, int64_t n, const f
 #endif
     double *num = (double *)calloc((size_t)M, sizeof(double));
     int64_t *cnt = (int64_t *)calloc((size_t)M, sizeof(int64_t));
-    int32_t *touched = (int32_t *)malloc((size_t)M * sizeof(int32_t));
     double *r = (double *)malloc((size_t)block * sizeof(double));
+    int32_t **ridx = (int32_t **)malloc((size_t)block * sizeof(int32_t *));
+    double **rlen = (double **)malloc((size_t)block * sizeof(double *));
+    int64_t *rcnt = (int64_t *)malloc((size_t)block * sizeof(int64_t));
     orc_row_t *rows = (orc_row_t *)calloc((size_t)block, sizeof(orc_row_t));
     if (mask)
         for (int64_t j = 0; j < M; ++j)
@@ -551,24 +608,17 @@ int orc_drop_recompute(const orc_grid *gr, const orc_geom *g, int64_t n, const f
                 for (int q = 0; q < 3; ++q) free(wk[q]);
             }
             /* accumulate in block order, then update */
-            int64_t nt = 0;
             for (int64_t q = 0; q < nb; ++q) {
-                for (int64_t e = 0; e < rows[q].cnt; ++e) {
-                    int32_t j = rows[q].idx[e];
-                    if (cnt[j] == 0) touched[nt++] = j;
-                    num[j] += r[q] * rows[q].len[e];
-                    cnt[j] += 1;
-                }
+                ridx[q] = rows[q].idx;
+                rlen[q] = rows[q].len;
+                rcnt[q] = rows[q].cnt;
+            }
+            scatter_apply(nb, ridx, rlen, rcnt, r, lambda, mask, M, x, num, cnt);
+            for (int64_t q = 0; q < nb; ++q) {
                 free(rows[q].idx);
                 free(rows[q].len);
                 rows[q].idx = NULL;
                 rows[q].len = NULL;
-            }
-            for (int64_t q = 0; q < nt; ++q) {
-                int32_t j = touched[q];
-                if (!mask || mask[j]) x[j] += lambda * num[j] / (double)cnt[j];
-                num[j] = 0.0;
-                cnt[j] = 0;
             }
         }
         if (resid) {
@@ -609,7 +659,9 @@ int orc_drop_recompute(const orc_grid *gr, const orc_geom *g, int64_t n, const f
     free(rows);
     free(num);
     free(cnt);
-    free(touched);
     free(r);
+    free(ridx);
+    free(rlen);
+    free(rcnt);
     return 0;
 }
