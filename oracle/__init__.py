@@ -15,7 +15,11 @@ The arithmetic lives in ``oracle.c`` (plain FP64 C):
   * ``drop_recompute`` -- the same DROP with no stored A: each block's rows are
                         traced, projected and dropped (A too large to keep,
                         Sec. 2 and Sec. 4.1);
-  * ``residual``     -- ||Ax - b||_2.
+  * ``residual``     -- ||Ax - b||_2;
+  * ``tv``, ``tv_grad``, ``tvs_apply`` -- total variation and the TV
+                        superiorization step (Sec. 4.2); ``drop_tvs`` -- DROP
+                        with it before every block;
+  * ``carp``         -- component-averaged row projections (Sec. 2.2).
 ``roi_means`` is the ROI analysis of Sec. 3.2 / 4.2 (mean RSP per insert).
 ``oracle.cnn`` (NumPy, FP64) holds the operations and gradients of the
 warm-start network that produces x0 (Sec. 2.1 leaves x0 open).
@@ -58,6 +62,11 @@ class OrcGeom(ctypes.Structure):
                 ("poly", ctypes.c_double * 8), ("E0", ctypes.c_double), ("X0", ctypes.c_double)]
 
 
+class OrcTvs(ctypes.Structure):
+    _fields_ = [("n_steps", ctypes.c_int32), ("max_trials", ctypes.c_int32), ("a", ctypes.c_double),
+                ("eps", ctypes.c_double)]
+
+
 _lib = None
 _dp = ctypes.POINTER(ctypes.c_double)
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -90,6 +99,21 @@ def _load():
                                            ctypes.POINTER(ctypes.POINTER(ctypes.c_float)), _i64p, ctypes.c_int64,
                                            ctypes.c_double, ctypes.POINTER(ctypes.c_uint8), ctypes.c_int64,
                                            ctypes.c_int32, _dp, _dp, ctypes.c_int32]
+        lib.orc_tv.restype = ctypes.c_double
+        lib.orc_tv.argtypes = [ctypes.POINTER(OrcGrid), _dp, ctypes.c_double]
+        lib.orc_tv_grad.restype = None
+        lib.orc_tv_grad.argtypes = [ctypes.POINTER(OrcGrid), _dp, ctypes.c_double, _dp]
+        lib.orc_tvs_apply.restype = ctypes.c_int
+        lib.orc_tvs_apply.argtypes = [ctypes.POINTER(OrcGrid), ctypes.POINTER(OrcTvs), ctypes.POINTER(ctypes.c_uint8),
+                                      _dp, _dp]
+        lib.orc_drop_tvs.restype = ctypes.c_int
+        lib.orc_drop_tvs.argtypes = [ctypes.POINTER(OrcGrid), ctypes.c_int64, _i64p, _i32p, _dp, _dp, _dp, _i64p,
+                                     ctypes.c_int64, ctypes.c_double, ctypes.POINTER(ctypes.c_uint8), ctypes.c_int32,
+                                     ctypes.POINTER(OrcTvs), _dp, _dp, _dp, ctypes.c_int32]
+        lib.orc_carp.restype = ctypes.c_int
+        lib.orc_carp.argtypes = [ctypes.POINTER(OrcGrid), ctypes.c_int64, _i64p, _i32p, _dp, _dp, _dp, _i64p,
+                                 ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.POINTER(ctypes.c_uint8),
+                                 ctypes.c_int32, ctypes.POINTER(OrcTvs), _dp, _dp, _dp, ctypes.c_int32]
         _lib = lib
     return _lib
 
@@ -247,6 +271,83 @@ def drop_recompute(grid: OrcGrid, geom: OrcGeom, hist: dict, x0, order, block: i
     if rc != 0:
         raise ValueError("bad block size")
     return x, res[:sweeps]
+
+
+def _u8p(mask):
+    if mask is None:
+        return None, None
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    return m, m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+def tv(grid: OrcGrid, x, eps: float) -> float:
+    """Total variation (forward differences, smoothed by eps) of an image."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return _load().orc_tv(ctypes.byref(grid), x.ctypes.data_as(_dp), eps)
+
+
+def tv_grad(grid: OrcGrid, x, eps: float) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    g = np.empty_like(x)
+    _load().orc_tv_grad(ctypes.byref(grid), x.ctypes.data_as(_dp), eps, g.ctypes.data_as(_dp))
+    return g
+
+
+def make_tvs(n_steps: int = 1, max_trials: int = 3, a: float = 0.995, eps: float = 1e-3) -> OrcTvs:
+    return OrcTvs(int(n_steps), int(max_trials), float(a), float(eps))
+
+
+def tvs_apply(grid: OrcGrid, x, tvs: OrcTvs, beta: float, mask=None) -> tuple[np.ndarray, float, int]:
+    """TVS steps (Sec. 4.2) on a copy of x; returns (x, beta after, accepted steps)."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    b = ctypes.c_double(beta)
+    m, mp = _u8p(mask)
+    acc = _load().orc_tvs_apply(ctypes.byref(grid), ctypes.byref(tvs), mp, x.ctypes.data_as(_dp), ctypes.byref(b))
+    return x, b.value, acc
+
+
+def drop_tvs(grid: OrcGrid, rows: Rows, b, x0, order, block: int, lam: float, sweeps: int, tvs: OrcTvs,
+             beta: float, mask=None, threads: int | None = None) -> tuple[np.ndarray, np.ndarray, float]:
+    """DROP with TVS steps on the image entering every block.  Returns (x,
+    residual per sweep, beta after)."""
+    lib = _load()
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.array(x0, dtype=np.float64, copy=True)
+    order = np.ascontiguousarray(order, dtype=np.int64)
+    res = np.empty(max(sweeps, 1))
+    bt = ctypes.c_double(beta)
+    m, mp = _u8p(mask)
+    rc = lib.orc_drop_tvs(ctypes.byref(grid), rows.n, rows.row_ptr.ctypes.data_as(_i64p),
+                          rows.idx.ctypes.data_as(_i32p), rows.len.ctypes.data_as(_dp),
+                          rows.norm2.ctypes.data_as(_dp), b.ctypes.data_as(_dp), order.ctypes.data_as(_i64p), block,
+                          lam, mp, sweeps, ctypes.byref(tvs), ctypes.byref(bt), x.ctypes.data_as(_dp),
+                          res.ctypes.data_as(_dp), _threads(threads))
+    if rc != 0:
+        raise ValueError("bad arguments")
+    return x, res[:sweeps], bt.value
+
+
+def carp(grid: OrcGrid, rows: Rows, b, x0, order, n_strings: int, block: int, lam: float, iters: int,
+         mask=None, tvs: OrcTvs | None = None, beta: float = 0.0,
+         threads: int | None = None) -> tuple[np.ndarray, np.ndarray, float]:
+    """CARP (Sec. 2.2): strings of consecutive order positions, each a DROP
+    sweep from the common x, then component averaging over the strings that
+    touch each voxel.  Returns (x, residual per iteration, beta after)."""
+    lib = _load()
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.array(x0, dtype=np.float64, copy=True)
+    order = np.ascontiguousarray(order, dtype=np.int64)
+    res = np.empty(max(iters, 1))
+    bt = ctypes.c_double(beta)
+    m, mp = _u8p(mask)
+    rc = lib.orc_carp(ctypes.byref(grid), rows.n, rows.row_ptr.ctypes.data_as(_i64p), rows.idx.ctypes.data_as(_i32p),
+                      rows.len.ctypes.data_as(_dp), rows.norm2.ctypes.data_as(_dp), b.ctypes.data_as(_dp),
+                      order.ctypes.data_as(_i64p), n_strings, block, lam, mp, iters,
+                      ctypes.byref(tvs) if tvs is not None else None, ctypes.byref(bt), x.ctypes.data_as(_dp),
+                      res.ctypes.data_as(_dp), _threads(threads))
+    if rc != 0:
+        raise ValueError("bad arguments")
+    return x, res[:iters], bt.value
 
 
 def roi_means(x, labels, n_labels: int) -> np.ndarray:

@@ -396,6 +396,100 @@ int64_t orc_trace(const orc_grid *gr, const orc_geom *g, int64_t n, const float 
     return row_ptr[n];
 }
 
+/* ------------------------------------------- total-variation superiorization */
+/*
+ * TVS (Sec. 4.2, the Table 2 discussion: both pipelines perturb the image
+ * towards lower total variation; DROP does it to the image entering every
+ * block, CARP once at the start of every iteration).  The paper gives no
+ * formula; this follows the superiorization scheme of the pCT literature it
+ * builds on (Penfold et al. 2010), in 3D:
+ *   TV(x)  = sum over voxels v of sqrt(dx_v^2 + dy_v^2 + dz_v^2 + eps^2),
+ *            d*_v = x(v + e_*) - x(v) (forward difference; 0 at the grid's
+ *            last plane on that axis);
+ *   g      = dTV/dx (zeroed outside the mask), v = -g / ||g||_2;
+ *   one step: try z = x + beta v, then beta <- a beta; accept z if
+ *            TV(z) <= TV(x), else try again with the smaller beta, at most
+ *            max_trials times.  beta keeps shrinking from call to call, so
+ *            the perturbations are summable.
+ */
+typedef struct {
+    int32_t n_steps;      /* perturbation steps per call */
+    int32_t max_trials;   /* step sizes tried per step */
+    double a;             /* beta factor per trial, 0 < a < 1 */
+    double eps;           /* smoothing of the TV norm */
+} orc_tvs;
+
+static double tv_term(const orc_grid *gr, const double *x, int64_t i, int64_t j, int64_t k, double eps) {
+    int64_t nx = gr->nx, ny = gr->ny, nz = gr->nz;
+    int64_t v = (k * ny + j) * nx + i;
+    double dx = (i + 1 < nx) ? x[v + 1] - x[v] : 0.0;
+    double dy = (j + 1 < ny) ? x[v + nx] - x[v] : 0.0;
+    double dz = (k + 1 < nz) ? x[v + nx * ny] - x[v] : 0.0;
+    return sqrt(dx * dx + dy * dy + dz * dz + eps * eps);
+}
+
+double orc_tv(const orc_grid *gr, const double *x, double eps) {
+    double acc = 0.0;
+    for (int64_t k = 0; k < gr->nz; ++k)
+        for (int64_t j = 0; j < gr->ny; ++j)
+            for (int64_t i = 0; i < gr->nx; ++i) acc += tv_term(gr, x, i, j, k, eps);
+    return acc;
+}
+
+/* g = dTV/dx: voxel u enters its own term (as -d*_u) and the terms of its
+ * three lower neighbours (as +d*_{u - e_*}) */
+void orc_tv_grad(const orc_grid *gr, const double *x, double eps, double *g) {
+    int64_t nx = gr->nx, ny = gr->ny, nz = gr->nz;
+    int64_t M = nx * ny * nz;
+    for (int64_t u = 0; u < M; ++u) g[u] = 0.0;
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                int64_t v = (k * ny + j) * nx + i;
+                double dx = (i + 1 < nx) ? x[v + 1] - x[v] : 0.0;
+                double dy = (j + 1 < ny) ? x[v + nx] - x[v] : 0.0;
+                double dz = (k + 1 < nz) ? x[v + nx * ny] - x[v] : 0.0;
+                double phi = sqrt(dx * dx + dy * dy + dz * dz + eps * eps);
+                g[v] -= (dx + dy + dz) / phi;
+                if (i + 1 < nx) g[v + 1] += dx / phi;
+                if (j + 1 < ny) g[v + nx] += dy / phi;
+                if (k + 1 < nz) g[v + nx * ny] += dz / phi;
+            }
+}
+
+/* TVS steps on x (mask: voxels that may change; NULL = all).  *beta is the
+ * current step size, updated in place.  Returns the number of accepted steps. */
+int orc_tvs_apply(const orc_grid *gr, const orc_tvs *t, const uint8_t *mask, double *x, double *beta) {
+    int64_t M = (int64_t)gr->nx * gr->ny * gr->nz;
+    double *g = (double *)malloc((size_t)M * sizeof(double));
+    double *z = (double *)malloc((size_t)M * sizeof(double));
+    int accepted = 0;
+    for (int s = 0; s < t->n_steps; ++s) {
+        orc_tv_grad(gr, x, t->eps, g);
+        double nrm = 0.0;
+        for (int64_t u = 0; u < M; ++u) {
+            if (mask && !mask[u]) g[u] = 0.0;
+            nrm += g[u] * g[u];
+        }
+        nrm = sqrt(nrm);
+        if (!(nrm > 0.0)) break;
+        double tvx = orc_tv(gr, x, t->eps);
+        for (int trial = 0; trial < t->max_trials; ++trial) {
+            double bt = *beta;
+            *beta *= t->a;
+            for (int64_t u = 0; u < M; ++u) z[u] = x[u] - bt * g[u] / nrm;
+            if (orc_tv(gr, z, t->eps) <= tvx) {
+                memcpy(x, z, (size_t)M * sizeof(double));
+                accepted++;
+                break;
+            }
+        }
+    }
+    free(g);
+    free(z);
+    return accepted;
+}
+
 /* --------------------------------------------------------------- solvers */
 /*
  * Block-iterative row projection (DROP, paper Sec. 2.1).  The rows are taken
@@ -436,7 +530,7 @@ double orc_residual(int64_t n, const int64_t *row_ptr, const int32_t *idx, const
  */
 static void scatter_apply(int64_t nb, int32_t *const *ridx, double *const *rlen, const int64_t *rcnt,
                           const double *r, double lambda, const uint8_t *mask, int64_t M, double *x, double *num,
-                          int64_t *cnt) {
+                          int64_t *cnt, uint8_t *touched) {
 #ifdef _OPENMP
 #pragma omp parallel
 #endif
@@ -461,6 +555,7 @@ static void scatter_apply(int64_t nb, int32_t *const *ridx, double *const *rlen,
         }
         for (int64_t j = j0; j < j1; ++j) {
             if (cnt[j] == 0) continue;
+            if (touched) touched[j] = 1;
             if (!mask || mask[j]) x[j] += lambda * num[j] / (double)cnt[j];
             num[j] = 0.0;
             cnt[j] = 0;
@@ -490,6 +585,66 @@ static double residual_norm_par(int64_t n, const int64_t *row_ptr, const int32_t
     return sqrt(acc);
 }
 
+/* scratch of a stored-row DROP sweep */
+typedef struct {
+    double *num, *r;
+    int64_t *cnt;
+    int32_t **ridx;
+    double **rlen;
+    int64_t *rcnt;
+} drop_work;
+
+static drop_work drop_work_alloc(int64_t M, int64_t block) {
+    drop_work w;
+    w.num = (double *)calloc((size_t)M, sizeof(double));
+    w.cnt = (int64_t *)calloc((size_t)M, sizeof(int64_t));
+    w.r = (double *)malloc((size_t)block * sizeof(double));
+    w.ridx = (int32_t **)malloc((size_t)block * sizeof(int32_t *));
+    w.rlen = (double **)malloc((size_t)block * sizeof(double *));
+    w.rcnt = (int64_t *)malloc((size_t)block * sizeof(int64_t));
+    return w;
+}
+
+static void drop_work_free(drop_work *w) {
+    free(w->num);
+    free(w->cnt);
+    free(w->r);
+    free(w->ridx);
+    free(w->rlen);
+    free(w->rcnt);
+}
+
+/*
+ * One DROP sweep over the rows at positions [p0, p1) of `order`, in
+ * consecutive blocks of `block` positions from p0.  With tvs given, the TVS
+ * steps are applied to the image that enters each block.  touched (or NULL):
+ * set to 1 for every voxel some row of the range touches.
+ */
+static void drop_sweep_range(const int64_t *row_ptr, const int32_t *idx, const double *len, const double *norm2,
+                             const double *b, const int64_t *order, int64_t p0, int64_t p1, int64_t block,
+                             double lambda, const uint8_t *mask, int64_t M, double *x, drop_work *w,
+                             const orc_grid *gr, const orc_tvs *tvs, double *beta, uint8_t *touched) {
+    for (int64_t b0 = p0; b0 < p1; b0 += block) {
+        int64_t nb = (p1 - b0 < block) ? p1 - b0 : block;
+        if (tvs) orc_tvs_apply(gr, tvs, mask, x, beta);
+        /* projections against x at block start */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) if (nb > 4096)
+#endif
+        for (int64_t q = 0; q < nb; ++q) {
+            int64_t i = order[b0 + q];
+            w->ridx[q] = (int32_t *)idx + row_ptr[i];
+            w->rlen[q] = (double *)len + row_ptr[i];
+            w->rcnt[q] = row_ptr[i + 1] - row_ptr[i];
+            if (w->rcnt[q] == 0) { w->r[q] = 0.0; continue; }
+            double d = 0.0;
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) d += len[e] * x[idx[e]];
+            w->r[q] = (b[i] - d) / norm2[i];
+        }
+        scatter_apply(nb, w->ridx, w->rlen, w->rcnt, w->r, lambda, mask, M, x, w->num, w->cnt, touched);
+    }
+}
+
 int orc_drop(int64_t n, const int64_t *row_ptr, const int32_t *idx, const double *len, const double *norm2,
              const double *b, const int64_t *order, int64_t block, double lambda, const uint8_t *mask, int64_t M,
              int32_t sweeps, double *x, double *resid, int32_t nthreads) {
@@ -497,42 +652,95 @@ int orc_drop(int64_t n, const int64_t *row_ptr, const int32_t *idx, const double
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
-    double *num = (double *)calloc((size_t)M, sizeof(double));
-    int64_t *cnt = (int64_t *)calloc((size_t)M, sizeof(int64_t));
-    double *r = (double *)malloc((size_t)block * sizeof(double));
-    int32_t **ridx = (int32_t **)malloc((size_t)block * sizeof(int32_t *));
-    double **rlen = (double **)malloc((size_t)block * sizeof(double *));
-    int64_t *rcnt = (int64_t *)malloc((size_t)block * sizeof(int64_t));
+    drop_work w = drop_work_alloc(M, block);
     if (mask)
         for (int64_t j = 0; j < M; ++j)
             if (!mask[j]) x[j] = 0.0;
     for (int32_t sw = 0; sw < sweeps; ++sw) {
-        for (int64_t b0 = 0; b0 < n; b0 += block) {
-            int64_t nb = (n - b0 < block) ? n - b0 : block;
-            /* projections against x at block start */
-#ifdef _OPENMP
-#pragma omp parallel for schedule(static) if (nb > 4096)
-#endif
-            for (int64_t q = 0; q < nb; ++q) {
-                int64_t i = order[b0 + q];
-                ridx[q] = (int32_t *)idx + row_ptr[i];
-                rlen[q] = (double *)len + row_ptr[i];
-                rcnt[q] = row_ptr[i + 1] - row_ptr[i];
-                if (rcnt[q] == 0) { r[q] = 0.0; continue; }
-                double d = 0.0;
-                for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) d += len[e] * x[idx[e]];
-                r[q] = (b[i] - d) / norm2[i];
-            }
-            scatter_apply(nb, ridx, rlen, rcnt, r, lambda, mask, M, x, num, cnt);
-        }
+        drop_sweep_range(row_ptr, idx, len, norm2, b, order, 0, n, block, lambda, mask, M, x, &w, NULL, NULL, NULL,
+                         NULL);
         if (resid) resid[sw] = residual_norm_par(n, row_ptr, idx, len, b, x);
     }
-    free(num);
-    free(cnt);
-    free(r);
-    free(ridx);
-    free(rlen);
-    free(rcnt);
+    drop_work_free(&w);
+    return 0;
+}
+
+/* DROP with the TVS steps before every block (Sec. 4.2); *beta as in
+ * orc_tvs_apply, carried across blocks and sweeps. */
+int orc_drop_tvs(const orc_grid *gr, int64_t n, const int64_t *row_ptr, const int32_t *idx, const double *len,
+                 const double *norm2, const double *b, const int64_t *order, int64_t block, double lambda,
+                 const uint8_t *mask, int32_t sweeps, const orc_tvs *tvs, double *beta, double *x, double *resid,
+                 int32_t nthreads) {
+    if (block < 1 || !tvs) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    int64_t M = (int64_t)gr->nx * gr->ny * gr->nz;
+    drop_work w = drop_work_alloc(M, block);
+    if (mask)
+        for (int64_t j = 0; j < M; ++j)
+            if (!mask[j]) x[j] = 0.0;
+    for (int32_t sw = 0; sw < sweeps; ++sw) {
+        drop_sweep_range(row_ptr, idx, len, norm2, b, order, 0, n, block, lambda, mask, M, x, &w, gr, tvs, beta,
+                         NULL);
+        if (resid) resid[sw] = residual_norm_par(n, row_ptr, idx, len, b, x);
+    }
+    drop_work_free(&w);
+    return 0;
+}
+
+/*
+ * CARP (Sec. 2.2, component-averaged row projections; Gordon & Gordon
+ * 2005): the positions of `order` are split into n_strings consecutive
+ * strings, string s = [n s / S, n (s+1) / S).  Every iteration each string
+ * starts from the same x and runs one DROP sweep over its own rows (blocks
+ * of `block` positions from the string's start) into its own image x_s;
+ * then every voxel becomes the mean of x_s over the strings whose rows touch
+ * it (voxels no string touches keep their value).  With tvs given, the TVS
+ * steps are applied once to x at the start of every iteration.
+ */
+int orc_carp(const orc_grid *gr, int64_t n, const int64_t *row_ptr, const int32_t *idx, const double *len,
+             const double *norm2, const double *b, const int64_t *order, int32_t n_strings, int64_t block,
+             double lambda, const uint8_t *mask, int32_t iters, const orc_tvs *tvs, double *beta, double *x,
+             double *resid, int32_t nthreads) {
+    if (block < 1 || n_strings < 1) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    int64_t M = (int64_t)gr->nx * gr->ny * gr->nz;
+    drop_work w = drop_work_alloc(M, block);
+    double *xs = (double *)malloc((size_t)M * sizeof(double));
+    double *acc = (double *)malloc((size_t)M * sizeof(double));
+    int32_t *tc = (int32_t *)malloc((size_t)M * sizeof(int32_t));
+    uint8_t *touched = (uint8_t *)malloc((size_t)M);
+    if (mask)
+        for (int64_t j = 0; j < M; ++j)
+            if (!mask[j]) x[j] = 0.0;
+    for (int32_t it = 0; it < iters; ++it) {
+        if (tvs) orc_tvs_apply(gr, tvs, mask, x, beta);
+        memset(acc, 0, (size_t)M * sizeof(double));
+        memset(tc, 0, (size_t)M * sizeof(int32_t));
+        for (int32_t s = 0; s < n_strings; ++s) {
+            int64_t p0 = n * s / n_strings, p1 = n * (s + 1) / n_strings;
+            memcpy(xs, x, (size_t)M * sizeof(double));
+            memset(touched, 0, (size_t)M);
+            drop_sweep_range(row_ptr, idx, len, norm2, b, order, p0, p1, block, lambda, mask, M, xs, &w, NULL, NULL,
+                             NULL, touched);
+            for (int64_t j = 0; j < M; ++j)
+                if (touched[j]) {
+                    acc[j] += xs[j];
+                    tc[j] += 1;
+                }
+        }
+        for (int64_t j = 0; j < M; ++j)
+            if (tc[j] > 0) x[j] = acc[j] / (double)tc[j];
+        if (resid) resid[it] = residual_norm_par(n, row_ptr, idx, len, b, x);
+    }
+    drop_work_free(&w);
+    free(xs);
+    free(acc);
+    free(tc);
+    free(touched);
     return 0;
 }
 
@@ -613,7 +821,7 @@ int orc_drop_recompute(const orc_grid *gr, const orc_geom *g, int64_t n, const f
                 rlen[q] = rows[q].len;
                 rcnt[q] = rows[q].cnt;
             }
-            scatter_apply(nb, ridx, rlen, rcnt, r, lambda, mask, M, x, num, cnt);
+            scatter_apply(nb, ridx, rlen, rcnt, r, lambda, mask, M, x, num, cnt, NULL);
             for (int64_t q = 0; q < nb; ++q) {
                 free(rows[q].idx);
                 free(rows[q].len);
@@ -665,3 +873,4 @@ int orc_drop_recompute(const orc_grid *gr, const orc_geom *g, int64_t n, const f
     free(rcnt);
     return 0;
 }
+
