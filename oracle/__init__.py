@@ -19,7 +19,9 @@ The arithmetic lives in ``oracle.c`` (plain FP64 C):
   * ``tv``, ``tv_grad``, ``tvs_apply`` -- total variation and the TV
                         superiorization step (Sec. 4.2); ``drop_tvs`` -- DROP
                         with it before every block;
-  * ``carp``         -- component-averaged row projections (Sec. 2.2).
+  * ``carp``         -- component-averaged row projections (Sec. 2.2);
+  * ``carve``        -- the space-carving hull from protons that crossed
+                        only air.
 ``roi_means`` is the ROI analysis of Sec. 3.2 / 4.2 (mean RSP per insert).
 ``oracle.cnn`` (NumPy, FP64) holds the operations and gradients of the
 warm-start network that produces x0 (Sec. 2.1 leaves x0 open).
@@ -114,6 +116,10 @@ def _load():
         lib.orc_carp.argtypes = [ctypes.POINTER(OrcGrid), ctypes.c_int64, _i64p, _i32p, _dp, _dp, _dp, _i64p,
                                  ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.POINTER(ctypes.c_uint8),
                                  ctypes.c_int32, ctypes.POINTER(OrcTvs), _dp, _dp, _dp, ctypes.c_int32]
+        lib.orc_carve.restype = ctypes.c_int64
+        lib.orc_carve.argtypes = [ctypes.POINTER(OrcGrid), ctypes.POINTER(OrcGeom), ctypes.c_int64,
+                                  ctypes.POINTER(ctypes.POINTER(ctypes.c_float)), ctypes.c_double, ctypes.c_double,
+                                  ctypes.POINTER(ctypes.c_uint8), ctypes.c_int32]
         _lib = lib
     return _lib
 
@@ -348,6 +354,20 @@ def carp(grid: OrcGrid, rows: Rows, b, x0, order, n_strings: int, block: int, la
     if rc != 0:
         raise ValueError("bad arguments")
     return x, res[:iters], bt.value
+
+
+def carve(grid: OrcGrid, geom: OrcGeom, hist: dict, wepl_max: float, min_len: float = 1e-6,
+          threads: int | None = None) -> tuple[np.ndarray, int]:
+    """Space-carving hull: (carved mask uint8 [M], histories used).  Voxels
+    that the straight line of a history with WEPL below wepl_max crosses for
+    more than min_len mm are carved (outside the object)."""
+    lib = _load()
+    arrs, ptrs = _hist_ptrs(hist)
+    M = grid.nx * grid.ny * grid.nz
+    out = np.zeros(M, dtype=np.uint8)
+    used = lib.orc_carve(ctypes.byref(grid), ctypes.byref(geom), len(arrs[0]), ptrs, wepl_max, min_len,
+                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), _threads(threads))
+    return out, int(used)
 
 
 def roi_means(x, labels, n_labels: int) -> np.ndarray:

@@ -874,3 +874,49 @@ int orc_drop_recompute(const orc_grid *gr, const orc_geom *g, int64_t n, const f
     return 0;
 }
 
+
+/* ------------------------------------------------------ space-carving hull */
+/*
+ * Hull from the data (the configurations' "hull" when no analytic outline is
+ * known): a proton whose WEPL is below wepl_max crossed only air, so every
+ * voxel its straight line (the entry tracker's position and slope, from
+ * u_in to u_out) passes through for more than min_len mm lies outside the
+ * object and is carved (carved[j] = 1; the caller zeroes the array).  The
+ * line is cut into voxel pieces by Siddon's method, as for the rows.
+ * Returns the number of histories used.
+ */
+int64_t orc_carve(const orc_grid *gr, const orc_geom *g, int64_t n, const float *const *hist, double wepl_max,
+                  double min_len, uint8_t *carved, int32_t nthreads) {
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    int64_t used = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : used)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        double h[H_NF];
+        int fin = 1;
+        for (int f = 0; f < H_NF; ++f) {
+            h[f] = (double)hist[f][i];
+            fin = fin && isfinite(h[f]);
+        }
+        if (!fin || !(h[H_WEPL] < wepl_max)) continue;
+        used++;
+        double P[3], Q[3];
+        double u0 = g->u_in, u1 = g->u_out;
+        beam_to_object(h[H_PHI], u0, h[H_TIN], h[H_VIN], P);
+        beam_to_object(h[H_PHI], u1, h[H_TIN] + h[H_DTIN] * (u1 - u0), h[H_VIN] + h[H_DVIN] * (u1 - u0), Q);
+        pbuf_t b = {0, 0, 0};
+        siddon_segment(gr, P, Q, &b);
+        for (int64_t q = 0; q < b.n; ++q)
+            if (b.p[q].l > min_len) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+                carved[b.p[q].j] = 1;
+            }
+        free(b.p);
+    }
+    return used;
+}

@@ -26,13 +26,25 @@ _SO = os.path.join(_HERE, "libpctgen.so")
 HIST_FIELDS = ("phi", "t_in", "v_in", "dt_in", "dv_in", "t_out", "v_out", "dt_out", "dv_out", "wepl")
 
 
+_SO_GPU = os.path.join(_HERE, "libpctgen_hip.so")
+
+
 def build(force: bool = True) -> str:
-    """Compile the generator with gcc (FP64, OpenMP, no fast-math)."""
+    """Compile the host generator with gcc (FP64, OpenMP, no fast-math) and
+    the device generator with hipcc for gfx950."""
     if force or not os.path.exists(_SO):
         cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", _SO + ".tmp",
                os.path.join(_HERE, "gen.c"), "-lm"]
         subprocess.check_call(cmd)
         os.replace(_SO + ".tmp", _SO)
+    if force or not os.path.exists(_SO_GPU):
+        hipcc = os.environ.get("HIPCC") or ("/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else "hipcc")
+        arch = os.environ.get("PCT_OFFLOAD_ARCH", "gfx950")
+        cmd = [hipcc, "-O3", "-std=c++17", f"--offload-arch={arch}", "-fPIC", "-shared",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-o", _SO_GPU + ".tmp", os.path.join(_HERE, "gen_gpu.hip")]
+        subprocess.check_call(cmd, stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+        os.replace(_SO_GPU + ".tmp", _SO_GPU)
     return _SO
 
 
@@ -66,6 +78,8 @@ def _load():
         lib.pctgen_histories.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Shape), ctypes.c_int32,
                                          ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64] + [fp] * 10 + [
                                             ctypes.c_int32]
+        lib.pctgen_miss_histories.restype = ctypes.c_int64
+        lib.pctgen_miss_histories.argtypes = lib.pctgen_histories.argtypes
         lib.pctgen_segment_wepl.restype = ctypes.c_double
         lib.pctgen_segment_wepl.argtypes = [ctypes.POINTER(_Shape), ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -337,6 +351,68 @@ def generate(cfg: Config, n: int | None = None, start: int = 0, seed: int | None
                                  threads or default_threads())
     if fails:
         raise RuntimeError(f"{fails} histories could not be generated")
+    return out
+
+
+def generate_misses(cfg: Config, n: int, start: int = 0, seed: int | None = None,
+                    threads: int | None = None) -> dict:
+    """Histories [start, start+n) of the seeded stream of protons that miss
+    the body (straight lines through air, WEPL = noise), float32 SoA: the
+    input of the space-carving hull."""
+    lib = _load()
+    n = int(n)
+    seed = cfg.seed if seed is None else seed
+    out = {k: np.empty(n, dtype=np.float32) for k in HIST_FIELDS}
+    shapes, ns = cfg.phantom.shapes_c()
+    p = _params_c(cfg)
+    fp = ctypes.POINTER(ctypes.c_float)
+    ptrs = [out[k].ctypes.data_as(fp) for k in HIST_FIELDS]
+    fails = lib.pctgen_miss_histories(ctypes.byref(p), shapes, ns, ctypes.c_uint64(seed), start, n, *ptrs,
+                                      threads or default_threads())
+    if fails:
+        raise RuntimeError(f"{fails} miss histories could not be generated")
+    return out
+
+
+_lib_gpu = None
+
+
+def _load_gpu():
+    global _lib_gpu
+    if _lib_gpu is None:
+        if not os.path.exists(_SO_GPU):
+            raise ImportError(f"{_SO_GPU} is missing: run synth.build()")
+        lib = ctypes.CDLL(_SO_GPU)
+        lib.pctgen_gpu_histories.restype = ctypes.c_int
+        lib.pctgen_gpu_histories.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64,
+                                             ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p),
+                                             ctypes.c_void_p, ctypes.c_void_p]
+        _lib_gpu = lib
+    return _lib_gpu
+
+
+def generate_gpu(cfg: Config, n: int | None = None, start: int = 0, seed: int | None = None, device=None) -> dict:
+    """Histories [start, start+n) of the same seeded sequence as generate(),
+    made on the GPU straight into device memory: a dict of float32 torch
+    tensors (torch supplies the allocations and the stream)."""
+    import torch
+    lib = _load_gpu()
+    n = cfg.n if n is None else int(n)
+    seed = cfg.seed if seed is None else seed
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    out = {k: torch.empty(n, dtype=torch.float32, device=dev) for k in HIST_FIELDS}
+    fails = torch.zeros(1, dtype=torch.int64, device=dev)
+    shapes, ns = cfg.phantom.shapes_c()
+    p = _params_c(cfg)
+    ptrs = (ctypes.c_void_p * 10)(*[out[k].data_ptr() for k in HIST_FIELDS])
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    rc = lib.pctgen_gpu_histories(ctypes.addressof(p), ctypes.addressof(shapes), ns, ctypes.c_uint64(seed), start, n,
+                                  ptrs, fails.data_ptr(), stream)
+    if rc != 0:
+        raise RuntimeError(f"device history generation failed ({rc})")
+    nf = int(fails.item())
+    if nf:
+        raise RuntimeError(f"{nf} histories could not be generated")
     return out
 
 

@@ -369,6 +369,74 @@ int64_t pctgen_histories(const pctgen_params *p, const pctgen_shape *shapes, int
     return r;
 }
 
+/*
+ * Histories [i0, i0+n) of a second seeded stream: protons whose straight
+ * line misses the body, as a scanner records them passing through air
+ * beside the object (input of the space-carving hull).  Same beam and field
+ * as pctgen_histories, counters (seed, proton, 0x40000000 + attempt, draw),
+ * so the stream is disjoint from the object histories; the line is kept
+ * when it misses the body between the tracker planes.  Exit state = the
+ * straight extrapolation, WEPL = Gaussian noise only.  Returns the number
+ * of failures (NaN rows), normally 0.
+ */
+int64_t pctgen_miss_histories(const pctgen_params *p, const pctgen_shape *shapes_in, int32_t n_shapes,
+                              uint64_t seed, int64_t i0, int64_t n,
+                              float *phi_o, float *t_in_o, float *v_in_o, float *dt_in_o, float *dv_in_o,
+                              float *t_out_o, float *v_out_o, float *dt_out_o, float *dv_out_o,
+                              float *wepl_o, int32_t nthreads) {
+    pctgen_shape *shapes = with_trig(shapes_in, n_shapes);
+    const pctgen_shape *body = &shapes[0];
+    int64_t failures = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : failures)
+#endif
+    for (int64_t ii = 0; ii < n; ++ii) {
+        int64_t i = i0 + ii;
+        int32_t a_idx = (int32_t)(i % p->n_angles);
+        double phi = 2.0 * M_PI * (double)a_idx / (double)p->n_angles;
+        double pc = cos(phi), ps = sin(phi);
+        int done = 0;
+        for (uint32_t attempt = 0; attempt < 1000 && !done; ++attempt) {
+            rng_t rg;
+            rng_init(&rg, seed, (uint64_t)i, 0x40000000u + attempt);
+            double t0 = (2.0 * rng_uniform(&rg) - 1.0) * p->t_half;
+            double v0 = (2.0 * rng_uniform(&rg) - 1.0) * p->v_half;
+            double z0, z1;
+            rng_normal2(&rg, &z0, &z1);
+            double st = z0 * p->slope_sigma, sv = z1 * p->slope_sigma;
+            double P[3], Q[3];
+            double ua = p->u_in, ub = p->u_out;
+            beam_point(pc, ps, ua, t0, v0, P);
+            beam_point(pc, ps, ub, t0 + st * (ub - ua), v0 + sv * (ub - ua), Q);
+            double Dl[3] = {Q[0] - P[0], Q[1] - P[1], Q[2] - P[2]};
+            double s_a, s_b;
+            if (shape_interval(body, P, Dl, &s_a, &s_b) && s_b > 0.0 && s_a < 1.0) continue;
+            double zn0, zn1;
+            rng_normal2(&rg, &zn0, &zn1);
+            phi_o[ii] = (float)phi;
+            t_in_o[ii] = (float)t0;
+            v_in_o[ii] = (float)v0;
+            dt_in_o[ii] = (float)st;
+            dv_in_o[ii] = (float)sv;
+            t_out_o[ii] = (float)(t0 + st * (ub - ua));
+            v_out_o[ii] = (float)(v0 + sv * (ub - ua));
+            dt_out_o[ii] = (float)st;
+            dv_out_o[ii] = (float)sv;
+            wepl_o[ii] = (float)(p->wepl_sigma * zn0);
+            done = 1;
+        }
+        if (!done) {
+            float nanv = NAN;
+            phi_o[ii] = t_in_o[ii] = v_in_o[ii] = dt_in_o[ii] = dv_in_o[ii] = nanv;
+            t_out_o[ii] = v_out_o[ii] = dt_out_o[ii] = dv_out_o[ii] = wepl_o[ii] = nanv;
+            failures += 1;
+        }
+    }
+    free(shapes);
+    return failures;
+}
+
 /* Exact RSP line integral of the analytic phantom along a segment (test hook). */
 double pctgen_segment_wepl(const pctgen_shape *shapes, int32_t n_shapes, const double P[3], const double Q[3]) {
     pctgen_shape *sh = with_trig(shapes, n_shapes);
