@@ -110,6 +110,28 @@ typedef struct {
     double *norm2;
 } pct_rows;
 
+/* Total-variation superiorization (Sec. 4.2, the Table 2 discussion: both
+ * of the paper's pipelines perturb the image towards lower total variation,
+ * DROP before every block, CARP once per iteration; it is what gives DROP its
+ * lower noise).  The paper gives no formula; the library takes the
+ * superiorization step of the pCT literature it builds on, in 3D:
+ *   TV(x) = sum over voxels of sqrt(dx^2 + dy^2 + dz^2 + eps^2) with forward
+ *   differences (0 at a grid's last plane), g = dTV/dx (0 outside the hull
+ *   mask); a step tries x - beta g / ||g||, multiplies beta by `a` after every
+ *   trial, keeps the first trial with TV not above TV(x), and gives up after
+ *   max_trials trials.  n_steps steps per application.
+ * state: device double[8], caller-owned; state[0] = the current beta (set it
+ * to the initial step size before the first call; the library shrinks it),
+ * state[5] counts the steps kept; the other slots are the library's.  TV
+ * sums are FP64 in a fixed order, the image stays float32. */
+typedef struct {
+    int32_t n_steps;         /* 0 = off */
+    int32_t max_trials;      /* 1..16 */
+    double a;                /* 0 < a < 1 */
+    double eps;              /* > 0 */
+    double *state;
+} pct_tvs;
+
 /* Block-iterative solver parameters (Sec. 2.1).  Rows are visited in the
  * order `order` (device int64 [n], a permutation of 0..n-1; NULL = identity)
  * in consecutive blocks of block_size rows (the last block may be short).
@@ -119,7 +141,9 @@ typedef struct {
  * algo 0 (ART): the same with block_size 1, rows strictly one after another
  *   (cached rows only).
  * hull_mask (device uint8 [M], NULL = none): voxels with 0 are held at 0.
- * n_sweeps: passes over all blocks (Sec. 2.1: a fixed iteration count). */
+ * n_sweeps: passes over all blocks (Sec. 2.1: a fixed iteration count).
+ * tvs (host struct, NULL = none): DROP applies its steps to the image that
+ *   enters every block (not with ART). */
 typedef struct {
     int32_t algo;
     int64_t block_size;
@@ -127,6 +151,7 @@ typedef struct {
     int32_t n_sweeps;
     const int64_t *order;
     const uint8_t *hull_mask;
+    const pct_tvs *tvs;
 } pct_sweep_params;
 
 /* A sweep plan: cached rows regrouped, block by block, into lists per spatial
@@ -221,6 +246,46 @@ pct_status pct_reconstruct(const pct_grid *grid, const pct_geom *geom, const pct
                            const pct_sweep_params *params, pct_rows *rows, pct_plan *plan, float *x_inout,
                            double *resid_host, void *workspace, size_t ws_bytes, void *stream);
 
+/* The TV superiorization steps of `tvs` applied once to x (device float32
+ * [M]), voxels with hull_mask 0 (device uint8 [M] or NULL) left as they are.
+ * workspace: pct_workspace_size() of the grid with params holding tvs (or at
+ * least 4 M + 16 ceil(M / 256) + 512 bytes).  Asynchronous. */
+pct_status pct_tvs_apply(const pct_grid *grid, float *x, const uint8_t *hull_mask, const pct_tvs *tvs,
+                         void *workspace, size_t ws_bytes, void *stream);
+
+/* CARP (Sec. 2.2, component-averaged row projections): the positions of
+ * params->order are split into n_strings consecutive strings (string s holds
+ * positions [n s / S, n (s+1) / S)); every iteration (params->n_sweeps of
+ * them) each string starts from the same x and runs one DROP sweep over its
+ * own rows, in blocks of params->block_size from the string's start, into an
+ * image of its own; then every voxel becomes the mean of the string images
+ * over the strings whose rows touch it (others keep their value).  With
+ * params->tvs, its steps are applied once to x at the start of every
+ * iteration.  rows != NULL: cached rows from pct_mlp_trace; rows == NULL:
+ * rows recomputed in every block.  1 <= n_strings <= 4096.
+ * resid_host (host double [n_sweeps] or NULL): ||Ax - b|| after each
+ * iteration.  Workspace: pct_workspace_size() plus 12 M bytes (string image,
+ * sums, string counts, touched flags) -- pct_carp_workspace_size().
+ * Synchronises `stream`. */
+size_t pct_carp_workspace_size(const pct_grid *grid, const pct_geom *geom, const pct_sweep_params *params,
+                               int64_t n_hist, int32_t fused);
+pct_status pct_carp(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist,
+                    const pct_sweep_params *params, int32_t n_strings, const pct_rows *rows, float *x_inout,
+                    double *resid_host, void *workspace, size_t ws_bytes, void *stream);
+
+/* Space-carving hull (a hull from the data, for objects with no known
+ * outline): a history whose WEPL is below wepl_max crossed only air, so each
+ * voxel its straight entry line (entry position and slope, from u_in to
+ * u_out) passes through for more than min_len mm is outside the object.
+ * hull_out (device uint8 [M]) is set to 1 everywhere, then to 0 on every
+ * carved voxel; it can serve as pct_sweep_params.hull_mask.  n_used (host,
+ * or NULL): histories used (synchronises `stream` when given).  Voxels are
+ * cut along the line by plane-crossing parameters (plane - p) / (q - p) in
+ * FP64, a sub-interval's voxel taken at its midpoint. */
+pct_status pct_carve_hull(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist, float wepl_max,
+                          float min_len, uint8_t *hull_out, int64_t *n_used, void *workspace, size_t ws_bytes,
+                          void *stream);
+
 /* ||Ax - b||_2 over non-empty rows (FP64) into *out (device double).
  * rows == NULL recomputes the rows.  Asynchronous. */
 pct_status pct_residual(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist,
@@ -254,7 +319,10 @@ enum {
     PCT_K_PLAN_SCATTER = 9,  /* plan: per-tile accumulation + block update */
     PCT_K_PLAN_BUILD = 10,   /* plan construction */
     PCT_K_PATH_SETUP = 11,   /* per-proton path set-up (hull, end states), one thread per proton */
-    PCT_K_COUNT = 12
+    PCT_K_TVS = 12,          /* total-variation superiorization steps */
+    PCT_K_CARP = 13,         /* CARP string copies, sums and averages */
+    PCT_K_CARVE = 14,        /* space-carving hull */
+    PCT_K_COUNT = 15
 };
 pct_status pct_profile_enable(int32_t on);
 pct_status pct_profile_read(int64_t *launches, double *ms);

@@ -125,13 +125,19 @@ def _load():
 
 
 def _threads(t):
+    """Threads for the OpenMP loops: the caller's count, else every core this
+    process may run on, limited by OMP_NUM_THREADS when that is set (a host
+    that shares its cores among several jobs sets it to this job's share)."""
     if t:
         return t
-    n = os.cpu_count() or 1
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
     env = os.environ.get("OMP_NUM_THREADS")
-    if env and env.isdigit():
+    if env and env.isdigit() and int(env) > 0:
         n = min(n, int(env))
-    return max(1, min(n, 16))
+    return max(1, n)
 
 
 def make_grid(nx, ny, nz, dx, dy, dz, ox, oy, oz) -> OrcGrid:

@@ -64,19 +64,26 @@ class pct_plan(ctypes.Structure):
                 ("ready", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class pct_tvs(ctypes.Structure):
+    _fields_ = [("n_steps", ctypes.c_int32), ("max_trials", ctypes.c_int32), ("a", ctypes.c_double),
+                ("eps", ctypes.c_double), ("state", _fp)]
+
+
 class pct_sweep_params(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("block_size", ctypes.c_int64), ("lambda_", ctypes.c_float),
-                ("n_sweeps", ctypes.c_int32), ("order", _fp), ("hull_mask", _fp)]
+                ("n_sweeps", ctypes.c_int32), ("order", _fp), ("hull_mask", _fp),
+                ("tvs", ctypes.POINTER(pct_tvs))]
 
 
 EXPORTS = ("pct_workspace_size", "pct_mlp_trace", "pct_project_sweep", "pct_plan_build", "pct_plan_sweep",
            "pct_plan_residual", "pct_reconstruct", "pct_residual", "pct_roi_stats", "pct_profile_enable",
+           "pct_tvs_apply", "pct_carp", "pct_carp_workspace_size", "pct_carve_hull",
            "pct_profile_read", "pct_last_error",
            "pct_cnn_conv3d", "pct_cnn_conv3d_bwd_data", "pct_cnn_wgrad_scratch", "pct_cnn_conv3d_bwd_weight",
            "pct_cnn_relu", "pct_cnn_relu_bwd", "pct_cnn_pool", "pct_cnn_pool_bwd", "pct_cnn_upsample",
            "pct_cnn_upsample_bwd", "pct_cnn_add", "pct_cnn_axpy", "pct_cnn_mask", "pct_cnn_mse_scratch", "pct_cnn_mse", "pct_cnn_adam")
 KERNEL_CLASSES = ("trace_path", "trace_compact", "project", "apply", "residual", "art", "other", "plan_dot",
-                  "plan_rows", "plan_scatter", "plan_build", "path_setup")
+                  "plan_rows", "plan_scatter", "plan_build", "path_setup", "tvs", "carp", "carve")
 
 _lib = None
 
@@ -121,6 +128,17 @@ def load(path: str | None = None):
     lib.pct_residual.restype = ctypes.c_int
     lib.pct_residual.argtypes = [P(pct_grid), P(pct_geom), P(pct_histories), P(pct_rows), _fp, _fp, _fp,
                                  ctypes.c_size_t, _fp]
+    lib.pct_tvs_apply.restype = ctypes.c_int
+    lib.pct_tvs_apply.argtypes = [P(pct_grid), _fp, _fp, P(pct_tvs), _fp, ctypes.c_size_t, _fp]
+    lib.pct_carp_workspace_size.restype = ctypes.c_size_t
+    lib.pct_carp_workspace_size.argtypes = [P(pct_grid), P(pct_geom), P(pct_sweep_params), ctypes.c_int64,
+                                            ctypes.c_int32]
+    lib.pct_carp.restype = ctypes.c_int
+    lib.pct_carp.argtypes = [P(pct_grid), P(pct_geom), P(pct_histories), P(pct_sweep_params), ctypes.c_int32,
+                             P(pct_rows), _fp, P(ctypes.c_double), _fp, ctypes.c_size_t, _fp]
+    lib.pct_carve_hull.restype = ctypes.c_int
+    lib.pct_carve_hull.argtypes = [P(pct_grid), P(pct_geom), P(pct_histories), ctypes.c_float, ctypes.c_float, _fp,
+                                   P(ctypes.c_int64), _fp, ctypes.c_size_t, _fp]
     lib.pct_roi_stats.restype = ctypes.c_int
     lib.pct_roi_stats.argtypes = [_fp, _fp, ctypes.c_int64, ctypes.c_int32, _fp, _fp, _fp]
     lib.pct_profile_enable.restype = ctypes.c_int

@@ -13,7 +13,7 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import check, pct_geom, pct_grid, pct_histories, pct_plan, pct_rows, pct_sweep_params
+from ._lib import check, pct_geom, pct_grid, pct_histories, pct_plan, pct_rows, pct_sweep_params, pct_tvs
 
 FIELDS = ("phi", "t_in", "v_in", "dt_in", "dv_in", "t_out", "v_out", "dt_out", "dv_out", "wepl")
 
@@ -106,11 +106,32 @@ class Rows:
         return r
 
 
+class Tvs:
+    """pct_tvs (total-variation superiorization, Sec. 4.2) with its device
+    state (state[0] = the current step size, shrunk by the library)."""
+
+    def __init__(self, beta0: float = 2.0, n_steps: int = 1, max_trials: int = 3, a: float = 0.995,
+                 eps: float = 1e-3, device=None):
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.state = torch.zeros(8, dtype=torch.float64, device=dev)
+        self.state[0] = float(beta0)
+        self.struct = pct_tvs(int(n_steps), int(max_trials), float(a), float(eps), self.state.data_ptr())
+
+    @property
+    def beta(self) -> float:
+        return float(self.state[0].item())
+
+    @property
+    def accepted(self) -> int:
+        return int(self.state[5].item())
+
+
 class SweepParams:
     """pct_sweep_params plus references to the device tensors it points to
     (so they stay allocated while the struct is in use)."""
 
-    def __init__(self, algo="drop", block_size=200_000, lam=0.5, n_sweeps=1, order=None, hull_mask=None):
+    def __init__(self, algo="drop", block_size=200_000, lam=0.5, n_sweeps=1, order=None, hull_mask=None,
+                 tvs: Tvs | None = None):
         for name, t, dt in (("order", order, torch.int64), ("hull_mask", hull_mask, torch.uint8)):
             if t is not None and not (t.is_cuda and t.dtype == dt and t.is_contiguous()):
                 raise ValueError(f"{name} must be a contiguous {dt} device tensor")
@@ -123,6 +144,9 @@ class SweepParams:
         s.n_sweeps = int(n_sweeps)
         s.order = _ptr(order)
         s.hull_mask = _ptr(hull_mask)
+        self.tvs = tvs
+        if tvs is not None:
+            s.tvs = ctypes.pointer(tvs.struct)
         self.struct = s
 
     @property
@@ -130,8 +154,9 @@ class SweepParams:
         return int(self.struct.n_sweeps)
 
 
-def sweep_params(algo="drop", block_size=200_000, lam=0.5, n_sweeps=1, order=None, hull_mask=None) -> SweepParams:
-    return SweepParams(algo, block_size, lam, n_sweeps, order, hull_mask)
+def sweep_params(algo="drop", block_size=200_000, lam=0.5, n_sweeps=1, order=None, hull_mask=None,
+                 tvs: Tvs | None = None) -> SweepParams:
+    return SweepParams(algo, block_size, lam, n_sweeps, order, hull_mask, tvs)
 
 
 _ws_cache: dict = {}
@@ -288,6 +313,48 @@ def residual(grid, geom, hist: Histories, rows: Rows | None, x: torch.Tensor, st
                            ctypes.byref(rs) if rs is not None else None, x.data_ptr(), out.data_ptr(),
                            ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
     return float(out.item())
+
+
+def tvs_apply(grid, x: torch.Tensor, tvs: Tvs, hull_mask: torch.Tensor | None = None, stream=None):
+    """pct_tvs_apply: the TV superiorization steps on x, in place."""
+    lib = _lib.load()
+    ws = workspace(grid, 0, x.device, SweepParams(tvs=tvs))
+    check(lib.pct_tvs_apply(ctypes.byref(grid), x.data_ptr(), _ptr(hull_mask), ctypes.byref(tvs.struct),
+                            ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+
+
+def carp(grid, geom, hist: Histories, params: SweepParams, n_strings: int, x: torch.Tensor, rows: Rows | None = None,
+         want_residuals: bool = True, stream=None):
+    """pct_carp (Sec. 2.2): params.n_sweeps iterations of n_strings strings;
+    x updated in place; returns the residual per iteration."""
+    lib = _lib.load()
+    _check_lengths(grid, hist, x, params)
+    fused = rows is None
+    nbytes = lib.pct_carp_workspace_size(ctypes.byref(grid), ctypes.byref(geom) if not fused else None,
+                                         ctypes.byref(params.struct), hist.n, 1 if fused else 0)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    hs = hist.struct()
+    rs = rows.struct() if rows is not None else None
+    res = (ctypes.c_double * max(params.n_sweeps, 1))()
+    check(lib.pct_carp(ctypes.byref(grid), ctypes.byref(geom), ctypes.byref(hs), ctypes.byref(params.struct),
+                       int(n_strings), ctypes.byref(rs) if rs is not None else None, x.data_ptr(),
+                       res if want_residuals else None, ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+    return [res[k] for k in range(params.n_sweeps)] if want_residuals else []
+
+
+def carve_hull(grid, geom, hist: Histories, wepl_max: float = 1.5, min_len: float = 1e-6, stream=None):
+    """pct_carve_hull: (hull mask uint8 [M] on the device, histories used)."""
+    lib = _lib.load()
+    dev = hist.t["phi"].device
+    M = grid.nx * grid.ny * grid.nz
+    out = torch.empty(M, dtype=torch.uint8, device=dev)
+    ws = workspace(grid, 0, dev)
+    used = ctypes.c_int64(0)
+    hs = hist.struct()
+    check(lib.pct_carve_hull(ctypes.byref(grid), ctypes.byref(geom), ctypes.byref(hs), float(wepl_max),
+                             float(min_len), out.data_ptr(), ctypes.byref(used), ws.data_ptr(), ws.numel(),
+                             _stream_ptr(stream)))
+    return out, int(used.value)
 
 
 def roi_stats(x: torch.Tensor, labels: torch.Tensor, n_labels: int, stream=None):

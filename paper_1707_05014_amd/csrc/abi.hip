@@ -185,6 +185,8 @@ pct_status check_rows(const pct_rows *r, int64_t n, bool need_data) {
   return PCT_OK;
 }
 
+pct_status check_tvs_params(const pct_sweep_params *p);
+
 pct_status check_params(const pct_sweep_params *p, bool cached) {
   if (!p) return fail(PCT_EINVAL, "params are NULL");
   if (p->algo != 0 && p->algo != 1) return fail(PCT_EINVAL, "algo must be 0 (ART) or 1 (DROP)");
@@ -192,7 +194,7 @@ pct_status check_params(const pct_sweep_params *p, bool cached) {
   if (p->algo == 1 && p->block_size < 1) return fail(PCT_EINVAL, "block_size must be >= 1");
   if (!(p->lambda > 0.f && p->lambda < 2.f)) return fail(PCT_EINVAL, "lambda must be in (0, 2)");
   if (p->n_sweeps < 0) return fail(PCT_EINVAL, "n_sweeps must be >= 0");
-  return PCT_OK;
+  return check_tvs_params(p);
 }
 
 struct Ctx {
@@ -204,10 +206,36 @@ struct Ctx {
   void *ws = nullptr;
   size_t ws_bytes = 0;
   bool recs_ready = false;  // W.recs holds every history's path record
+  int extra = 0;            // optional workspace regions (kWsTvs, kWsCarp)
 };
 
-pct_status check_ws(void *ws, size_t ws_bytes, int64_t M, int64_t n, int64_t plan_bt = 0) {
-  const size_t need = pct::workspace_bytes(M, n, plan_bt);
+bool tvs_on(const pct_sweep_params *p) { return p && p->tvs && p->tvs->n_steps > 0; }
+
+pct_status check_tvs(const pct_tvs *t);
+pct_status check_tvs_params(const pct_sweep_params *p) {
+  if (!p->tvs) return PCT_OK;
+  if (p->tvs->n_steps > 0 && p->algo == 0) return fail(PCT_EINVAL, "TV superiorization runs with DROP (algo 1)");
+  return check_tvs(p->tvs);
+}
+
+pct_status check_tvs(const pct_tvs *t) {
+  if (!t || t->n_steps == 0) return PCT_OK;
+  if (t->n_steps < 0) return fail(PCT_EINVAL, "tvs.n_steps must be >= 0");
+  if (t->max_trials < 1 || t->max_trials > 16) return fail(PCT_EINVAL, "tvs.max_trials must be 1..16");
+  if (!(t->a > 0.0 && t->a < 1.0)) return fail(PCT_EINVAL, "tvs.a must be in (0, 1)");
+  if (!(t->eps > 0.0) || !std::isfinite(t->eps)) return fail(PCT_EINVAL, "tvs.eps must be positive");
+  if (!t->state) return fail(PCT_EINVAL, "tvs.state is NULL");
+  return PCT_OK;
+}
+
+// the TVS steps on x (the image entering a block, or a CARP iteration)
+hipError_t run_tvs(const Ctx &c, int32_t nx, int32_t ny, int32_t nz, float *x, const uint8_t *mask,
+                   const pct_tvs *t) {
+  return pct::launch_tvs(nx, ny, nz, x, mask, t->n_steps, t->max_trials, t->a, t->eps, t->state, c.W.tvs, c.s);
+}
+
+pct_status check_ws(void *ws, size_t ws_bytes, int64_t M, int64_t n, int64_t plan_bt = 0, int extra = 0) {
+  const size_t need = pct::workspace_bytes(M, n, plan_bt, 0, 0, false, extra);
   if (!ws || ws_bytes < need)
     return fail(PCT_ENOMEM, "workspace of %zu bytes given, %zu needed", ws ? ws_bytes : (size_t)0, need);
   return PCT_OK;
@@ -236,13 +264,14 @@ pct_status do_trace(Ctx &c, const pct_grid *g, pct_rows *rows) {
   const bool fill = rows->idx != nullptr;
   int64_t st_rows = std::min<int64_t>(c.n, pct::kStageRows);
   if (fill) {
-    while (st_rows > 1 && pct::workspace_bytes(c.M, c.n, 0, st_rows * c.P.emax) > c.ws_bytes) st_rows /= 2;
-    const size_t need = pct::workspace_bytes(c.M, c.n, 0, std::max<int64_t>(st_rows, 1) * c.P.emax);
+    while (st_rows > 1 && pct::workspace_bytes(c.M, c.n, 0, st_rows * c.P.emax, 0, false, c.extra) > c.ws_bytes)
+      st_rows /= 2;
+    const size_t need = pct::workspace_bytes(c.M, c.n, 0, std::max<int64_t>(st_rows, 1) * c.P.emax, 0, false, c.extra);
     if (need > c.ws_bytes)
       return fail(PCT_ENOMEM, "workspace of %zu bytes given, %zu needed to stage rows", c.ws_bytes, need);
   }
   st_rows = std::max<int64_t>(st_rows, 1);
-  c.W = pct::carve_workspace(c.ws, c.M, c.n, 0, fill ? st_rows * c.P.emax : 0);
+  c.W = pct::carve_workspace(c.ws, c.M, c.n, 0, fill ? st_rows * c.P.emax : 0, 0, false, c.extra);
   const float scale = 1.0f / len_unit(g);
   HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
   if (c.n == 0) HIPCHECK(pct::launch_scan_rows(rows->row_ptr, 0, 0, c.W.scan, c.s));
@@ -284,16 +313,17 @@ int64_t fused_count_elems(int64_t M, int64_t n, const pct_sweep_params *p) {
 // Fused calls: when the workspace holds one path record per history, carve
 // it so (keeping the per-block counts when blk > 0 and they fit too).
 bool carve_fused(Ctx &c, int64_t blk) {
-  if (blk > 0 && pct::workspace_bytes(c.M, c.n, 0, 0, blk, true) <= c.ws_bytes) {
-    c.W = pct::carve_workspace(c.ws, c.M, c.n, 0, 0, blk, true);
+  const int x = c.extra;
+  if (blk > 0 && pct::workspace_bytes(c.M, c.n, 0, 0, blk, true, x) <= c.ws_bytes) {
+    c.W = pct::carve_workspace(c.ws, c.M, c.n, 0, 0, blk, true, x);
     return true;
   }
-  if (pct::workspace_bytes(c.M, c.n, 0, 0, 0, true) <= c.ws_bytes) {
-    c.W = pct::carve_workspace(c.ws, c.M, c.n, 0, 0, 0, true);
+  if (pct::workspace_bytes(c.M, c.n, 0, 0, 0, true, x) <= c.ws_bytes) {
+    c.W = pct::carve_workspace(c.ws, c.M, c.n, 0, 0, 0, true, x);
     return true;
   }
-  if (blk > 0 && pct::workspace_bytes(c.M, c.n, 0, 0, blk) <= c.ws_bytes)
-    c.W = pct::carve_workspace(c.ws, c.M, c.n, 0, 0, blk);
+  if (blk > 0 && pct::workspace_bytes(c.M, c.n, 0, 0, blk, false, x) <= c.ws_bytes)
+    c.W = pct::carve_workspace(c.ws, c.M, c.n, 0, 0, blk, false, x);
   return false;
 }
 
@@ -306,9 +336,12 @@ pct_status prepare_records(Ctx &c) {
 }
 
 // count_mode 0: s_j formed with atomics in every block; 1: formed and stored
-// per block; 2: read from the stored counts
+// per block; 2: read from the stored counts.  The sweep covers the positions
+// [p0, p1) of the order (p1 < 0: all), in blocks from p0; with p->tvs the
+// TVS steps run on x before every block; touched (CARP) marks the voxels
+// the rows touch.
 pct_status do_sweep(Ctx &c, const pct_grid *g, const pct_rows *rows, float *x, const pct_sweep_params *p,
-                    int count_mode = 0) {
+                    int count_mode = 0, int64_t p0 = 0, int64_t p1 = -1, uint8_t *touched = nullptr) {
   HIPCHECK(pct::launch_mask(x, p->hull_mask, c.M, c.s));
   const float unit = len_unit(g);
   if (p->algo == 0) {
@@ -316,11 +349,15 @@ pct_status do_sweep(Ctx &c, const pct_grid *g, const pct_rows *rows, float *x, c
                                     c.H.wepl, p->order, c.n, c.M, x, p->hull_mask, p->lambda, c.W.status, c.s));
     return PCT_OK;
   }
+  const bool tv = tvs_on(p);
+  if (tv && !c.W.tvs) return fail(PCT_ENOMEM, "workspace carved without the TV superiorization scratch");
+  if (p1 < 0) p1 = c.n;
   HIPCHECK(pct::launch_fill_f32(c.W.num, c.M, 0.f, c.s));
   HIPCHECK(pct::launch_fill_u32(c.W.cnt, c.M, 0u, c.s));
-  if (rows || !c.W.blk_cnt) count_mode = 0;
-  for (int64_t first = 0, blk = 0; first < c.n; first += p->block_size, ++blk) {
-    const int64_t count = std::min<int64_t>(p->block_size, c.n - first);
+  if (rows || !c.W.blk_cnt || touched) count_mode = 0;
+  for (int64_t first = p0, blk = 0; first < p1; first += p->block_size, ++blk) {
+    const int64_t count = std::min<int64_t>(p->block_size, p1 - first);
+    if (tv) PROF(PCT_K_TVS, run_tvs(c, g->nx, g->ny, g->nz, x, p->hull_mask, p->tvs));
     if (rows)
       PROF(PCT_K_PROJECT, pct::launch_project_cached(rows->row_ptr, rows->idx, rows->len, rows->len_dtype, unit,
                                                      rows->norm2, c.H.wepl, p->order, first, count, c.n, c.M, x,
@@ -329,15 +366,15 @@ pct_status do_sweep(Ctx &c, const pct_grid *g, const pct_rows *rows, float *x, c
       PROF(PCT_K_PROJECT, pct::launch_project_fused(c.P, c.W.recs, p->order, first, c.n, true, count, x, c.W.num,
                                                     count_mode == 2 ? nullptr : c.W.cnt, c.W.status, c.s));
     else
-      for (int64_t s0 = 0; s0 < count; s0 += pct::kStageRows) {
-        const int64_t cs = std::min<int64_t>(pct::kStageRows, count - s0);
+      for (int64_t s0 = 0; s0 < count; s0 += c.W.rec_rows) {
+        const int64_t cs = std::min<int64_t>(c.W.rec_rows, count - s0);
         PROF(PCT_K_PATH_SETUP, pct::launch_path_setup(c.P, c.H, p->order, first + s0, cs, c.n, c.W.recs,
                                                       c.W.status, false, c.s));
         PROF(PCT_K_PROJECT, pct::launch_project_fused(c.P, c.W.recs, nullptr, 0, c.n, false, cs, x, c.W.num,
                                                       count_mode == 2 ? nullptr : c.W.cnt, c.W.status, c.s));
       }
     PROF(PCT_K_APPLY, pct::launch_apply_counts(x, c.W.num, c.W.cnt, count_mode ? c.W.blk_cnt + blk * c.M : nullptr,
-                                               count_mode, p->hull_mask, c.M, p->lambda, c.W.status, c.s));
+                                               count_mode, p->hull_mask, c.M, p->lambda, c.W.status, c.s, touched));
   }
   return PCT_OK;
 }
@@ -350,8 +387,8 @@ pct_status do_residual(Ctx &c, const pct_grid *g, const pct_rows *rows, const fl
     PROF(PCT_K_RESIDUAL, pct::launch_residual_fused(c.P, c.W.recs, c.n, x, c.W.partials, c.W.status, false, c.s));
     HIPCHECK(pct::launch_residual_final(c.W.partials, pct::kResidFusedGrid, out, c.s));
   } else {
-    for (int64_t i0 = 0; i0 < c.n; i0 += pct::kStageRows) {
-      const int64_t cs = std::min<int64_t>(pct::kStageRows, c.n - i0);
+    for (int64_t i0 = 0; i0 < c.n; i0 += c.W.rec_rows) {
+      const int64_t cs = std::min<int64_t>(c.W.rec_rows, c.n - i0);
       PROF(PCT_K_PATH_SETUP, pct::launch_path_setup(c.P, c.H, nullptr, i0, cs, c.n, c.W.recs, c.W.status, false,
                                                     c.s));
       PROF(PCT_K_RESIDUAL, pct::launch_residual_fused(c.P, c.W.recs, cs, x, c.W.partials, c.W.status, i0 > 0, c.s));
@@ -363,16 +400,17 @@ pct_status do_residual(Ctx &c, const pct_grid *g, const pct_rows *rows, const fl
 }
 
 pct_status setup(Ctx &c, const pct_grid *grid, const pct_geom *geom, const pct_histories *hist, void *ws,
-                  size_t ws_bytes, void *stream) {
+                  size_t ws_bytes, void *stream, int extra = 0) {
   pct_status r;
   if ((r = check_grid(grid)) != PCT_OK) return r;
   if ((r = check_hist(hist)) != PCT_OK) return r;
   if ((r = make_params(grid, geom, c.P)) != PCT_OK) return r;
   c.M = grid_voxels(grid);
   c.n = hist->n;
-  if ((r = check_ws(ws, ws_bytes, c.M, c.n)) != PCT_OK) return r;
+  c.extra = extra;
+  if ((r = check_ws(ws, ws_bytes, c.M, c.n, 0, extra)) != PCT_OK) return r;
   c.H = hist_ptrs(hist);
-  c.W = pct::carve_workspace(ws, c.M, c.n, 0);
+  c.W = pct::carve_workspace(ws, c.M, c.n, 0, 0, 0, false, extra);
   c.ws = ws;
   c.ws_bytes = ws_bytes;
   c.s = reinterpret_cast<hipStream_t>(stream);
@@ -491,7 +529,7 @@ pct_status check_plan_params(const pct_sweep_params *p, int64_t n) {
     return fail(PCT_EINVAL, "plans need 1 <= block_size <= %lld", (long long)pct::kMaxPlanBlock);
   if (!(p->lambda > 0.f && p->lambda < 2.f)) return fail(PCT_EINVAL, "lambda must be in (0, 2)");
   (void)n;
-  return PCT_OK;
+  return check_tvs_params(p);
 }
 
 // sizing pass + (when plan->mem is set) construction
@@ -609,7 +647,10 @@ pct_status check_plan(const pct_plan *plan, const pct_grid *g) {
 pct_status do_plan_sweep(Ctx &c, const pct_plan *plan, const pct::PlanView &V, float *x,
                          const pct_sweep_params *p) {
   HIPCHECK(pct::launch_mask(x, p->hull_mask, c.M, c.s));
+  const bool tv = tvs_on(p);
+  if (tv && !c.W.tvs) return fail(PCT_ENOMEM, "workspace carved without the TV superiorization scratch");
   for (int64_t b = 0; b < plan->n_blocks; ++b) {
+    if (tv) PROF(PCT_K_TVS, run_tvs(c, plan->nx, plan->ny, plan->nz, x, p->hull_mask, p->tvs));
     PROF(PCT_K_PLAN_DOT, pct::launch_plan_dot(V, b, x, c.s));
     PROF(PCT_K_PLAN_ROWS, pct::launch_plan_rows(V, b, c.s));
     PROF(PCT_K_PLAN_SCATTER, pct::launch_plan_scatter(V, b, x, p->hull_mask, p->lambda, c.s));
@@ -639,12 +680,20 @@ static int64_t rec_rows_for(int64_t n_hist, bool recs_all) {
   return recs_all ? n : std::min<int64_t>(n, kStageRows);
 }
 
+static size_t extra_bytes(int64_t M, int extra) {
+  size_t b = 0;
+  if (extra & kWsTvs) b += align_up(tvs_scratch_bytes(M));
+  if (extra & kWsCarp) b += 2 * align_up((size_t)M * 4) + align_up((size_t)M * 2) + align_up((size_t)M);
+  return b;
+}
+
 size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots, int64_t blk_cnt_elems,
-                       bool recs_all) {
+                       bool recs_all, int extra) {
   size_t b = align_up(4 * sizeof(uint32_t));
   b += align_up((size_t)M * sizeof(float));
   b += align_up((size_t)M * sizeof(uint32_t));
   b += align_up((size_t)kMaxPartials * sizeof(double));
+  b += extra_bytes(M, extra);
   b += align_up((size_t)((n_hist + kScanChunk - 1) / kScanChunk + 2) * sizeof(int64_t));
   b += align_up((size_t)rec_rows_for(n_hist, recs_all) * kPathRecBytes);
   const size_t plan_b = (size_t)(plan_bt > 0 ? plan_bt : 0) * sizeof(int64_t);
@@ -655,7 +704,7 @@ size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage
 }
 
 Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots,
-                          int64_t blk_cnt_elems, bool recs_all) {
+                          int64_t blk_cnt_elems, bool recs_all, int extra) {
   char *p = static_cast<char *>(base);
   Workspace w;
   w.status = reinterpret_cast<uint32_t *>(p);
@@ -666,6 +715,24 @@ Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt
   p += align_up((size_t)M * sizeof(uint32_t));
   w.partials = reinterpret_cast<double *>(p);
   p += align_up((size_t)kMaxPartials * sizeof(double));
+  w.tvs = nullptr;
+  w.carp_xs = w.carp_acc = nullptr;
+  w.carp_tc = nullptr;
+  w.carp_touched = nullptr;
+  if (extra & kWsTvs) {
+    w.tvs = p;
+    p += align_up(tvs_scratch_bytes(M));
+  }
+  if (extra & kWsCarp) {
+    w.carp_xs = reinterpret_cast<float *>(p);
+    p += align_up((size_t)M * 4);
+    w.carp_acc = reinterpret_cast<float *>(p);
+    p += align_up((size_t)M * 4);
+    w.carp_tc = reinterpret_cast<uint16_t *>(p);
+    p += align_up((size_t)M * 2);
+    w.carp_touched = reinterpret_cast<uint8_t *>(p);
+    p += align_up((size_t)M);
+  }
   w.scan = reinterpret_cast<int64_t *>(p);
   p += align_up((size_t)((n_hist + kScanChunk - 1) / kScanChunk + 2) * sizeof(int64_t));
   w.recs = p;
@@ -696,7 +763,19 @@ size_t pct_workspace_size(const pct_grid *grid, const pct_geom *geom, const pct_
   if (geom && !fused && make_params(grid, geom, P) == PCT_OK)
     stage = std::min<int64_t>(n_hist, pct::kStageRows) * P.emax;
   const int64_t blk = fused ? fused_count_elems(grid_voxels(grid), n_hist, params) : 0;
-  return pct::workspace_bytes(grid_voxels(grid), n_hist, plan_bt, stage, blk, fused != 0);
+  return pct::workspace_bytes(grid_voxels(grid), n_hist, plan_bt, stage, blk, fused != 0,
+                              tvs_on(params) ? pct::kWsTvs : 0);
+}
+
+size_t pct_carp_workspace_size(const pct_grid *grid, const pct_geom *geom, const pct_sweep_params *params,
+                               int64_t n_hist, int32_t fused) {
+  if (!grid || grid->nx <= 0 || grid->ny <= 0 || grid->nz <= 0 || n_hist < 0) return 0;
+  int64_t stage = 0;
+  pct::PathParams P;
+  if (geom && !fused && make_params(grid, geom, P) == PCT_OK)
+    stage = std::min<int64_t>(n_hist, pct::kStageRows) * P.emax;
+  return pct::workspace_bytes(grid_voxels(grid), n_hist, 0, stage, 0, fused != 0,
+                              pct::kWsCarp | (tvs_on(params) ? pct::kWsTvs : 0));
 }
 
 pct_status pct_mlp_trace(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist, pct_rows *rows,
@@ -715,10 +794,11 @@ pct_status pct_project_sweep(const pct_grid *grid, const pct_geom *geom, const p
                              void *workspace, size_t ws_bytes, void *stream) {
   g_err.clear();
   Ctx c;
-  pct_status r = setup(c, grid, geom, hist, workspace, ws_bytes, stream);
-  if (r != PCT_OK) return r;
-  if (rows && (r = check_rows(rows, c.n, true)) != PCT_OK) return r;
+  pct_status r;
   if ((r = check_params(params, rows != nullptr)) != PCT_OK) return r;
+  if ((r = setup(c, grid, geom, hist, workspace, ws_bytes, stream, tvs_on(params) ? pct::kWsTvs : 0)) != PCT_OK)
+    return r;
+  if (rows && (r = check_rows(rows, c.n, true)) != PCT_OK) return r;
   if (!x) return fail(PCT_EINVAL, "x is NULL");
   HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
   if (!rows && params->algo == 1 && carve_fused(c, 0)) {
@@ -764,8 +844,9 @@ pct_status pct_plan_sweep(const pct_grid *grid, const pct_plan *plan, float *x, 
   Ctx c;
   c.M = grid_voxels(grid);
   c.n = plan->n;
-  if ((r = check_ws(workspace, ws_bytes, c.M, c.n)) != PCT_OK) return r;
-  c.W = pct::carve_workspace(workspace, c.M, c.n, 0);
+  c.extra = tvs_on(params) ? pct::kWsTvs : 0;
+  if ((r = check_ws(workspace, ws_bytes, c.M, c.n, 0, c.extra)) != PCT_OK) return r;
+  c.W = pct::carve_workspace(workspace, c.M, c.n, 0, 0, 0, false, c.extra);
   c.s = reinterpret_cast<hipStream_t>(stream);
   const pct::PlanView V = plan_view(plan, len_unit(grid));
   HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
@@ -799,10 +880,11 @@ pct_status pct_reconstruct(const pct_grid *grid, const pct_geom *geom, const pct
                            double *resid_host, void *workspace, size_t ws_bytes, void *stream) {
   g_err.clear();
   Ctx c;
-  pct_status r = setup(c, grid, geom, hist, workspace, ws_bytes, stream);
-  if (r != PCT_OK) return r;
-  if (rows && (r = check_rows(rows, c.n, true)) != PCT_OK) return r;
+  pct_status r;
   if ((r = check_params(params, rows != nullptr)) != PCT_OK) return r;
+  if ((r = setup(c, grid, geom, hist, workspace, ws_bytes, stream, tvs_on(params) ? pct::kWsTvs : 0)) != PCT_OK)
+    return r;
+  if (rows && (r = check_rows(rows, c.n, true)) != PCT_OK) return r;
   if (plan && !rows) return fail(PCT_EINVAL, "a plan needs cached rows");
   if (plan && (r = check_plan_params(params, c.n)) != PCT_OK) return r;
   if (plan && !plan->mem) return fail(PCT_EINVAL, "plan memory is NULL (size it with pct_plan_build first)");
@@ -854,6 +936,102 @@ pct_status pct_reconstruct(const pct_grid *grid, const pct_geom *geom, const pct
   r = status_to_code(st);
   if (r != PCT_OK) return r;
   return trace_st;
+}
+
+pct_status pct_tvs_apply(const pct_grid *grid, float *x, const uint8_t *hull_mask, const pct_tvs *tvs,
+                         void *workspace, size_t ws_bytes, void *stream) {
+  g_err.clear();
+  pct_status r;
+  if ((r = check_grid(grid)) != PCT_OK) return r;
+  if (!x || !tvs) return fail(PCT_EINVAL, "x / tvs is NULL");
+  if ((r = check_tvs(tvs)) != PCT_OK) return r;
+  if (tvs->n_steps == 0) return PCT_OK;
+  const int64_t M = grid_voxels(grid);
+  const size_t need = pct::tvs_scratch_bytes(M);
+  if (!workspace || ws_bytes < need)
+    return fail(PCT_ENOMEM, "workspace of %zu bytes given, %zu needed", workspace ? ws_bytes : (size_t)0, need);
+  Ctx c;
+  c.s = reinterpret_cast<hipStream_t>(stream);
+  c.W.tvs = workspace;
+  PROF(PCT_K_TVS, run_tvs(c, grid->nx, grid->ny, grid->nz, x, hull_mask, tvs));
+  return PCT_OK;
+}
+
+pct_status pct_carp(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist,
+                    const pct_sweep_params *params, int32_t n_strings, const pct_rows *rows, float *x_inout,
+                    double *resid_host, void *workspace, size_t ws_bytes, void *stream) {
+  g_err.clear();
+  Ctx c;
+  pct_status r;
+  if ((r = check_params(params, rows != nullptr)) != PCT_OK) return r;
+  if (params->algo != 1) return fail(PCT_EINVAL, "CARP strings run DROP sweeps (algo 1)");
+  if (n_strings < 1 || n_strings > 4096) return fail(PCT_EINVAL, "n_strings must be 1..4096");
+  const int extra = pct::kWsCarp | (tvs_on(params) ? pct::kWsTvs : 0);
+  if ((r = setup(c, grid, geom, hist, workspace, ws_bytes, stream, extra)) != PCT_OK) return r;
+  if (rows && (r = check_rows(rows, c.n, true)) != PCT_OK) return r;
+  if (!x_inout) return fail(PCT_EINVAL, "x is NULL");
+  HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
+  if (!rows && carve_fused(c, 0)) {
+    HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
+    if ((r = prepare_records(c)) != PCT_OK) return r;
+  }
+  // the strings' sweeps: DROP without TVS (CARP applies it once per iteration)
+  pct_sweep_params ps = *params;
+  ps.tvs = nullptr;
+  PROF(PCT_K_CARP, pct::launch_fill_f32(c.W.carp_acc, c.M, 0.f, c.s));
+  HIPCHECK(pct::launch_fill_u8(reinterpret_cast<uint8_t *>(c.W.carp_tc), 2 * c.M, 0, c.s));
+  HIPCHECK(pct::launch_fill_u8(c.W.carp_touched, c.M, 0, c.s));
+  HIPCHECK(pct::launch_mask(x_inout, params->hull_mask, c.M, c.s));
+  double *dres = c.W.partials + (pct::kMaxPartials - 1);
+  for (int32_t it = 0; it < params->n_sweeps; ++it) {
+    if (tvs_on(params)) PROF(PCT_K_TVS, run_tvs(c, grid->nx, grid->ny, grid->nz, x_inout, params->hull_mask,
+                                                params->tvs));
+    for (int32_t s = 0; s < n_strings; ++s) {
+      const int64_t p0 = c.n * s / n_strings, p1 = c.n * (s + 1) / n_strings;
+      PROF(PCT_K_CARP, pct::launch_copy_f32(x_inout, c.W.carp_xs, c.M, c.s));
+      if ((r = do_sweep(c, grid, rows, c.W.carp_xs, &ps, 0, p0, p1, c.W.carp_touched)) != PCT_OK) return r;
+      PROF(PCT_K_CARP, pct::launch_carp_accumulate(c.W.carp_xs, c.W.carp_touched, c.W.carp_acc, c.W.carp_tc, c.M,
+                                                   c.s));
+    }
+    PROF(PCT_K_CARP, pct::launch_carp_average(x_inout, c.W.carp_acc, c.W.carp_tc, c.M, c.s));
+    if (resid_host) {
+      if ((r = do_residual(c, grid, rows, x_inout, dres)) != PCT_OK) return r;
+      HIPCHECK(hipMemcpyAsync(&resid_host[it], dres, sizeof(double), hipMemcpyDeviceToHost, c.s));
+    }
+  }
+  uint32_t st = 0;
+  if ((r = read_status(c, &st)) != PCT_OK) return r;
+  return status_to_code(st);
+}
+
+pct_status pct_carve_hull(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist, float wepl_max,
+                          float min_len, uint8_t *hull_out, int64_t *n_used, void *workspace, size_t ws_bytes,
+                          void *stream) {
+  g_err.clear();
+  pct_status r;
+  pct::PathParams P;
+  if ((r = check_grid(grid)) != PCT_OK) return r;
+  if ((r = check_hist(hist)) != PCT_OK) return r;
+  if ((r = make_params(grid, geom, P)) != PCT_OK) return r;
+  if (!hull_out) return fail(PCT_EINVAL, "hull_out is NULL");
+  if (!std::isfinite(wepl_max) || !(min_len >= 0.f) || !std::isfinite(min_len))
+    return fail(PCT_EINVAL, "wepl_max must be finite and min_len >= 0");
+  if (!workspace || ws_bytes < 256) return fail(PCT_ENOMEM, "workspace of at least 256 bytes needed");
+  Ctx c;
+  c.s = reinterpret_cast<hipStream_t>(stream);
+  unsigned long long *used = static_cast<unsigned long long *>(workspace);
+  const int64_t M = grid_voxels(grid);
+  HIPCHECK(pct::launch_fill_u8(hull_out, M, 1, c.s));
+  HIPCHECK(pct::launch_fill_u32(reinterpret_cast<uint32_t *>(used), 2, 0u, c.s));
+  PROF(PCT_K_CARVE, pct::launch_carve(P, hist_ptrs(hist), hist->n, (double)wepl_max, (double)min_len, hull_out,
+                                      used, c.s));
+  if (n_used) {
+    unsigned long long u = 0;
+    HIPCHECK(hipMemcpyAsync(&u, used, sizeof u, hipMemcpyDeviceToHost, c.s));
+    HIPCHECK(hipStreamSynchronize(c.s));
+    *n_used = (int64_t)u;
+  }
+  return PCT_OK;
 }
 
 pct_status pct_residual(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist,

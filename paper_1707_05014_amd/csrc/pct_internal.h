@@ -68,7 +68,14 @@ struct Workspace {
   uint16_t *blk_cnt;     // [blk_cnt_elems] per-block voxel counts s_j of the fused sweep (or NULL)
   void *recs;            // [rec_rows] path set-up records (kPathRecBytes each)
   int64_t rec_rows;      // n (one record per history, fused sweeps) or min(n, kStageRows) (chunks)
+  void *tvs;             // [tvs_scratch_bytes(M)] TV superiorization scratch (kWsTvs) or NULL
+  float *carp_xs;        // [M] CARP: one string's image (kWsCarp) or NULL
+  float *carp_acc;       // [M] CARP: per-voxel sums of the string images
+  uint16_t *carp_tc;     // [M] CARP: strings touching each voxel
+  uint8_t *carp_touched; // [M] CARP: voxels the current string touches
 };
+// optional workspace regions (the `extra` flags below)
+constexpr int kWsTvs = 1, kWsCarp = 2;
 constexpr int64_t kMaxPartials = 1 << 16;
 constexpr int64_t kScanChunk = 4096;
 constexpr int64_t kStageRows = 1 << 20;  // rows traced per staging chunk
@@ -79,9 +86,9 @@ constexpr int64_t kMaxBlkCntBytes = int64_t(32) << 30;
 // recs_all: one path record per history (the fused sweeps set every proton up
 // once per call), else records for one chunk of kStageRows rows
 size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots = 0,
-                       int64_t blk_cnt_elems = 0, bool recs_all = false);
+                       int64_t blk_cnt_elems = 0, bool recs_all = false, int extra = 0);
 Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage_slots = 0,
-                          int64_t blk_cnt_elems = 0, bool recs_all = false);
+                          int64_t blk_cnt_elems = 0, bool recs_all = false, int extra = 0);
 
 // ---- tiled sweep plan (cached rows regrouped by block and spatial tile)
 constexpr int kTX = 16, kTY = 16, kTZ = 8;           // tile of 2048 voxels
@@ -165,6 +172,7 @@ hipError_t launch_scan_rows(int64_t *row_ptr, int64_t i0, int64_t nrows, int64_t
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
 
 hipError_t launch_mask(float *x, const uint8_t *mask, int64_t M, hipStream_t s);
 hipError_t launch_project_cached(const int64_t *row_ptr, const int32_t *idx, const void *len, int32_t len_dtype,
@@ -180,7 +188,23 @@ hipError_t launch_project_fused(const PathParams &P, const void *recs, const int
 // mode 0: counts from cnt (cleared); 1: also store them as uint16 into blk_cnt;
 // 2: counts read from blk_cnt (cnt unused)
 hipError_t launch_apply_counts(float *x, float *num, uint32_t *cnt, uint16_t *blk_cnt, int mode, const uint8_t *mask,
-                               int64_t M, float lambda, uint32_t *status, hipStream_t s);
+                               int64_t M, float lambda, uint32_t *status, hipStream_t s, uint8_t *touched = nullptr);
+// CARP: xs into the per-voxel sums of the strings touching it (touched
+// cleared), then x = mean where some string touched (acc, tc cleared)
+hipError_t launch_carp_accumulate(const float *xs, uint8_t *touched, float *acc, uint16_t *tc, int64_t M,
+                                  hipStream_t s);
+hipError_t launch_carp_average(float *x, float *acc, uint16_t *tc, int64_t M, hipStream_t s);
+hipError_t launch_copy_f32(const float *a, float *b, int64_t n, hipStream_t s);
+// total-variation superiorization steps on x (tvs.hip); scratch of
+// tvs_scratch_bytes(M) bytes; state: device double[8], state[0] = step size
+size_t tvs_scratch_bytes(int64_t M);
+hipError_t launch_tvs(int32_t nx, int32_t ny, int32_t nz, float *x, const uint8_t *mask, int32_t n_steps,
+                      int32_t max_trials, double a, double eps, double *state, void *scratch, hipStream_t s);
+// space carving (tvs.hip): hull[j] = 0 for every voxel crossed for more than
+// min_len mm by the straight line of a history with WEPL < wepl_max; *used
+// += histories used
+hipError_t launch_carve(const PathParams &P, const HistPtrs &H, int64_t n, double wepl_max, double min_len,
+                        uint8_t *hull, unsigned long long *used, hipStream_t s);
 hipError_t launch_art(const int64_t *row_ptr, const int32_t *idx, const void *len, int32_t len_dtype,
                       float len_unit, const double *norm2, const float *b, const int64_t *order, int64_t n,
                       int64_t M, float *x, const uint8_t *mask, float lambda, uint32_t *status, hipStream_t s);

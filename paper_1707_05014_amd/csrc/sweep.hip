@@ -112,13 +112,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k
   }
 }
 
+// touched (or NULL): set to 1 for every voxel the block's rows touch (CARP's
+// component averaging counts the strings that touch a voxel)
 __global__ void __launch_bounds__(256) k_apply(float *__restrict__ x, float *__restrict__ num,
                                                uint32_t *__restrict__ cnt, const uint8_t *__restrict__ mask,
-                                               int64_t M, float lambda) {
+                                               int64_t M, float lambda, uint8_t *__restrict__ touched) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < M; j += stride) {
     const uint32_t c = cnt[j];
     if (c) {
+      if (touched) touched[j] = 1;
       const float v = x[j] + lambda * num[j] / (float)c;
       x[j] = (mask && !mask[j]) ? 0.0f : v;
       num[j] = 0.0f;
@@ -153,6 +156,37 @@ __global__ void __launch_bounds__(256) k_apply_counts(float *__restrict__ x, flo
     }
   }
   if (MODE == 1 && __ballot(sat) && wave_lane() == 0) atomicOr(status, kStCountSat);
+}
+
+// CARP (Sec. 2.2): string image xs into the component sums over the strings
+// that touch each voxel (touched cleared for the next string), then the mean
+__global__ void __launch_bounds__(256) k_carp_accumulate(const float *__restrict__ xs, uint8_t *__restrict__ touched,
+                                                         float *__restrict__ acc, uint16_t *__restrict__ tc,
+                                                         int64_t M) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < M; j += stride) {
+    if (touched[j]) {
+      acc[j] += xs[j];
+      tc[j] = (uint16_t)(tc[j] + 1);
+      touched[j] = 0;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_carp_average(float *__restrict__ x, float *__restrict__ acc,
+                                                      uint16_t *__restrict__ tc, int64_t M) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < M; j += stride) {
+    const uint16_t c = tc[j];
+    if (c) x[j] = acc[j] / (float)c;
+    acc[j] = 0.0f;
+    tc[j] = 0;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_copy_f32(const float *__restrict__ a, float *__restrict__ b, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) b[j] = a[j];
 }
 
 __global__ void __launch_bounds__(256) k_mask(float *__restrict__ x, const uint8_t *__restrict__ mask, int64_t M) {
@@ -371,14 +405,31 @@ hipError_t launch_project_fused(const PathParams &P, const void *recs, const int
 }
 
 hipError_t launch_apply_counts(float *x, float *num, uint32_t *cnt, uint16_t *blk_cnt, int mode, const uint8_t *mask,
-                               int64_t M, float lambda, uint32_t *status, hipStream_t s) {
+                               int64_t M, float lambda, uint32_t *status, hipStream_t s, uint8_t *touched) {
   const dim3 g(grid_for(M, 256, 8192)), b(256);
   if (mode == 0)
-    hipLaunchKernelGGL(k_apply, g, b, 0, s, x, num, cnt, mask, M, lambda);
+    hipLaunchKernelGGL(k_apply, g, b, 0, s, x, num, cnt, mask, M, lambda, touched);
   else if (mode == 1)
     hipLaunchKernelGGL(k_apply_counts<1>, g, b, 0, s, x, num, cnt, blk_cnt, mask, M, lambda, status);
   else
     hipLaunchKernelGGL(k_apply_counts<2>, g, b, 0, s, x, num, cnt, blk_cnt, mask, M, lambda, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_carp_accumulate(const float *xs, uint8_t *touched, float *acc, uint16_t *tc, int64_t M,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_carp_accumulate, dim3(grid_for(M, 256, 8192)), dim3(256), 0, s, xs, touched, acc, tc, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_carp_average(float *x, float *acc, uint16_t *tc, int64_t M, hipStream_t s) {
+  hipLaunchKernelGGL(k_carp_average, dim3(grid_for(M, 256, 8192)), dim3(256), 0, s, x, acc, tc, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_f32(const float *a, float *b, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_f32, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, a, b, n);
   return hipGetLastError();
 }
 

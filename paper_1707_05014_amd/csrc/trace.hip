@@ -267,5 +267,10 @@ hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
+hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<uint8_t>, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
 
 }  // namespace pct

@@ -98,11 +98,15 @@ def _load():
 
 
 def default_threads() -> int:
-    n = os.cpu_count() or 1
+    """Every core this process may run on, limited by OMP_NUM_THREADS."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
     env = os.environ.get("OMP_NUM_THREADS")
-    if env and env.isdigit():
+    if env and env.isdigit() and int(env) > 0:
         n = min(n, int(env))
-    return max(1, min(n, 16))
+    return max(1, n)
 
 
 # ----------------------------------------------------------------- geometry

@@ -86,3 +86,128 @@ def compare_rows(o_ptr, o_idx, o_len, g_ptr, g_idx, g_len, len_tol=1e-4):
                 frac_len_ok=float(ok.sum()) / n_good if n_good else 1.0,
                 max_dlen=max_d_good, max_dlen_all=float(d.max()) if len(d) else 0.0,
                 max_only_len=float(only.max()) if len(only) else 0.0)
+
+
+# ------------------------------------------------- geometry of row mismatches
+FACE_TOL = 1e-4     # mm: how close to a voxel face a path must pass for a mismatch to be allowed
+GRAZE_LEN = 0.1     # mm of path within FACE_TOL of one face: a crossing at a sine <= 2e-3
+
+
+def polyline_xyz(geom, hist_row) -> np.ndarray:
+    """The oracle's most-likely-path polyline of one history, object frame (n x 3)."""
+    u, t, v = oracle.mlp_path(geom, hist_row)
+    c, s = np.cos(hist_row[0]), np.sin(hist_row[0])
+    return np.stack([u * c - t * s, u * s + t * c, v], axis=1)
+
+
+def voxel_box(cfg: synth.Config, j: int):
+    g = cfg.grid
+    i, jj, k = j % g.nx, (j // g.nx) % g.ny, j // (g.nx * g.ny)
+    lo = np.array([g.ox + i * g.dx, g.oy + jj * g.dy, g.oz + k * g.dz])
+    return lo, lo + np.array([g.dx, g.dy, g.dz])
+
+
+def signed_depth(p, lo, hi):
+    """Distance from p to the box surface, positive inside, negative outside
+    (a concave function along any line, since the box is convex)."""
+    p = np.asarray(p, np.float64)
+    ins = np.minimum(p - lo, hi - p).min(axis=-1)
+    out = np.linalg.norm(np.maximum(np.maximum(lo - p, p - hi), 0.0), axis=-1)
+    return np.where(ins >= 0.0, ins, -out)
+
+
+def _segments_near(xyz, lo, hi, pad: float):
+    """Segments of the polyline whose bounding boxes meet the box grown by pad."""
+    P, Q = xyz[:-1], xyz[1:]
+    bl, bh = np.minimum(P, Q), np.maximum(P, Q)
+    hit = np.all((bh >= lo - pad) & (bl <= hi + pad), axis=1)
+    return P[hit], Q[hit]
+
+
+def max_penetration(xyz, lo, hi, iters: int = 90, pad: float = 1.0) -> float:
+    """max over the polyline of signed_depth: how deep the path enters the box
+    (negative: how far it stays outside; -inf beyond pad).  Ternary search per
+    segment on the concave depth profile."""
+    best = -np.inf
+    for P, Q in zip(*_segments_near(np.asarray(xyz, np.float64), lo, hi, pad)):
+        a, b = 0.0, 1.0
+        for _ in range(iters):
+            m1, m2 = a + (b - a) / 3.0, b - (b - a) / 3.0
+            if signed_depth(P + m1 * (Q - P), lo, hi) < signed_depth(P + m2 * (Q - P), lo, hi):
+                a = m1
+            else:
+                b = m2
+        s = 0.5 * (a + b)
+        best = max(best, float(signed_depth(P + s * (Q - P), lo, hi)), float(signed_depth(P, lo, hi)),
+                   float(signed_depth(Q, lo, hi)))
+    return best
+
+
+def near_face_length(xyz, lo, hi, tol: float = FACE_TOL, h: float = 2e-5) -> float:
+    """Largest length of path, over the six faces of the box, that lies within
+    tol of the face's plane and within tol of the face itself (sampled every
+    h mm).  A crossing of the face at an angle of sine sin_t gives about
+    2 tol / sin_t; a path running along the face gives its whole length."""
+    best = 0.0
+    span = np.stack([lo, hi])
+    for P, Q in zip(*_segments_near(np.asarray(xyz, np.float64), lo, hi, tol)):
+        seg = float(np.linalg.norm(Q - P))
+        if seg == 0.0:
+            continue
+        s = np.linspace(0.0, 1.0, max(2, int(np.ceil(seg / h)) + 1))
+        pts = P[None, :] + s[:, None] * (Q - P)[None, :]
+        for a in range(3):
+            o = [q for q in range(3) if q != a]
+            within = np.all((pts[:, o] >= lo[o] - tol) & (pts[:, o] <= hi[o] + tol), axis=1)
+            for side in range(2):
+                near = within & (np.abs(pts[:, a] - span[side, a]) <= tol)
+                best = max(best, float(near.sum()) * seg / (len(s) - 1))
+    return best
+
+
+def mismatch_voxels(o_ptr, o_idx, o_len, g_ptr, g_idx, g_len, len_tol: float = 1e-4):
+    """(row, voxel, kind, dlen) for every voxel present in one row set only
+    (kind 'oracle' / 'gpu') or present in both with lengths more than len_tol
+    apart (kind 'length'); rows fully merged and sorted by voxel."""
+    n = len(o_ptr) - 1
+    ro = np.repeat(np.arange(n, dtype=np.int64), np.diff(o_ptr))
+    rg = np.repeat(np.arange(n, dtype=np.int64), np.diff(g_ptr))
+    ko = ro * (1 << 31) + np.asarray(o_idx, np.int64)
+    kg = rg * (1 << 31) + np.asarray(g_idx, np.int64)
+    in_g = np.isin(ko, kg, assume_unique=True)
+    in_o = np.isin(kg, ko, assume_unique=True)
+    out = []
+    for k, ln in zip(ko[~in_g], np.asarray(o_len)[~in_g]):
+        out.append((int(k >> 31), int(k & ((1 << 31) - 1)), "oracle", float(ln)))
+    for k, ln in zip(kg[~in_o], np.asarray(g_len)[~in_o]):
+        out.append((int(k >> 31), int(k & ((1 << 31) - 1)), "gpu", float(ln)))
+    d = np.asarray(g_len)[in_o] - np.asarray(o_len)[in_g]
+    kc = ko[in_g]
+    for k, dl in zip(kc[np.abs(d) > len_tol], d[np.abs(d) > len_tol]):
+        out.append((int(k >> 31), int(k & ((1 << 31) - 1)), "length", float(dl)))
+    return out
+
+
+def check_mismatch_geometry(cfg, geom, h: dict, rows_sel, cases, limit: int = 400):
+    """Every mismatch must sit where the oracle's path passes within FACE_TOL
+    of a voxel face: a one-sided voxel is entered (or missed) by at most
+    FACE_TOL; a length difference on a common voxel needs the path to run
+    within FACE_TOL of one of its faces over at least GRAZE_LEN.  rows_sel
+    maps the row numbers of `cases` to history indices.  Returns the list of
+    violations (empty when all hold) and the worst penetration seen."""
+    bad = []
+    worst = 0.0
+    for (r, j, kind, val) in cases[:limit]:
+        i = int(rows_sel[r])
+        xyz = polyline_xyz(geom, hist_row(h, i))
+        lo, hi = voxel_box(cfg, j)
+        if kind in ("oracle", "gpu"):
+            pen = max_penetration(xyz, lo, hi)
+            worst = max(worst, abs(pen))
+            if abs(pen) > FACE_TOL:
+                bad.append((i, j, kind, val, pen))
+        else:
+            nl = near_face_length(xyz, lo, hi)
+            if nl < GRAZE_LEN:
+                bad.append((i, j, kind, val, nl))
+    return bad, worst

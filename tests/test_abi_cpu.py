@@ -31,7 +31,8 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(_lib.pct_geom) == 48 + 64 + 16
     assert ctypes.sizeof(_lib.pct_histories) == 8 + 10 * 8
     assert ctypes.sizeof(_lib.pct_rows) == 3 * 8 + 3 * 8 + 8 + 8
-    assert ctypes.sizeof(_lib.pct_sweep_params) == 4 + 4 + 8 + 4 + 4 + 8 + 8
+    assert ctypes.sizeof(_lib.pct_sweep_params) == 4 + 4 + 8 + 4 + 4 + 8 + 8 + 8
+    assert ctypes.sizeof(_lib.pct_tvs) == 4 + 4 + 8 + 8 + 8
     assert ctypes.sizeof(_lib.pct_plan) == 8 + 8 + 11 * 8 + 4 * 4 + 2 * 8 + 2 * 4
 
 
@@ -163,3 +164,34 @@ def test_workspace_grows_for_fused_records():
     p = api.sweep_params("drop", 1 << 20, 0.5, 4)
     kept = lib.pct_workspace_size(ctypes.byref(g), None, ctypes.byref(p.struct), n, 1)
     assert kept - fused >= 3 * g.nx * g.ny * g.nz * 2
+
+
+def test_tvs_carp_carve_args_rejected_on_host():
+    lib = _lib.load()
+    g = _grid()
+    geo = _geom()
+    x = ctypes.c_float(0.0)
+    t = _lib.pct_tvs(1, 0, 0.9, 1e-3, None)       # max_trials 0
+    assert lib.pct_tvs_apply(ctypes.byref(g), ctypes.addressof(x), None, ctypes.byref(t), None, 0, None) == \
+        _lib.PCT_EINVAL
+    t = _lib.pct_tvs(1, 3, 1.5, 1e-3, None)       # a outside (0, 1)
+    assert lib.pct_tvs_apply(ctypes.byref(g), ctypes.addressof(x), None, ctypes.byref(t), None, 0, None) == \
+        _lib.PCT_EINVAL
+    t = _lib.pct_tvs(0, 0, 0.0, 0.0, None)        # off: nothing to do
+    assert lib.pct_tvs_apply(ctypes.byref(g), ctypes.addressof(x), None, ctypes.byref(t), None, 0, None) == _lib.PCT_OK
+    h = _lib.pct_histories()
+    h.n = 0
+    p = api.sweep_params("drop", 10, 0.5, 1)
+    for ns in (0, 5000):
+        assert lib.pct_carp(ctypes.byref(g), ctypes.byref(geo), ctypes.byref(h), ctypes.byref(p.struct), ns, None,
+                            ctypes.addressof(x), None, None, 0, None) == _lib.PCT_EINVAL
+    assert lib.pct_carve_hull(ctypes.byref(g), ctypes.byref(geo), ctypes.byref(h), 1.5, 1e-6, None, None, None, 0,
+                              None) == _lib.PCT_EINVAL
+    assert lib.pct_carve_hull(ctypes.byref(g), ctypes.byref(geo), ctypes.byref(h), float("inf"), 1e-6,
+                              ctypes.addressof(x), None, None, 0, None) == _lib.PCT_EINVAL
+    # ART with TVS is refused
+    tv = _lib.pct_tvs(1, 3, 0.9, 1e-3, ctypes.addressof(ctypes.c_double(1.0)))
+    pa = api.sweep_params("art", 1, 0.5, 1)
+    pa.struct.tvs = ctypes.pointer(tv)
+    assert lib.pct_project_sweep(ctypes.byref(g), ctypes.byref(geo), ctypes.byref(h), None, ctypes.addressof(x),
+                                 ctypes.byref(pa.struct), None, None, 0, None) == _lib.PCT_EINVAL
