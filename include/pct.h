@@ -327,6 +327,43 @@ enum {
 pct_status pct_profile_enable(int32_t on);
 pct_status pct_profile_read(int64_t *launches, double *ms);
 
+/* Memory-path microbenchmarks: the measured peaks against which the sweeps'
+ * achieved rates are reported (the paper's Sec. 4.1 finds the reconstruction
+ * bound by its data movement; the last-level cache bandwidth and the atomic
+ * rate of the device have no published figure).  Each call runs `reps`
+ * launches of one probe on `stream` and returns the mean device time of a
+ * launch in *ms_out (HIP events; the call synchronises the stream).
+ *   PCT_PROBE_COPY        copies `region` floats (buf[0:region] ->
+ *                         buf[region:2 region]); region % 4 == 0.  Bytes
+ *                         moved per launch: 8 region.
+ *   PCT_PROBE_GATHER      n_ops 4-byte reads at hashed positions inside the
+ *                         first `region` floats of buf (one float per thread
+ *                         written after them).  A region that fits the
+ *                         last-level cache gives its gather bandwidth.
+ *   PCT_PROBE_ATOMIC      n_ops FP32 atomic adds of 1.0 in path-like runs (64
+ *                         lanes along one random line of a 200 x 200 x ...
+ *                         grid per row) into buf[0:region].
+ *   PCT_PROBE_ATOMIC_XCD  the same into one private copy per die
+ *                         (buf[8 region]; copy = the die's hardware id), with
+ *                         workgroup-scope atomics.
+ *   PCT_PROBE_LDS_ATOMIC  the same into a 16384-float image in each
+ *                         workgroup's LDS (region unused).
+ * buf: device, at least pct_probe_bytes(kind, region, n_ops) bytes, caller
+ * owned; the atomic probes add into it (zero it to check the total: each
+ * launch adds floor(n_ops / 64) * 64).  n_ops >= 64 * 2048 for every probe
+ * but the copy.  Errors: PCT_EINVAL for a bad kind, size or count,
+ * PCT_ENOMEM for a short buffer, PCT_EDEVICE for a failed launch. */
+typedef enum {
+    PCT_PROBE_COPY = 0,
+    PCT_PROBE_GATHER = 1,
+    PCT_PROBE_ATOMIC = 2,
+    PCT_PROBE_ATOMIC_XCD = 3,
+    PCT_PROBE_LDS_ATOMIC = 4
+} pct_probe_kind;
+size_t pct_probe_bytes(int32_t kind, int64_t region, int64_t n_ops);
+pct_status pct_probe(int32_t kind, void *buf, size_t buf_bytes, int64_t region, int64_t n_ops, int32_t reps,
+                     double *ms_out, void *stream);
+
 /* Message for the last failing call on this thread (empty if none). */
 const char *pct_last_error(void);
 

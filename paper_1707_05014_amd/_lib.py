@@ -18,6 +18,7 @@ PCT_ENOMEM = -2
 PCT_EDEVICE = -3
 PCT_EROWCAP = -4
 PCT_ENONFINITE = -5
+PROBE_KINDS = {"copy": 0, "gather": 1, "atomic": 2, "atomic_xcd": 3, "lds_atomic": 4}
 STATUS_NAMES = {0: "PCT_OK", -1: "PCT_EINVAL", -2: "PCT_ENOMEM", -3: "PCT_EDEVICE", -4: "PCT_EROWCAP",
                 -5: "PCT_ENONFINITE"}
 
@@ -78,7 +79,7 @@ class pct_sweep_params(ctypes.Structure):
 EXPORTS = ("pct_workspace_size", "pct_mlp_trace", "pct_project_sweep", "pct_plan_build", "pct_plan_sweep",
            "pct_plan_residual", "pct_reconstruct", "pct_residual", "pct_roi_stats", "pct_profile_enable",
            "pct_tvs_apply", "pct_carp", "pct_carp_workspace_size", "pct_carve_hull",
-           "pct_profile_read", "pct_last_error",
+           "pct_profile_read", "pct_last_error", "pct_probe", "pct_probe_bytes",
            "pct_cnn_conv3d", "pct_cnn_conv3d_bwd_data", "pct_cnn_wgrad_scratch", "pct_cnn_conv3d_bwd_weight",
            "pct_cnn_relu", "pct_cnn_relu_bwd", "pct_cnn_pool", "pct_cnn_pool_bwd", "pct_cnn_upsample",
            "pct_cnn_upsample_bwd", "pct_cnn_add", "pct_cnn_axpy", "pct_cnn_mask", "pct_cnn_mse_scratch", "pct_cnn_mse", "pct_cnn_adam")
@@ -145,6 +146,11 @@ def load(path: str | None = None):
     lib.pct_profile_enable.argtypes = [ctypes.c_int32]
     lib.pct_profile_read.restype = ctypes.c_int
     lib.pct_profile_read.argtypes = [P(ctypes.c_int64), P(ctypes.c_double)]
+    lib.pct_probe_bytes.restype = ctypes.c_size_t
+    lib.pct_probe_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64]
+    lib.pct_probe.restype = ctypes.c_int
+    lib.pct_probe.argtypes = [ctypes.c_int32, _fp, ctypes.c_size_t, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                              P(ctypes.c_double), _fp]
     lib.pct_last_error.restype = ctypes.c_char_p
     lib.pct_last_error.argtypes = []
     i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float

@@ -377,3 +377,22 @@ def profile_read() -> dict:
     ms = (ctypes.c_double * n)()
     check(_lib.load().pct_profile_read(launches, ms))
     return {k: (int(launches[i]), float(ms[i])) for i, k in enumerate(_lib.KERNEL_CLASSES)}
+
+
+def probe(kind: str, region: int, n_ops: int = 0, reps: int = 5, buf: torch.Tensor | None = None,
+          stream=None) -> tuple[float, torch.Tensor]:
+    """Mean device time (ms) of one launch of memory-path probe `kind` (one of
+    _lib.PROBE_KINDS; see pct_probe in include/pct.h) and the buffer it ran
+    on (zeroed first, so an atomic probe's buffer sums to reps x the adds of
+    a launch)."""
+    lib = _lib.load()
+    k = _lib.PROBE_KINDS[kind]
+    need = int(lib.pct_probe_bytes(k, region, n_ops))
+    if buf is None:
+        buf = torch.zeros((need + 3) // 4, dtype=torch.float32, device="cuda")
+    else:
+        buf.zero_()
+    ms = ctypes.c_double(0.0)
+    _lib.check(lib.pct_probe(k, _ptr(buf), buf.numel() * buf.element_size(), region, n_ops, reps,
+                             ctypes.byref(ms), _stream_ptr(stream)))
+    return ms.value, buf

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpct.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build", "pct")
-SOURCES = ("trace.hip", "sweep.hip", "plan.hip", "cnn.hip", "tvs.hip", "abi.hip")
+SOURCES = ("trace.hip", "sweep.hip", "plan.hip", "cnn.hip", "tvs.hip", "probe.hip", "abi.hip")
 ARCH = os.environ.get("PCT_OFFLOAD_ARCH", "gfx950")
 
 CFLAGS = [

@@ -1074,6 +1074,45 @@ pct_status pct_profile_enable(int32_t on) {
   return PCT_OK;
 }
 
+pct_status pct_probe(int32_t kind, void *buf, size_t buf_bytes, int64_t region, int64_t n_ops, int32_t reps,
+                     double *ms_out, void *stream) {
+  g_err.clear();
+  if (kind < PCT_PROBE_COPY || kind > PCT_PROBE_LDS_ATOMIC) return fail(PCT_EINVAL, "unknown probe kind %d", kind);
+  if (!ms_out) return fail(PCT_EINVAL, "ms_out is NULL");
+  if (reps < 1 || reps > 1000) return fail(PCT_EINVAL, "reps must be 1..1000");
+  if (kind != PCT_PROBE_LDS_ATOMIC && (region < 64 || region > 0x7fffffffLL))
+    return fail(PCT_EINVAL, "region must be 64..2^31-1 elements");
+  if (kind == PCT_PROBE_COPY && region % 4 != 0) return fail(PCT_EINVAL, "copy region must be a multiple of 4");
+  if (kind != PCT_PROBE_COPY && (n_ops < 64 * pct::kProbeGrid || n_ops > (int64_t)1 << 40))
+    return fail(PCT_EINVAL, "n_ops must be %lld..2^40", (long long)(64 * pct::kProbeGrid));
+  const size_t need = pct::probe_bytes(kind, region, n_ops, pct::kProbeGrid);
+  if (!buf || buf_bytes < need)
+    return fail(PCT_ENOMEM, "probe buffer of %zu bytes given, %zu needed", buf ? buf_bytes : (size_t)0, need);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPCHECK(hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) {
+    hipEventDestroy(a);
+    return fail(PCT_EDEVICE, "hipEventCreate failed");
+  }
+  hipError_t e = hipEventRecord(a, s);
+  for (int32_t r = 0; r < reps && e == hipSuccess; ++r) e = pct::launch_probe(kind, buf, region, n_ops, pct::kProbeGrid, s);
+  if (e == hipSuccess) e = hipEventRecord(b, s);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  if (e != hipSuccess) return fail(PCT_EDEVICE, "probe: %s", hipGetErrorString(e));
+  *ms_out = (double)ms / reps;
+  return PCT_OK;
+}
+
+size_t pct_probe_bytes(int32_t kind, int64_t region, int64_t n_ops) {
+  if (kind < PCT_PROBE_COPY || kind > PCT_PROBE_LDS_ATOMIC || region < 0 || n_ops < 0) return 0;
+  return pct::probe_bytes(kind, region, n_ops, pct::kProbeGrid);
+}
+
 pct_status pct_profile_read(int64_t *launches, double *ms) {
   g_err.clear();
   if (!launches || !ms) return fail(PCT_EINVAL, "NULL output array");

@@ -219,6 +219,10 @@ hipError_t launch_residual_fused(const PathParams &P, const void *recs, int64_t 
 hipError_t launch_residual_final(const double *partials, int64_t np, double *out, hipStream_t s);
 // *out = NaN if any status bit is set (asynchronous error report)
 hipError_t launch_poison_on_status(double *out, const uint32_t *status, hipStream_t s);
+// memory-path microbenchmarks (probe.hip)
+constexpr int64_t kProbeGrid = 2048;
+size_t probe_bytes(int kind, int64_t region, int64_t n_ops, int64_t grid);
+hipError_t launch_probe(int kind, void *buf, int64_t region, int64_t n_ops, int64_t grid, hipStream_t s);
 hipError_t launch_roi(const float *x, const uint8_t *labels, int64_t M, int32_t n_labels, double *sums,
                       int64_t *counts, hipStream_t s);
 

@@ -195,3 +195,25 @@ def test_tvs_carp_carve_args_rejected_on_host():
     pa.struct.tvs = ctypes.pointer(tv)
     assert lib.pct_project_sweep(ctypes.byref(g), ctypes.byref(geo), ctypes.byref(h), None, ctypes.addressof(x),
                                  ctypes.byref(pa.struct), None, None, 0, None) == _lib.PCT_EINVAL
+
+
+def test_probe_args_rejected_on_host():
+    """The memory-path probes check kind, sizes, counts and the buffer on the
+    host before any launch."""
+    lib = _lib.load()
+    ms = ctypes.c_double(0.0)
+    buf = ctypes.c_void_p(1)  # never dereferenced: every call below fails validation first
+    E = _lib.PCT_EINVAL
+    K = _lib.PROBE_KINDS
+    assert lib.pct_probe(9, buf, 1 << 30, 1024, 1 << 20, 1, ctypes.byref(ms), None) == E
+    assert lib.pct_probe(K["copy"], buf, 1 << 30, 1022, 0, 1, ctypes.byref(ms), None) == E   # not a multiple of 4
+    assert lib.pct_probe(K["atomic"], buf, 1 << 30, 32, 1 << 20, 1, ctypes.byref(ms), None) == E  # region < 64
+    assert lib.pct_probe(K["atomic"], buf, 1 << 30, 1024, 100, 1, ctypes.byref(ms), None) == E  # too few ops
+    assert lib.pct_probe(K["gather"], buf, 1 << 30, 1024, 1 << 20, 0, ctypes.byref(ms), None) == E  # reps
+    assert lib.pct_probe(K["gather"], buf, 1 << 30, 1024, 1 << 20, 1, None, None) == E
+    need = lib.pct_probe_bytes(K["atomic_xcd"], 1_600_000, 1 << 26)
+    assert need == 8 * 4 * 1_600_000
+    assert lib.pct_probe(K["atomic_xcd"], buf, need - 1, 1_600_000, 1 << 26, 1, ctypes.byref(ms), None) == \
+        _lib.PCT_ENOMEM
+    assert lib.pct_probe_bytes(K["copy"], 1024, 0) == 8 * 1024
+    assert lib.pct_probe_bytes(7, 1024, 0) == 0
