@@ -217,6 +217,24 @@ pct_status pct_project_sweep(const pct_grid *grid, const pct_geom *geom, const p
                              const pct_rows *rows, float *x, const pct_sweep_params *params, double *resid_out,
                              void *workspace, size_t ws_bytes, void *stream);
 
+/* pct_project_sweep over cached rows for callers that cannot allocate or
+ * pass device memory of their own: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  Same arguments and
+ * results as pct_project_sweep with rows != NULL, but no workspace: the
+ * sweep's scratch (status word, DROP numerators and counts, residual partial
+ * sums; 16.5 MiB) is a static device array of the library, one per GPU,
+ * held until the process ends.  Nothing is allocated by the call.  The grid
+ * may hold at most 2^21 voxels (PCT_EINVAL beyond); rows must be given
+ * (PCT_EINVAL for NULL) and TV superiorization is not available here
+ * (PCT_EINVAL if params->tvs asks for steps).  The array keeps the last
+ * call's contents; each call clears what it needs.  Every call on one GPU
+ * shares that GPU's array, so calls that overlap on one GPU (several
+ * streams or threads at once) race and give undefined results.  Runs on the
+ * device current on the calling thread.  Asynchronous. */
+pct_status pct_project_sweep_noalloc(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist,
+                                     const pct_rows *rows, float *x, const pct_sweep_params *params,
+                                     double *resid_out, void *stream);
+
 /* Build the sweep plan of cached rows for params (DROP, block_size <= 2^18;
  * b from hist->wepl).  With plan->mem == NULL this is a sizing call: it sets
  * plan->bytes and returns PCT_OK.  Otherwise plan->bytes must be at least the

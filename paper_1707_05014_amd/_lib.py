@@ -76,7 +76,7 @@ class pct_sweep_params(ctypes.Structure):
                 ("tvs", ctypes.POINTER(pct_tvs))]
 
 
-EXPORTS = ("pct_workspace_size", "pct_mlp_trace", "pct_project_sweep", "pct_plan_build", "pct_plan_sweep",
+EXPORTS = ("pct_workspace_size", "pct_mlp_trace", "pct_project_sweep", "pct_project_sweep_noalloc", "pct_plan_build", "pct_plan_sweep",
            "pct_plan_residual", "pct_reconstruct", "pct_residual", "pct_roi_stats", "pct_profile_enable",
            "pct_tvs_apply", "pct_carp", "pct_carp_workspace_size", "pct_carve_hull",
            "pct_profile_read", "pct_last_error", "pct_probe", "pct_probe_bytes",
@@ -115,6 +115,9 @@ def load(path: str | None = None):
     lib.pct_project_sweep.restype = ctypes.c_int
     lib.pct_project_sweep.argtypes = [P(pct_grid), P(pct_geom), P(pct_histories), P(pct_rows), _fp,
                                       P(pct_sweep_params), _fp, _fp, ctypes.c_size_t, _fp]
+    lib.pct_project_sweep_noalloc.restype = ctypes.c_int
+    lib.pct_project_sweep_noalloc.argtypes = [P(pct_grid), P(pct_geom), P(pct_histories), P(pct_rows), _fp,
+                                              P(pct_sweep_params), _fp, _fp]
     lib.pct_plan_build.restype = ctypes.c_int
     lib.pct_plan_build.argtypes = [P(pct_grid), P(pct_histories), P(pct_rows), P(pct_sweep_params), P(pct_plan),
                                    _fp, ctypes.c_size_t, _fp]

@@ -813,6 +813,83 @@ pct_status pct_project_sweep(const pct_grid *grid, const pct_geom *geom, const p
   return PCT_OK;
 }
 
+// ---- one sweep over cached rows with no workspace argument: its scratch
+// (status word, DROP numerators and counts, residual partial sums) is the
+// library's static device array below, one copy per GPU
+namespace {
+
+constexpr int64_t kNoAllocMaxVoxels = int64_t(1) << 21;
+constexpr size_t kNoAllocStatusBytes = 256;
+constexpr size_t kNoAllocBytes =
+    kNoAllocStatusBytes + 2 * (size_t)kNoAllocMaxVoxels * 4 + (size_t)pct::kMaxPartials * sizeof(double);
+constexpr int kNoAllocMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+// the device address of `scratch` on the current device (looked up once per
+// device; host code never uses the array's name as an address)
+pct_status noalloc_scratch(void **out) {
+  int dev = -1;
+  HIPCHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return fail(PCT_EDEVICE, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> g(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(PCT_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return PCT_OK;
+}
+
+}  // namespace
+
+pct_status pct_project_sweep_noalloc(const pct_grid *grid, const pct_geom *geom, const pct_histories *hist,
+                                     const pct_rows *rows, float *x, const pct_sweep_params *params,
+                                     double *resid_out, void *stream) {
+  g_err.clear();
+  Ctx c;
+  pct_status r;
+  if (!rows) return fail(PCT_EINVAL, "the no-allocation sweep needs cached rows");
+  if ((r = check_params(params, true)) != PCT_OK) return r;
+  if (tvs_on(params)) return fail(PCT_EINVAL, "the no-allocation sweep runs without TV superiorization");
+  if ((r = check_grid(grid)) != PCT_OK) return r;
+  if ((r = check_hist(hist)) != PCT_OK) return r;
+  if ((r = make_params(grid, geom, c.P)) != PCT_OK) return r;
+  c.M = grid_voxels(grid);
+  c.n = hist->n;
+  if (c.M > kNoAllocMaxVoxels)
+    return fail(PCT_EINVAL, "grid of %lld voxels exceeds the no-allocation scratch (at most %lld voxels)",
+                (long long)c.M, (long long)kNoAllocMaxVoxels);
+  if ((r = check_rows(rows, c.n, true)) != PCT_OK) return r;
+  if (!x) return fail(PCT_EINVAL, "x is NULL");
+  void *base = nullptr;
+  if ((r = noalloc_scratch(&base)) != PCT_OK) return r;
+  char *p = static_cast<char *>(base);
+  c.H = hist_ptrs(hist);
+  c.W = pct::Workspace{};
+  c.W.status = reinterpret_cast<uint32_t *>(p);
+  c.W.num = reinterpret_cast<float *>(p + kNoAllocStatusBytes);
+  c.W.cnt = reinterpret_cast<uint32_t *>(p + kNoAllocStatusBytes + (size_t)kNoAllocMaxVoxels * 4);
+  c.W.partials = reinterpret_cast<double *>(p + kNoAllocStatusBytes + 2 * (size_t)kNoAllocMaxVoxels * 4);
+  c.s = reinterpret_cast<hipStream_t>(stream);
+  // the array keeps the previous call's contents: the status word is cleared
+  // here, the numerators and counts by do_sweep, the partials are written
+  // before they are read
+  HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
+  if ((r = do_sweep(c, grid, rows, x, params)) != PCT_OK) return r;
+  if (resid_out) {
+    if ((r = do_residual(c, grid, rows, x, resid_out)) != PCT_OK) return r;
+    HIPCHECK(pct::launch_poison_on_status(resid_out, c.W.status, c.s));
+  }
+  return PCT_OK;
+}
+
 pct_status pct_plan_build(const pct_grid *grid, const pct_histories *hist, const pct_rows *rows,
                           const pct_sweep_params *params, pct_plan *plan, void *workspace, size_t ws_bytes,
                           void *stream) {
