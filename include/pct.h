@@ -340,7 +340,8 @@ enum {
     PCT_K_TVS = 12,          /* total-variation superiorization steps */
     PCT_K_CARP = 13,         /* CARP string copies, sums and averages */
     PCT_K_CARVE = 14,        /* space-carving hull */
-    PCT_K_COUNT = 15
+    PCT_K_PROJECT_COUNTING = 15, /* rebuilt-row projection that also counts s_j (atomics; first sweep) */
+    PCT_K_COUNT = 16
 };
 pct_status pct_profile_enable(int32_t on);
 pct_status pct_profile_read(int64_t *launches, double *ms);
@@ -354,18 +355,22 @@ pct_status pct_profile_read(int64_t *launches, double *ms);
  *   PCT_PROBE_COPY        copies `region` floats (buf[0:region] ->
  *                         buf[region:2 region]); region % 4 == 0.  Bytes
  *                         moved per launch: 8 region.
- *   PCT_PROBE_GATHER      n_ops 4-byte reads at hashed positions inside the
- *                         first `region` floats of buf (one float per thread
- *                         written after them).  A region that fits the
- *                         last-level cache gives its gather bandwidth.
- *   PCT_PROBE_ATOMIC      n_ops FP32 atomic adds of 1.0 in path-like runs (64
- *                         lanes along one random line of a 200 x 200 x ...
- *                         grid per row) into buf[0:region].
+ *   PCT_PROBE_GATHER      n_ops 4-byte reads of an image of `region` voxels
+ *                         (buf[0:region]; one float per thread written
+ *                         after it), 64 per wavefront pass along a straight
+ *                         line at a hashed angle in a z plane of a 200 x 200
+ *                         x (region / 40000) grid numbered in 4 x 4 x 4
+ *                         bricks, as the rebuilt-row sweeps read x; region a
+ *                         multiple of 160000.
+ *   PCT_PROBE_ATOMIC      n_ops FP32 atomic adds of 1.0 along the same runs
+ *                         into buf[0:region], as the rebuilt-row sweeps add
+ *                         their numerators.
  *   PCT_PROBE_ATOMIC_XCD  the same into one private copy per die
  *                         (buf[8 region]; copy = the die's hardware id), with
  *                         workgroup-scope atomics.
- *   PCT_PROBE_LDS_ATOMIC  the same into a 16384-float image in each
- *                         workgroup's LDS (region unused).
+ *   PCT_PROBE_LDS_ATOMIC  n_ops FP32 atomic adds at hashed positions of a
+ *                         2048-float image in each workgroup's LDS (region
+ *                         unused).
  * buf: device, at least pct_probe_bytes(kind, region, n_ops) bytes, caller
  * owned; the atomic probes add into it (zero it to check the total: each
  * launch adds floor(n_ops / 64) * 64).  n_ops >= 64 * 2048 for every probe

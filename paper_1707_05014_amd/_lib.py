@@ -84,7 +84,7 @@ EXPORTS = ("pct_workspace_size", "pct_mlp_trace", "pct_project_sweep", "pct_proj
            "pct_cnn_relu", "pct_cnn_relu_bwd", "pct_cnn_pool", "pct_cnn_pool_bwd", "pct_cnn_upsample",
            "pct_cnn_upsample_bwd", "pct_cnn_add", "pct_cnn_axpy", "pct_cnn_mask", "pct_cnn_mse_scratch", "pct_cnn_mse", "pct_cnn_adam")
 KERNEL_CLASSES = ("trace_path", "trace_compact", "project", "apply", "residual", "art", "other", "plan_dot",
-                  "plan_rows", "plan_scatter", "plan_build", "path_setup", "tvs", "carp", "carve")
+                  "plan_rows", "plan_scatter", "plan_build", "path_setup", "tvs", "carp", "carve", "project_counting")
 
 _lib = None
 

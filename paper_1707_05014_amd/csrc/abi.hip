@@ -91,13 +91,26 @@ inline size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 int64_t grid_voxels(const pct_grid *g) { return (int64_t)g->nx * g->ny * g->nz; }
 
+// voxels of the grid rounded up to whole 4 x 4 x 4 bricks: the length of the
+// workspace's per-voxel arrays, which the rebuilt-row sweeps index in brick
+// order
+int64_t brick_voxels(const pct_grid *g) {
+  return (int64_t)((g->nx + 3) / 4) * ((g->ny + 3) / 4) * ((g->nz + 3) / 4) * 64;
+}
+
+pct::PathParams brick_params(const pct::PathParams &P) {
+  pct::PathParams b = P;
+  b.brick = 1;
+  return b;
+}
+
 pct_status check_grid(const pct_grid *g) {
   if (!g) return fail(PCT_EINVAL, "grid is NULL");
   if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0) return fail(PCT_EINVAL, "grid dimensions must be positive");
   if (!(g->dx > 0.f && g->dy > 0.f && g->dz > 0.f)) return fail(PCT_EINVAL, "voxel sizes must be positive");
   if (!(std::isfinite(g->ox) && std::isfinite(g->oy) && std::isfinite(g->oz)))
     return fail(PCT_EINVAL, "grid origin must be finite");
-  if (grid_voxels(g) > 0x7fffffffLL) return fail(PCT_EINVAL, "grid has more than 2^31-1 voxels");
+  if (brick_voxels(g) > 0x7fffffffLL) return fail(PCT_EINVAL, "grid has more than 2^31-1 voxels in whole 4x4x4 bricks");
   return PCT_OK;
 }
 
@@ -154,6 +167,9 @@ pct_status make_params(const pct_grid *g, const pct_geom *G, pct::PathParams &P)
   P.oy = g->oy;
   P.oz = g->oz;
   P.eps_len = 1e-6f * dmin;
+  P.brick = 0;
+  P.nbx = (g->nx + 3) / 4;
+  P.nby = (g->ny + 3) / 4;
   const double reach = 2.0 * std::max(G->hull_a, G->hull_b);
   P.kmax = (int32_t)std::ceil(reach / G->step_mm) + 2;
   // Entries of a row: at most one more than the voxel faces its path crosses.
@@ -202,6 +218,7 @@ struct Ctx {
   pct::HistPtrs H;
   pct::Workspace W;
   int64_t M, n;
+  int64_t Mw = 0;           // voxels of the workspace's accumulators (M rounded up to whole bricks)
   hipStream_t s;
   void *ws = nullptr;
   size_t ws_bytes = 0;
@@ -264,14 +281,14 @@ pct_status do_trace(Ctx &c, const pct_grid *g, pct_rows *rows) {
   const bool fill = rows->idx != nullptr;
   int64_t st_rows = std::min<int64_t>(c.n, pct::kStageRows);
   if (fill) {
-    while (st_rows > 1 && pct::workspace_bytes(c.M, c.n, 0, st_rows * c.P.emax, 0, false, c.extra) > c.ws_bytes)
+    while (st_rows > 1 && pct::workspace_bytes(c.Mw, c.n, 0, st_rows * c.P.emax, 0, false, c.extra) > c.ws_bytes)
       st_rows /= 2;
-    const size_t need = pct::workspace_bytes(c.M, c.n, 0, std::max<int64_t>(st_rows, 1) * c.P.emax, 0, false, c.extra);
+    const size_t need = pct::workspace_bytes(c.Mw, c.n, 0, std::max<int64_t>(st_rows, 1) * c.P.emax, 0, false, c.extra);
     if (need > c.ws_bytes)
       return fail(PCT_ENOMEM, "workspace of %zu bytes given, %zu needed to stage rows", c.ws_bytes, need);
   }
   st_rows = std::max<int64_t>(st_rows, 1);
-  c.W = pct::carve_workspace(c.ws, c.M, c.n, 0, fill ? st_rows * c.P.emax : 0, 0, false, c.extra);
+  c.W = pct::carve_workspace(c.ws, c.Mw, c.n, 0, fill ? st_rows * c.P.emax : 0, 0, false, c.extra);
   const float scale = 1.0f / len_unit(g);
   HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
   if (c.n == 0) HIPCHECK(pct::launch_scan_rows(rows->row_ptr, 0, 0, c.W.scan, c.s));
@@ -314,16 +331,16 @@ int64_t fused_count_elems(int64_t M, int64_t n, const pct_sweep_params *p) {
 // it so (keeping the per-block counts when blk > 0 and they fit too).
 bool carve_fused(Ctx &c, int64_t blk) {
   const int x = c.extra;
-  if (blk > 0 && pct::workspace_bytes(c.M, c.n, 0, 0, blk, true, x) <= c.ws_bytes) {
-    c.W = pct::carve_workspace(c.ws, c.M, c.n, 0, 0, blk, true, x);
+  if (blk > 0 && pct::workspace_bytes(c.Mw, c.n, 0, 0, blk, true, x) <= c.ws_bytes) {
+    c.W = pct::carve_workspace(c.ws, c.Mw, c.n, 0, 0, blk, true, x);
     return true;
   }
-  if (pct::workspace_bytes(c.M, c.n, 0, 0, 0, true, x) <= c.ws_bytes) {
-    c.W = pct::carve_workspace(c.ws, c.M, c.n, 0, 0, 0, true, x);
+  if (pct::workspace_bytes(c.Mw, c.n, 0, 0, 0, true, x) <= c.ws_bytes) {
+    c.W = pct::carve_workspace(c.ws, c.Mw, c.n, 0, 0, 0, true, x);
     return true;
   }
-  if (blk > 0 && pct::workspace_bytes(c.M, c.n, 0, 0, blk, false, x) <= c.ws_bytes)
-    c.W = pct::carve_workspace(c.ws, c.M, c.n, 0, 0, blk, false, x);
+  if (blk > 0 && pct::workspace_bytes(c.Mw, c.n, 0, 0, blk, false, x) <= c.ws_bytes)
+    c.W = pct::carve_workspace(c.ws, c.Mw, c.n, 0, 0, blk, false, x);
   return false;
 }
 
@@ -352,46 +369,61 @@ pct_status do_sweep(Ctx &c, const pct_grid *g, const pct_rows *rows, float *x, c
   const bool tv = tvs_on(p);
   if (tv && !c.W.tvs) return fail(PCT_ENOMEM, "workspace carved without the TV superiorization scratch");
   if (p1 < 0) p1 = c.n;
-  HIPCHECK(pct::launch_fill_f32(c.W.num, c.M, 0.f, c.s));
-  HIPCHECK(pct::launch_fill_u32(c.W.cnt, c.M, 0u, c.s));
+  HIPCHECK(pct::launch_fill_f32(c.W.num, c.Mw, 0.f, c.s));
+  HIPCHECK(pct::launch_fill_u32(c.W.cnt, c.Mw, 0u, c.s));
   if (rows || !c.W.blk_cnt || touched) count_mode = 0;
+  // rebuilt rows: voxels numbered in bricks (accumulators and a copy of x
+  // in that order), so that each wavefront's atomics and gathers along a
+  // path touch few cache lines
+  const pct::PathParams Pb = brick_params(c.P);
+  if (!rows) HIPCHECK(pct::launch_to_bricks(Pb, x, c.W.xb, c.Mw, c.s));
+  const int kproj = count_mode == 2 ? PCT_K_PROJECT : PCT_K_PROJECT_COUNTING;
   for (int64_t first = p0, blk = 0; first < p1; first += p->block_size, ++blk) {
     const int64_t count = std::min<int64_t>(p->block_size, p1 - first);
-    if (tv) PROF(PCT_K_TVS, run_tvs(c, g->nx, g->ny, g->nz, x, p->hull_mask, p->tvs));
+    if (tv) {
+      PROF(PCT_K_TVS, run_tvs(c, g->nx, g->ny, g->nz, x, p->hull_mask, p->tvs));
+      if (!rows) HIPCHECK(pct::launch_to_bricks(Pb, x, c.W.xb, c.Mw, c.s));
+    }
     if (rows)
       PROF(PCT_K_PROJECT, pct::launch_project_cached(rows->row_ptr, rows->idx, rows->len, rows->len_dtype, unit,
                                                      rows->norm2, c.H.wepl, p->order, first, count, c.n, c.M, x,
                                                      c.W.num, c.W.cnt, c.W.status, c.s));
     else if (c.recs_ready)
-      PROF(PCT_K_PROJECT, pct::launch_project_fused(c.P, c.W.recs, p->order, first, c.n, true, count, x, c.W.num,
-                                                    count_mode == 2 ? nullptr : c.W.cnt, c.W.status, c.s));
+      PROF(kproj, pct::launch_project_fused(Pb, c.W.recs, p->order, first, c.n, true, count, c.W.xb, c.W.num,
+                                            count_mode == 2 ? nullptr : c.W.cnt, c.W.status, c.s));
     else
       for (int64_t s0 = 0; s0 < count; s0 += c.W.rec_rows) {
         const int64_t cs = std::min<int64_t>(c.W.rec_rows, count - s0);
         PROF(PCT_K_PATH_SETUP, pct::launch_path_setup(c.P, c.H, p->order, first + s0, cs, c.n, c.W.recs,
                                                       c.W.status, false, c.s));
-        PROF(PCT_K_PROJECT, pct::launch_project_fused(c.P, c.W.recs, nullptr, 0, c.n, false, cs, x, c.W.num,
-                                                      count_mode == 2 ? nullptr : c.W.cnt, c.W.status, c.s));
+        PROF(kproj, pct::launch_project_fused(Pb, c.W.recs, nullptr, 0, c.n, false, cs, c.W.xb, c.W.num,
+                                              count_mode == 2 ? nullptr : c.W.cnt, c.W.status, c.s));
       }
-    PROF(PCT_K_APPLY, pct::launch_apply_counts(x, c.W.num, c.W.cnt, count_mode ? c.W.blk_cnt + blk * c.M : nullptr,
-                                               count_mode, p->hull_mask, c.M, p->lambda, c.W.status, c.s, touched));
+    PROF(PCT_K_APPLY, pct::launch_apply_counts(x, c.W.num, c.W.cnt, count_mode ? c.W.blk_cnt + blk * c.Mw : nullptr,
+                                               count_mode, p->hull_mask, c.M, p->lambda, c.W.status, c.s, touched,
+                                               rows ? nullptr : &Pb, c.W.xb, c.Mw));
   }
   return PCT_OK;
 }
 
 pct_status do_residual(Ctx &c, const pct_grid *g, const pct_rows *rows, const float *x, double *out) {
-  if (rows)
+  if (rows) {
     PROF(PCT_K_RESIDUAL, pct::launch_residual_cached(rows->row_ptr, rows->idx, rows->len, rows->len_dtype,
                                                      len_unit(g), c.H.wepl, c.n, c.M, x, c.W.partials, out, c.s));
-  else if (c.recs_ready) {
-    PROF(PCT_K_RESIDUAL, pct::launch_residual_fused(c.P, c.W.recs, c.n, x, c.W.partials, c.W.status, false, c.s));
+    return PCT_OK;
+  }
+  const pct::PathParams Pb = brick_params(c.P);
+  HIPCHECK(pct::launch_to_bricks(Pb, x, c.W.xb, c.Mw, c.s));
+  if (c.recs_ready) {
+    PROF(PCT_K_RESIDUAL, pct::launch_residual_fused(Pb, c.W.recs, c.n, c.W.xb, c.W.partials, c.W.status, false, c.s));
     HIPCHECK(pct::launch_residual_final(c.W.partials, pct::kResidFusedGrid, out, c.s));
   } else {
     for (int64_t i0 = 0; i0 < c.n; i0 += c.W.rec_rows) {
       const int64_t cs = std::min<int64_t>(c.W.rec_rows, c.n - i0);
       PROF(PCT_K_PATH_SETUP, pct::launch_path_setup(c.P, c.H, nullptr, i0, cs, c.n, c.W.recs, c.W.status, false,
                                                     c.s));
-      PROF(PCT_K_RESIDUAL, pct::launch_residual_fused(c.P, c.W.recs, cs, x, c.W.partials, c.W.status, i0 > 0, c.s));
+      PROF(PCT_K_RESIDUAL, pct::launch_residual_fused(Pb, c.W.recs, cs, c.W.xb, c.W.partials, c.W.status, i0 > 0,
+                                                      c.s));
     }
     if (c.n == 0) HIPCHECK(pct::launch_fill_f64(c.W.partials, pct::kResidFusedGrid, 0.0, c.s));
     HIPCHECK(pct::launch_residual_final(c.W.partials, pct::kResidFusedGrid, out, c.s));
@@ -406,11 +438,12 @@ pct_status setup(Ctx &c, const pct_grid *grid, const pct_geom *geom, const pct_h
   if ((r = check_hist(hist)) != PCT_OK) return r;
   if ((r = make_params(grid, geom, c.P)) != PCT_OK) return r;
   c.M = grid_voxels(grid);
+  c.Mw = brick_voxels(grid);
   c.n = hist->n;
   c.extra = extra;
-  if ((r = check_ws(ws, ws_bytes, c.M, c.n, 0, extra)) != PCT_OK) return r;
+  if ((r = check_ws(ws, ws_bytes, c.Mw, c.n, 0, extra)) != PCT_OK) return r;
   c.H = hist_ptrs(hist);
-  c.W = pct::carve_workspace(ws, c.M, c.n, 0, 0, 0, false, extra);
+  c.W = pct::carve_workspace(ws, c.Mw, c.n, 0, 0, 0, false, extra);
   c.ws = ws;
   c.ws_bytes = ws_bytes;
   c.s = reinterpret_cast<hipStream_t>(stream);
@@ -537,9 +570,9 @@ pct_status do_plan_build(Ctx &c, const pct_grid *g, const pct_rows *rows, const 
                          pct_plan *plan, void *ws, size_t ws_bytes) {
   const PlanDims d = plan_dims(g, c.n, params->block_size);
   const int64_t scr = plan_scratch_len(d);
-  pct_status r = check_ws(ws, ws_bytes, c.M, c.n, scr);
+  pct_status r = check_ws(ws, ws_bytes, c.Mw, c.n, scr);
   if (r != PCT_OK) return r;
-  c.W = pct::carve_workspace(ws, c.M, c.n, scr);
+  c.W = pct::carve_workspace(ws, c.Mw, c.n, scr);
   const float unit = len_unit(g);
   pct_plan tmp = *plan;
   tmp.n = d.n;
@@ -693,6 +726,7 @@ size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage
   b += align_up((size_t)M * sizeof(float));
   b += align_up((size_t)M * sizeof(uint32_t));
   b += align_up((size_t)kMaxPartials * sizeof(double));
+  b += align_up((size_t)M * sizeof(float));
   b += extra_bytes(M, extra);
   b += align_up((size_t)((n_hist + kScanChunk - 1) / kScanChunk + 2) * sizeof(int64_t));
   b += align_up((size_t)rec_rows_for(n_hist, recs_all) * kPathRecBytes);
@@ -715,6 +749,8 @@ Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt
   p += align_up((size_t)M * sizeof(uint32_t));
   w.partials = reinterpret_cast<double *>(p);
   p += align_up((size_t)kMaxPartials * sizeof(double));
+  w.xb = reinterpret_cast<float *>(p);
+  p += align_up((size_t)M * sizeof(float));
   w.tvs = nullptr;
   w.carp_xs = w.carp_acc = nullptr;
   w.carp_tc = nullptr;
@@ -762,8 +798,8 @@ size_t pct_workspace_size(const pct_grid *grid, const pct_geom *geom, const pct_
   pct::PathParams P;
   if (geom && !fused && make_params(grid, geom, P) == PCT_OK)
     stage = std::min<int64_t>(n_hist, pct::kStageRows) * P.emax;
-  const int64_t blk = fused ? fused_count_elems(grid_voxels(grid), n_hist, params) : 0;
-  return pct::workspace_bytes(grid_voxels(grid), n_hist, plan_bt, stage, blk, fused != 0,
+  const int64_t blk = fused ? fused_count_elems(brick_voxels(grid), n_hist, params) : 0;
+  return pct::workspace_bytes(brick_voxels(grid), n_hist, plan_bt, stage, blk, fused != 0,
                               tvs_on(params) ? pct::kWsTvs : 0);
 }
 
@@ -774,7 +810,7 @@ size_t pct_carp_workspace_size(const pct_grid *grid, const pct_geom *geom, const
   pct::PathParams P;
   if (geom && !fused && make_params(grid, geom, P) == PCT_OK)
     stage = std::min<int64_t>(n_hist, pct::kStageRows) * P.emax;
-  return pct::workspace_bytes(grid_voxels(grid), n_hist, 0, stage, 0, fused != 0,
+  return pct::workspace_bytes(brick_voxels(grid), n_hist, 0, stage, 0, fused != 0,
                               pct::kWsCarp | (tvs_on(params) ? pct::kWsTvs : 0));
 }
 
@@ -862,6 +898,7 @@ pct_status pct_project_sweep_noalloc(const pct_grid *grid, const pct_geom *geom,
   if ((r = check_hist(hist)) != PCT_OK) return r;
   if ((r = make_params(grid, geom, c.P)) != PCT_OK) return r;
   c.M = grid_voxels(grid);
+  c.Mw = c.M;  // rows only: linear accumulators
   c.n = hist->n;
   if (c.M > kNoAllocMaxVoxels)
     return fail(PCT_EINVAL, "grid of %lld voxels exceeds the no-allocation scratch (at most %lld voxels)",
@@ -902,6 +939,7 @@ pct_status pct_plan_build(const pct_grid *grid, const pct_histories *hist, const
   if ((r = check_plan_params(params, hist->n)) != PCT_OK) return r;
   if (!plan) return fail(PCT_EINVAL, "plan is NULL");
   c.M = grid_voxels(grid);
+  c.Mw = brick_voxels(grid);
   c.n = hist->n;
   c.H = hist_ptrs(hist);
   c.s = reinterpret_cast<hipStream_t>(stream);
@@ -920,10 +958,11 @@ pct_status pct_plan_sweep(const pct_grid *grid, const pct_plan *plan, float *x, 
   if (!x) return fail(PCT_EINVAL, "x is NULL");
   Ctx c;
   c.M = grid_voxels(grid);
+  c.Mw = brick_voxels(grid);
   c.n = plan->n;
   c.extra = tvs_on(params) ? pct::kWsTvs : 0;
-  if ((r = check_ws(workspace, ws_bytes, c.M, c.n, 0, c.extra)) != PCT_OK) return r;
-  c.W = pct::carve_workspace(workspace, c.M, c.n, 0, 0, 0, false, c.extra);
+  if ((r = check_ws(workspace, ws_bytes, c.Mw, c.n, 0, c.extra)) != PCT_OK) return r;
+  c.W = pct::carve_workspace(workspace, c.Mw, c.n, 0, 0, 0, false, c.extra);
   c.s = reinterpret_cast<hipStream_t>(stream);
   const pct::PlanView V = plan_view(plan, len_unit(grid));
   HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
@@ -944,6 +983,7 @@ pct_status pct_plan_residual(const pct_grid *grid, const pct_plan *plan, const f
   if (!x || !out) return fail(PCT_EINVAL, "x / out is NULL");
   Ctx c;
   c.M = grid_voxels(grid);
+  c.Mw = brick_voxels(grid);
   c.n = plan->n;
   (void)workspace;
   (void)ws_bytes;
@@ -972,7 +1012,7 @@ pct_status pct_reconstruct(const pct_grid *grid, const pct_geom *geom, const pct
     trace_st = do_trace(c, grid, rows);
     if (trace_st != PCT_OK && trace_st != PCT_ENONFINITE) return trace_st;
   } else {
-    const int64_t blk = fused_count_elems(c.M, c.n, params);
+    const int64_t blk = fused_count_elems(c.Mw, c.n, params);
     const bool all = params->algo == 1 && carve_fused(c, blk);
     if (c.W.blk_cnt) count_mode = 1;
     HIPCHECK(pct::launch_fill_u32(c.W.status, 4, 0u, c.s));
@@ -1160,6 +1200,8 @@ pct_status pct_probe(int32_t kind, void *buf, size_t buf_bytes, int64_t region, 
   if (kind != PCT_PROBE_LDS_ATOMIC && (region < 64 || region > 0x7fffffffLL))
     return fail(PCT_EINVAL, "region must be 64..2^31-1 elements");
   if (kind == PCT_PROBE_COPY && region % 4 != 0) return fail(PCT_EINVAL, "copy region must be a multiple of 4");
+  if ((kind == PCT_PROBE_GATHER || kind == PCT_PROBE_ATOMIC || kind == PCT_PROBE_ATOMIC_XCD) && region % 160000 != 0)
+    return fail(PCT_EINVAL, "gather and atomic regions must be whole 200 x 200 x 4 slabs (multiples of 160000)");
   if (kind != PCT_PROBE_COPY && (n_ops < 64 * pct::kProbeGrid || n_ops > (int64_t)1 << 40))
     return fail(PCT_EINVAL, "n_ops must be %lld..2^40", (long long)(64 * pct::kProbeGrid));
   const size_t need = pct::probe_bytes(kind, region, n_ops, pct::kProbeGrid);

@@ -330,6 +330,12 @@ __device__ __forceinline__ void mlp_point(const PathParams &P, const R *cF, cons
   v = pp.v0 + pp.sv0 * d1 + (G0 * pp.dvt + G1 * pp.dvs);
 }
 
+// index of voxel (ix, iy, iz) in the rows' numbering (P.brick)
+__device__ __forceinline__ int voxel_id(const PathParams &P, int ix, int iy, int iz) {
+  if (!P.brick) return (iz * P.ny + iy) * P.nx + ix;
+  return ((((iz >> 2) * P.nby + (iy >> 2)) * P.nbx + (ix >> 2)) << 6) | ((iz & 3) << 4) | ((iy & 3) << 2) | (ix & 3);
+}
+
 // Voxel walk of one segment given in local coordinates: (px,py,pz) in [0,1]^3
 // relative to voxel (bx,by,bz), end point (qx,qy,qz) in the same frame,
 // physical length seg.  Emits up to kMaxPieces (voxel, length) pieces;
@@ -360,7 +366,7 @@ __device__ __forceinline__ int walk_segment(const PathParams &P, int bx, int by,
     const W l = (tn - tc) * seg;
     if (l > eps && ix >= 0 && iy >= 0 && iz >= 0 && ix < P.nx && iy < P.ny && iz < P.nz) {
       if (np == kMaxPieces) return kMaxPieces + 1;
-      const int j = (iz * P.ny + iy) * P.nx + ix;
+      const int j = voxel_id(P, ix, iy, iz);
 #pragma unroll
       for (int q = 0; q < kMaxPieces; ++q)
         if (q == np) { vox[q] = j; len[q] = (float)l; }

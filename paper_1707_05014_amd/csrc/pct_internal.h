@@ -45,6 +45,10 @@ struct PathParams {
   float dx, dy, dz;
   double idx, idy, idz, ox, oy, oz;
   float eps_len;      // pieces shorter than this (mm) are dropped
+  // voxel numbering of the rows: 0 = linear (k ny + j) nx + i; 1 = in 4 x 4 x 4
+  // bricks (brick (bi, bj, bk) of nbx x nby x ... bricks, then (k, j, i) in
+  // it), so that the voxels a path crosses share cache lines
+  int32_t brick, nbx, nby;
   // bounds
   int32_t kmax;       // max path segments
   int32_t emax;       // max row entries held in LDS per wavefront
@@ -62,6 +66,7 @@ struct Workspace {
   float *num;            // [M]
   uint32_t *cnt;         // [M]
   double *partials;      // [kMaxPartials]
+  float *xb;             // [M] the image in brick order (rebuilt-row sweeps)
   int64_t *scan;         // [scan_len]
   int32_t *st_idx;       // [stage_slots] staged row entries of one chunk of rows (trace)
   float *st_len;         // [stage_slots]
@@ -175,6 +180,8 @@ hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
 
 hipError_t launch_mask(float *x, const uint8_t *mask, int64_t M, hipStream_t s);
+// xb = x in brick order (zero in the padding of partial bricks)
+hipError_t launch_to_bricks(const PathParams &P, const float *x, float *xb, int64_t Mb, hipStream_t s);
 hipError_t launch_project_cached(const int64_t *row_ptr, const int32_t *idx, const void *len, int32_t len_dtype,
                                  float len_unit, const double *norm2, const float *b, const int64_t *order,
                                  int64_t first, int64_t count, int64_t n, int64_t M, const float *x, float *num,
@@ -186,9 +193,12 @@ hipError_t launch_project_fused(const PathParams &P, const void *recs, const int
                                 bool global, int64_t count, const float *x, float *num, uint32_t *cnt,
                                 uint32_t *status, hipStream_t s);
 // mode 0: counts from cnt (cleared); 1: also store them as uint16 into blk_cnt;
-// 2: counts read from blk_cnt (cnt unused)
+// 2: counts read from blk_cnt (cnt unused).  Bp (or NULL): num, cnt and
+// blk_cnt are in brick order over Mb voxels, and xb (x in brick order) is
+// kept equal to x
 hipError_t launch_apply_counts(float *x, float *num, uint32_t *cnt, uint16_t *blk_cnt, int mode, const uint8_t *mask,
-                               int64_t M, float lambda, uint32_t *status, hipStream_t s, uint8_t *touched = nullptr);
+                               int64_t M, float lambda, uint32_t *status, hipStream_t s, uint8_t *touched = nullptr,
+                               const PathParams *Bp = nullptr, float *xb = nullptr, int64_t Mb = 0);
 // CARP: xs into the per-voxel sums of the strings touching it (touched
 // cleared), then x = mean where some string touched (acc, tc cleared)
 hipError_t launch_carp_accumulate(const float *xs, uint8_t *touched, float *acc, uint16_t *tc, int64_t M,

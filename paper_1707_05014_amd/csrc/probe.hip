@@ -4,16 +4,18 @@
 // last-level-cache bandwidth or for the atomic rate of an MI355X).
 //
 //   copy          plain device copy: HBM bandwidth
-//   gather        4-byte reads at hashed positions inside a region (a
-//                 region that fits the last-level cache gives its gather
-//                 bandwidth; the sweeps gather x this way)
-//   atomic        FP32 atomic adds along path-like voxel runs (one row of 64
-//                 consecutive voxels of a random line per wavefront pass)
-//                 into one image of `region` voxels: the global atomic rate
+//   gather        4-byte reads along path-like voxel runs (64 voxels of a
+//                 line per wavefront pass, in brick order) of an image of
+//                 `region` voxels: one that fits the last-level cache gives
+//                 its gather rate, the way the rebuilt-row sweeps read x
+//   atomic        FP32 atomic adds along the same runs into the image: the
+//                 global atomic rate of the rebuilt-row sweeps' scatter
 //   atomic_xcd    the same adds into a private copy of the image per
 //                 accelerator complex die (XCD), the copy chosen by the
 //                 die's hardware id, with workgroup-scope atomics
-//   lds_atomic    the same adds into a 16384-float LDS image per workgroup
+//   lds_atomic    FP32 atomic adds at hashed positions of a 2048-float LDS
+//                 image per workgroup (a tile's numerators, entries in no
+//                 particular order)
 #include <hip/hip_runtime.h>
 
 #include "pct_internal.h"
@@ -23,7 +25,7 @@ namespace pct {
 namespace {
 
 constexpr int kProbeBlock = 256;
-constexpr int kLdsImage = 16384;
+constexpr int kLdsImage = 2048;
 
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
@@ -34,33 +36,49 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   return x;
 }
 
-// index of lane `lane` in path-like row r of an image of `region` voxels:
-// start voxel and stride (1, 200, 201, 40000 or 40201: along x, y, a diagonal,
-// z or a space diagonal of a 200 x 200 x ... grid) from a hash of r
+// Path-like rows: row r is a straight line in the z plane of a grid of 200 x
+// 200 x (region / 40000) voxels, at a hashed angle, start and slice; lane l
+// takes the voxel at distance l (voxel units) along it (wrapped into the
+// grid), numbered in 4 x 4 x 4 bricks as the rebuilt-row sweeps number
+// theirs (50 x 50 x ... bricks).
 __device__ __forceinline__ int64_t path_index(uint64_t r, int lane, int64_t region) {
+  const int nz = (int)(region / 40000);
   const uint32_t h = mix32((uint32_t)r ^ 0x9e3779b9U * (uint32_t)(r >> 32));
-  const uint32_t sel = mix32(h + 1u) % 5u;
-  const int64_t stride = sel == 0 ? 1 : (sel == 1 ? 200 : (sel == 2 ? 201 : (sel == 3 ? 40000 : 40201)));
-  const int64_t start = (int64_t)(h % (uint32_t)region);
-  return (start + stride * lane) % region;
+  const float phi = (float)(mix32(h + 1u) & 0xffffu) * (6.2831853f / 65536.0f);
+  const float x0 = (float)(h % 200u), y0 = (float)((h >> 8) % 200u);
+  const int iz = (int)(mix32(h + 2u) % (uint32_t)nz);
+  int ix = (int)floorf(x0 + lane * cosf(phi)), iy = (int)floorf(y0 + lane * sinf(phi));
+  ix = ((ix % 200) + 200) % 200;
+  iy = ((iy % 200) + 200) % 200;
+  return ((((int64_t)(iz >> 2) * 50 + (iy >> 2)) * 50 + (ix >> 2)) << 6) | ((iz & 3) << 4) | ((iy & 3) << 2) | (ix & 3);
 }
 
-__global__ void __launch_bounds__(kProbeBlock) k_probe_copy(const float4 *__restrict__ a, float4 *__restrict__ b,
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// four 16-byte loads in flight per thread before their stores
+__global__ void __launch_bounds__(kProbeBlock) k_probe_copy(const v4f *__restrict__ a, v4f *__restrict__ b,
                                                             int64_t n4) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) b[i] = a[i];
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n4; i += 4 * stride) {
+    const v4f v0 = __builtin_nontemporal_load(a + i), v1 = __builtin_nontemporal_load(a + i + stride);
+    const v4f v2 = __builtin_nontemporal_load(a + i + 2 * stride), v3 = __builtin_nontemporal_load(a + i + 3 * stride);
+    __builtin_nontemporal_store(v0, b + i);
+    __builtin_nontemporal_store(v1, b + i + stride);
+    __builtin_nontemporal_store(v2, b + i + 2 * stride);
+    __builtin_nontemporal_store(v3, b + i + 3 * stride);
+  }
+  for (; i < n4; i += stride) b[i] = a[i];
 }
 
 __global__ void __launch_bounds__(kProbeBlock) k_probe_gather(const float *__restrict__ src, int64_t region,
-                                                              int64_t per_thread, float *__restrict__ out) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+                                                              int64_t rows, float *__restrict__ out) {
+  const int lane = __lane_id();
+  const int64_t nw = (int64_t)gridDim.x * (kProbeBlock / 64);
   float acc = 0.f;
-  uint32_t h = mix32(t * 2654435761U + 12345U);
-  for (int64_t k = 0; k < per_thread; ++k) {
-    h = h * 1664525U + 1013904223U;
-    acc += src[(int64_t)(mix32(h) % (uint32_t)region)];
-  }
-  out[t] = acc;
+  for (int64_t r = (int64_t)blockIdx.x * (kProbeBlock / 64) + threadIdx.x / 64; r < rows; r += nw)
+    acc += src[path_index((uint64_t)r, lane, region)];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = acc;
 }
 
 template <int KIND>  // 0: one image, agent-scope adds; 1: per-die image, workgroup-scope adds
@@ -88,7 +106,7 @@ __global__ void __launch_bounds__(kProbeBlock) k_probe_lds_atomic(int64_t rows_p
   const int lane = __lane_id();
   const int w = threadIdx.x / 64;
   for (int64_t r = w; r < rows_per_block; r += kProbeBlock / 64) {
-    const int64_t j = path_index((uint64_t)r * 977u + blockIdx.x, lane, kLdsImage);
+    const uint32_t j = mix32((uint32_t)(r * 64 + lane) * 2654435761U + blockIdx.x) & (kLdsImage - 1);
     atomicAdd(&img[j], 1.0f);
   }
   __syncthreads();
@@ -117,16 +135,14 @@ hipError_t launch_probe(int kind, void *buf, int64_t region, int64_t n_ops, int6
   switch (kind) {
     case 0: {
       const int64_t n4 = region / 4;  // region floats per half, copied as float4
-      hipLaunchKernelGGL(k_probe_copy, g, b, 0, s, static_cast<const float4 *>(buf),
-                         reinterpret_cast<float4 *>(static_cast<float *>(buf) + region), n4);
+      hipLaunchKernelGGL(k_probe_copy, g, b, 0, s, static_cast<const v4f *>(buf),
+                         reinterpret_cast<v4f *>(static_cast<float *>(buf) + region), n4);
       break;
     }
-    case 1: {
-      const int64_t per = (n_ops + grid * kProbeBlock - 1) / (grid * kProbeBlock);
-      hipLaunchKernelGGL(k_probe_gather, g, b, 0, s, static_cast<const float *>(buf), region, per,
+    case 1:
+      hipLaunchKernelGGL(k_probe_gather, g, b, 0, s, static_cast<const float *>(buf), region, n_ops / 64,
                          static_cast<float *>(buf) + region);
       break;
-    }
     case 2:
       hipLaunchKernelGGL(k_probe_atomic<0>, g, b, 0, s, static_cast<float *>(buf), region, n_ops / 64);
       break;

@@ -112,50 +112,66 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k
   }
 }
 
+// Block update x_j += lambda num_j / s_j for s_j > 0 (hull mask: x_j = 0
+// outside), num_j cleared.  MODE 0: s_j from cnt (cleared); 1: also stored
+// as uint16 into blk_cnt; 2: s_j read from blk_cnt (cnt untouched).
+// BRICK: the accumulators and blk_cnt are in brick order (position q of Mb),
+// x and the mask linear, and xb (x in brick order) is updated with x.
 // touched (or NULL): set to 1 for every voxel the block's rows touch (CARP's
-// component averaging counts the strings that touch a voxel)
+// component averaging counts the strings that touch a voxel).
+template <int MODE, bool BRICK>
 __global__ void __launch_bounds__(256) k_apply(float *__restrict__ x, float *__restrict__ num,
-                                               uint32_t *__restrict__ cnt, const uint8_t *__restrict__ mask,
-                                               int64_t M, float lambda, uint8_t *__restrict__ touched) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < M; j += stride) {
-    const uint32_t c = cnt[j];
-    if (c) {
-      if (touched) touched[j] = 1;
-      const float v = x[j] + lambda * num[j] / (float)c;
-      x[j] = (mask && !mask[j]) ? 0.0f : v;
-      num[j] = 0.0f;
-      cnt[j] = 0u;
-    }
-  }
-}
-
-// k_apply with the block's counts stored (MODE 1: from cnt into blk_cnt, all
-// M voxels written) or read back (MODE 2: from blk_cnt, cnt untouched)
-template <int MODE>
-__global__ void __launch_bounds__(256) k_apply_counts(float *__restrict__ x, float *__restrict__ num,
-                                                      uint32_t *__restrict__ cnt, uint16_t *__restrict__ blk_cnt,
-                                                      const uint8_t *__restrict__ mask, int64_t M, float lambda,
-                                                      uint32_t *status) {
+                                               uint32_t *__restrict__ cnt, uint16_t *__restrict__ blk_cnt,
+                                               const uint8_t *__restrict__ mask, int64_t M, float lambda,
+                                               uint32_t *status, uint8_t *__restrict__ touched, int32_t nx,
+                                               int32_t ny, int32_t nz, int32_t nbx, int32_t nby,
+                                               float *__restrict__ xb, int64_t Mq) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   bool sat = false;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < M; j += stride) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < Mq; q += stride) {
+    int64_t j = q;
+    if constexpr (BRICK) {
+      const int64_t br = q >> 6;
+      const int w = (int)(q & 63);
+      const int ix = (int)(br % nbx) * 4 + (w & 3);
+      const int iy = (int)((br / nbx) % nby) * 4 + ((w >> 2) & 3);
+      const int iz = (int)(br / ((int64_t)nbx * nby)) * 4 + (w >> 4);
+      if (ix >= nx || iy >= ny || iz >= nz) continue;
+      j = ((int64_t)iz * ny + iy) * nx + ix;
+    }
     uint32_t c;
-    if constexpr (MODE == 1) {
-      c = cnt[j];
-      sat |= c > 0xffffu;
-      blk_cnt[j] = (uint16_t)(c > 0xffffu ? 0xffffu : c);
+    if constexpr (MODE == 2) {
+      c = blk_cnt[q];
     } else {
-      c = blk_cnt[j];
+      c = cnt[q];
+      if constexpr (MODE == 1) {
+        sat |= c > 0xffffu;
+        blk_cnt[q] = (uint16_t)(c > 0xffffu ? 0xffffu : c);
+      }
     }
     if (c) {
-      const float v = x[j] + lambda * num[j] / (float)c;
-      x[j] = (mask && !mask[j]) ? 0.0f : v;
-      num[j] = 0.0f;
-      if constexpr (MODE == 1) cnt[j] = 0u;
+      if (touched) touched[j] = 1;
+      const float v = (mask && !mask[j]) ? 0.0f : x[j] + lambda * num[q] / (float)c;
+      x[j] = v;
+      if constexpr (BRICK) xb[q] = v;
+      num[q] = 0.0f;
+      if constexpr (MODE != 2) cnt[q] = 0u;
     }
   }
   if (MODE == 1 && __ballot(sat) && wave_lane() == 0) atomicOr(status, kStCountSat);
+}
+
+__global__ void __launch_bounds__(256) k_to_bricks(const float *__restrict__ x, float *__restrict__ xb, int32_t nx,
+                                                   int32_t ny, int32_t nz, int32_t nbx, int32_t nby, int64_t Mb) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < Mb; q += stride) {
+    const int64_t br = q >> 6;
+    const int w = (int)(q & 63);
+    const int ix = (int)(br % nbx) * 4 + (w & 3);
+    const int iy = (int)((br / nbx) % nby) * 4 + ((w >> 2) & 3);
+    const int iz = (int)(br / ((int64_t)nbx * nby)) * 4 + (w >> 4);
+    xb[q] = (ix < nx && iy < ny && iz < nz) ? x[((int64_t)iz * ny + iy) * nx + ix] : 0.0f;
+  }
 }
 
 // CARP (Sec. 2.2): string image xs into the component sums over the strings
@@ -405,14 +421,32 @@ hipError_t launch_project_fused(const PathParams &P, const void *recs, const int
 }
 
 hipError_t launch_apply_counts(float *x, float *num, uint32_t *cnt, uint16_t *blk_cnt, int mode, const uint8_t *mask,
-                               int64_t M, float lambda, uint32_t *status, hipStream_t s, uint8_t *touched) {
-  const dim3 g(grid_for(M, 256, 8192)), b(256);
-  if (mode == 0)
-    hipLaunchKernelGGL(k_apply, g, b, 0, s, x, num, cnt, mask, M, lambda, touched);
-  else if (mode == 1)
-    hipLaunchKernelGGL(k_apply_counts<1>, g, b, 0, s, x, num, cnt, blk_cnt, mask, M, lambda, status);
-  else
-    hipLaunchKernelGGL(k_apply_counts<2>, g, b, 0, s, x, num, cnt, blk_cnt, mask, M, lambda, status);
+                               int64_t M, float lambda, uint32_t *status, hipStream_t s, uint8_t *touched,
+                               const PathParams *Bp, float *xb, int64_t Mb) {
+  const int64_t Mq = Bp ? Mb : M;
+  const dim3 g(grid_for(Mq, 256, 8192)), b(256);
+  const int32_t nx = Bp ? Bp->nx : 0, ny = Bp ? Bp->ny : 0, nz = Bp ? Bp->nz : 0;
+  const int32_t nbx = Bp ? Bp->nbx : 1, nby = Bp ? Bp->nby : 1;
+#define PCT_APPLY(MODE, BRICK)                                                                                     \
+  hipLaunchKernelGGL((k_apply<MODE, BRICK>), g, b, 0, s, x, num, cnt, blk_cnt, mask, M, lambda, status, touched, nx, \
+                     ny, nz, nbx, nby, xb, Mq)
+  if (Bp) {
+    if (mode == 0) PCT_APPLY(0, true);
+    else if (mode == 1) PCT_APPLY(1, true);
+    else PCT_APPLY(2, true);
+  } else {
+    if (mode == 0) PCT_APPLY(0, false);
+    else if (mode == 1) PCT_APPLY(1, false);
+    else PCT_APPLY(2, false);
+  }
+#undef PCT_APPLY
+  return hipGetLastError();
+}
+
+hipError_t launch_to_bricks(const PathParams &P, const float *x, float *xb, int64_t Mb, hipStream_t s) {
+  if (Mb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_bricks, dim3(grid_for(Mb, 256, 8192)), dim3(256), 0, s, x, xb, P.nx, P.ny, P.nz, P.nbx,
+                     P.nby, Mb);
   return hipGetLastError();
 }
 

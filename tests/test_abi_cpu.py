@@ -208,9 +208,10 @@ def test_probe_args_rejected_on_host():
     assert lib.pct_probe(9, buf, 1 << 30, 1024, 1 << 20, 1, ctypes.byref(ms), None) == E
     assert lib.pct_probe(K["copy"], buf, 1 << 30, 1022, 0, 1, ctypes.byref(ms), None) == E   # not a multiple of 4
     assert lib.pct_probe(K["atomic"], buf, 1 << 30, 32, 1 << 20, 1, ctypes.byref(ms), None) == E  # region < 64
-    assert lib.pct_probe(K["atomic"], buf, 1 << 30, 1024, 100, 1, ctypes.byref(ms), None) == E  # too few ops
-    assert lib.pct_probe(K["gather"], buf, 1 << 30, 1024, 1 << 20, 0, ctypes.byref(ms), None) == E  # reps
-    assert lib.pct_probe(K["gather"], buf, 1 << 30, 1024, 1 << 20, 1, None, None) == E
+    assert lib.pct_probe(K["atomic"], buf, 1 << 30, 100_000, 1 << 20, 1, ctypes.byref(ms), None) == E  # not slabs
+    assert lib.pct_probe(K["atomic"], buf, 1 << 30, 160_000, 100, 1, ctypes.byref(ms), None) == E  # too few ops
+    assert lib.pct_probe(K["gather"], buf, 1 << 30, 160_000, 1 << 20, 0, ctypes.byref(ms), None) == E  # reps
+    assert lib.pct_probe(K["gather"], buf, 1 << 30, 160_000, 1 << 20, 1, None, None) == E
     need = lib.pct_probe_bytes(K["atomic_xcd"], 1_600_000, 1 << 26)
     assert need == 8 * 4 * 1_600_000
     assert lib.pct_probe(K["atomic_xcd"], buf, need - 1, 1_600_000, 1 << 26, 1, ctypes.byref(ms), None) == \
