@@ -1,14 +1,22 @@
-"""Learned warm start, end to end on the GPU: the network is trained by the
-library's own forward and backward kernels on pairs that the solver makes
-from seeded phantoms, then used as x0 on held-out phantoms.
+"""Learned warm start, end to end on the GPU: networks trained by the
+library's own forward and backward kernels on pairs made from seeded
+phantoms, then used as x0 on held-out phantoms, where the plain sweeps
+continue from them and judge them.
 
-What it gains over the plain method, checked here at a reduced size (2e6
-histories per phantom in blocks of 4e4, so that a sweep still has the 50
-blocks of the 1e7-history workload; 4 training phantoms, 600 Adam steps):
-* its output is much closer to the phantom than the image it starts from
-  (relative L2 inside the hull below 0.6 times that of the 2-sweep image);
-* the ROI-mean RSP error (the paper's figure of merit) drops too;
-* the sweeps needed to reach <= 1% RSP error are printed for both starts.
+Two training targets for the image after 2 sweeps from the hull start:
+the solver's own image after 20 sweeps, and the phantom itself (the limit
+of the sweeps on a noise-free, model-exact scan; the default, since the
+20-sweep image carries the data's noise, which the network cannot predict).
+At a reduced size (2e6 histories per phantom in blocks of 4e4, so that a
+sweep still has the 50 blocks of the 1e7-history workload; 4 training
+phantoms, 600 Adam steps per network):
+* each network's output is closer to its own kind of target on the held-out
+  phantoms than the 2-sweep image it starts from, and lowers the ROI-mean
+  RSP error (the paper's figure of merit);
+* with the default network, the sweeps needed to reach <= 1% RSP error
+  (its 2 input sweeps included) summed over the held-out phantoms are no
+  more than from the hull start; the solver-target network's count is
+  printed beside it.
 """
 import sys
 
@@ -27,6 +35,7 @@ BLOCK = 40_000
 TRAIN_SEEDS = (1000, 1001, 1002, 1003)
 EVAL_SEEDS = (3, 2)
 IN_SWEEPS = 2
+OUT_SWEEPS = 20
 STEPS = 600
 
 
@@ -61,7 +70,7 @@ def _rel_l2(x, truth, inside):
     return float(torch.linalg.vector_norm((x - truth)[inside]) / torch.linalg.vector_norm(truth[inside]))
 
 
-def _sweeps_to_1pct(grid, plan, params, x, labels, true_rsp, max_sweeps=12):
+def _sweeps_to_1pct(grid, plan, params, x, labels, true_rsp, max_sweeps=30):
     for s in range(1, max_sweeps + 1):
         api.plan_sweep(grid, plan, x, params)
         if _rsp_err(x, labels, true_rsp) <= 0.01:
@@ -70,23 +79,29 @@ def _sweeps_to_1pct(grid, plan, params, x, labels, true_rsp, max_sweeps=12):
 
 
 def test_warm_start_gain():
-    pairs = []
+    train = []
     for seed in TRAIN_SEEDS:
         _say(f"training phantom {seed}: {N} histories")
         cfg = synth.training_config(seed, N, block=BLOCK)
         grid, plan, params, mask = _setup(cfg)
         x = mask.to(torch.float32)
-        snaps = wsm.sweep_snapshots(grid, plan, x, params, [IN_SWEEPS])
+        snaps = wsm.sweep_snapshots(grid, plan, x, params, [IN_SWEEPS, OUT_SWEEPS])
         truth = torch.from_numpy(synth.truth_image(cfg)).cuda()
-        pairs.append((wsm.net_input(snaps, (IN_SWEEPS,), grid), wsm.volume(truth, grid)))
+        train.append((wsm.net_input(snaps, (IN_SWEEPS,), grid), wsm.volume(snaps[OUT_SWEEPS], grid),
+                      wsm.volume(truth, grid)))
         del plan
-    net = cnn.UNet3D((16, 32, 64, 64), seed=7)
-    losses, train_s = wsm.train(net, pairs, STEPS, 1e-3, seed=11)
-    _say(f"trained {STEPS} steps in {train_s:.1f} s: loss {np.mean(losses[:4]):.3e} -> {np.mean(losses[-4:]):.3e}")
-    assert np.mean(losses[-4:]) < 0.5 * np.mean(losses[:4])
-    del pairs
+    nets = {}
+    for target in ("truth", "out"):
+        net = cnn.UNet3D((16, 32, 64, 64), seed=7)
+        pairs = [(a, b if target == "out" else c) for a, b, c in train]
+        losses, train_s = wsm.train(net, pairs, STEPS, 1e-3, seed=11)
+        _say(f"target {target}: trained {STEPS} steps in {train_s:.1f} s: loss {np.mean(losses[:4]):.3e} -> "
+             f"{np.mean(losses[-4:]):.3e}")
+        assert np.mean(losses[-4:]) < 0.5 * np.mean(losses[:4])
+        nets[target] = net
+    del train
 
-    hull_sweeps, warm_sweeps = [], []
+    sweeps = {"hull": [], "truth": [], "out": []}
     for seed in EVAL_SEEDS:
         cfg = synth.config(5, n=N) if seed == 3 else synth.training_config(seed, N)
         cfg.block = BLOCK
@@ -97,19 +112,25 @@ def test_warm_start_gain():
         truth = torch.from_numpy(synth.truth_image(cfg)).cuda()
         inside = mask.bool()
         x = mask.to(torch.float32)
-        snaps = wsm.sweep_snapshots(grid, plan, x, params, [IN_SWEEPS])
-        x_in = snaps[IN_SWEEPS]
-        x0 = wsm.warm_start(net, wsm.net_input(snaps, (IN_SWEEPS,), grid), mask)
-        l2_in, l2_net = _rel_l2(x_in, truth, inside), _rel_l2(x0, truth, inside)
-        e_in, e_net = _rsp_err(x_in, labels, true_rsp), _rsp_err(x0, labels, true_rsp)
-        # outside the hull the warm start is zero, like the sweeps' image
-        assert float(x0[~inside].abs().max()) == 0.0
+        snaps = wsm.sweep_snapshots(grid, plan, x, params, [IN_SWEEPS, OUT_SWEEPS])
+        x_in, x_out = snaps[IN_SWEEPS], snaps[OUT_SWEEPS]
+        e_in = _rsp_err(x_in, labels, true_rsp)
         h = _sweeps_to_1pct(grid, plan, params, x_in.clone(), labels, true_rsp)
-        w = 0 if e_net <= 0.01 else _sweeps_to_1pct(grid, plan, params, x0.clone(), labels, true_rsp)
-        hull_sweeps.append(None if h is None else IN_SWEEPS + h)
-        warm_sweeps.append(None if w is None else IN_SWEEPS + w)
-        _say(f"  2-sweep image: rel L2 {l2_in:.4f}, RSP error {e_in:.4f}; network output: rel L2 {l2_net:.4f}, "
-             f"RSP error {e_net:.4f}; sweeps to <= 1%: hull start {hull_sweeps[-1]}, warm start {warm_sweeps[-1]}")
-        assert l2_net < 0.6 * l2_in
-        assert e_net < e_in
+        sweeps["hull"].append(None if h is None else IN_SWEEPS + h)
+        for target, net in nets.items():
+            x0 = wsm.warm_start(net, wsm.net_input(snaps, (IN_SWEEPS,), grid), mask)
+            # outside the hull the warm start is zero, like the sweeps' image
+            assert float(x0[~inside].abs().max()) == 0.0
+            ref = truth if target == "truth" else x_out
+            l2_in, l2_net = _rel_l2(x_in, ref, inside), _rel_l2(x0, ref, inside)
+            e_net = _rsp_err(x0, labels, true_rsp)
+            w = 0 if e_net <= 0.01 else _sweeps_to_1pct(grid, plan, params, x0.clone(), labels, true_rsp)
+            sweeps[target].append(None if w is None else IN_SWEEPS + w)
+            _say(f"  target {target}: rel L2 to it {l2_in:.4f} -> {l2_net:.4f}; RSP error {e_in:.4f} -> {e_net:.4f}; "
+                 f"sweeps to <= 1%: hull start {sweeps['hull'][-1]}, warm start {sweeps[target][-1]}")
+            assert l2_net < l2_in
+            assert e_net < e_in
         del plan
+    _say(f"sweeps to <= 1% RSP error: {sweeps}")
+    assert None not in sweeps["hull"] and None not in sweeps["truth"]
+    assert sum(sweeps["truth"]) <= sum(sweeps["hull"])
