@@ -22,23 +22,6 @@ path-arithmetic, cache-gather and atomic times against measured peaks of
 the same access patterns), the FP64 residual of the final image, the time to
 reach <= 1% RSP error in the insert ROIs, and the FP64 CPU oracle timed on a
 bounded sample of the same workload on this job's host threads.
-"""Throughput benchmark of the pCT reconstruction hot path on one MI355X.
-
-Workload (default): 1e7 seeded synthetic proton histories through a
-200 x 200 x 40 grid of 1 mm voxels (elliptic head phantom with 8 inserts),
-180 gantry angles, 6 DROP sweeps in blocks of 2e5 histories, rows cached in
-HBM as int32 voxel index + float32 length.
-
-One step = one whole reconstruction through the C ABI (pct_reconstruct):
-most-likely path + voxel walk for every history (count and fill passes),
-6 block-iterative sweeps (projection, scatter, block update), and the FP64
-residual ||Ax - b|| after every sweep.  value = histories x sweeps / step
-time (histories per second per sweep), inputs resident in HBM.
-
-Also reported: per-kernel device times (HIP events on the launching stream),
-the roofline of the dominant kernel, the number of sweeps and the time to
-reach <= 1% RSP error in the insert ROIs, and the FP64 CPU oracle timed on
-a bounded sample of the same workload.
 """
 from __future__ import annotations
 
