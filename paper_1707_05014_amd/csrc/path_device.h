@@ -359,26 +359,39 @@ __device__ __forceinline__ int walk_segment(const PathParams &P, int bx, int by,
   W tc = (W)0;
   int np = 0;
   const W eps = (W)P.eps_len;
+  // Straight-line body (selects, no branches inside): a lane that has
+  // reached the segment's end keeps its state and emits nothing; the loop
+  // ends when every lane has.
+  bool done = false, over = false;
   for (int it = 0; it < 3 * kMaxPieces; ++it) {
     W tn = tx < ty ? tx : ty;
     tn = tn < tz ? tn : tz;
     tn = tn < (W)1 ? tn : (W)1;
     const W l = (tn - tc) * seg;
-    if (l > eps && ix >= 0 && iy >= 0 && iz >= 0 && ix < P.nx && iy < P.ny && iz < P.nz) {
-      if (np == kMaxPieces) return kMaxPieces + 1;
-      const int j = voxel_id(P, ix, iy, iz);
+    const bool keep = !done && l > eps && ix >= 0 && iy >= 0 && iz >= 0 && ix < P.nx && iy < P.ny && iz < P.nz;
+    over = over || (keep && np == kMaxPieces);
+    const int j = voxel_id(P, ix, iy, iz);
 #pragma unroll
-      for (int q = 0; q < kMaxPieces; ++q)
-        if (q == np) { vox[q] = j; len[q] = (float)l; }
-      ++np;
+    for (int q = 0; q < kMaxPieces; ++q) {
+      const bool w = keep && q == np;
+      vox[q] = w ? j : vox[q];
+      len[q] = w ? (float)l : len[q];
     }
-    if (tn >= (W)1) return np;
-    tc = tn;
-    if (tx <= ty && tx <= tz) { ix += sx; tx += ddx; }
-    else if (ty <= tz) { iy += sy; ty += ddy; }
-    else { iz += sz; tz += ddz; }
+    np += keep ? 1 : 0;
+    done = done || tn >= (W)1;
+    if (!__any(!done)) break;
+    tc = done ? tc : tn;
+    const bool ax = !done && tx <= ty && tx <= tz;
+    const bool ay = !done && !ax && ty <= tz;
+    const bool az = !done && !ax && !ay;
+    ix += ax ? sx : 0;
+    iy += ay ? sy : 0;
+    iz += az ? sz : 0;
+    tx = ax ? tx + ddx : tx;
+    ty = ay ? ty + ddy : ty;
+    tz = az ? tz + ddz : tz;
   }
-  return kMaxPieces + 1;
+  return (over || !done) ? kMaxPieces + 1 : (np > kMaxPieces ? kMaxPieces + 1 : np);
 }
 
 // the row buffer of wavefront wid in the dynamic LDS area (see row_buf_bytes)
@@ -412,6 +425,7 @@ __device__ int build_row(const PathParams &P, const R *cF, const ProtonPath<R> &
   const R gix = (R)P.idx, giy = (R)P.idy, giz = (R)P.idz;
   int count = 0;
   int carry_vox = -1;
+  int lane_dirs = 0;  // directions in which the voxel indices of this lane's segments change (below)
   for (int base = 0; base < K; base += kSegPerRound) {
     const int k = base + lane;
     R wx = 0, wy = 0, wz = 0;
@@ -438,13 +452,21 @@ __device__ int build_row(const PathParams &P, const R *cF, const ProtonPath<R> &
     int vox[kMaxPieces];
     float len[kMaxPieces];
     int np = 0;
+    int dirs = 0;
     if (lane < kSegPerRound && k < K) {
       const R ex = nwx - wx, ey = nwy - wy, ez = nwz - wz;
       const R seg = rsqrt_<R>(ex * ex + ey * ey + ez * ez);
       const R fx = floor(gx), fy = floor(gy), fz = floor(gz);
       np = walk_segment<R>(P, (int)fx, (int)fy, (int)fz, gx - fx, gy - fy, gz - fz, ngx - fx, ngy - fy,
                            ngz - fz, seg, vox, len);
+      // the segment's voxel-index changes per axis: bit a for up along axis
+      // a (x, y, z), bit a + 3 for down (a path ending exactly on a face
+      // enters the next voxel with the next segment; counted here)
+      const R nfx = floor(ngx), nfy = floor(ngy), nfz = floor(ngz);
+      dirs = (nfx > fx ? 1 : 0) | (nfy > fy ? 2 : 0) | (nfz > fz ? 4 : 0) | (nfx < fx ? 8 : 0) |
+             (nfy < fy ? 16 : 0) | (nfz < fz ? 32 : 0);
     }
+    lane_dirs |= dirs;
     const bool bad = np > kMaxPieces;
     if (__ballot(bad)) {
       if (lane == 0) atomicOr(status, kStOverflow);
@@ -483,7 +505,14 @@ __device__ int build_row(const PathParams &P, const R *cF, const ProtonPath<R> &
     wave_lds_sync();
     carry_vox = count > 0 ? s_vox[count - 1] : -1;
   }
-  // voxels revisited after a short excursion: fold into the first visit
+  // voxels revisited after a short excursion: fold into the first visit.
+  // A path returns to a voxel only if it crosses faces of one axis in both
+  // directions, so rows that never do skip the search.
+  int row_dirs = 0;
+#pragma unroll
+  for (int b = 0; b < 6; ++b)
+    if (__ballot(lane_dirs & (1 << b))) row_dirs |= 1 << b;
+  if ((row_dirs & (row_dirs >> 3) & 7) == 0) return count;
   bool any = false;
   for (int e0 = 0; e0 < count; e0 += kWave) {
     const int e = e0 + lane;
