@@ -84,7 +84,7 @@ def parse():
     ap.add_argument("--ws-n", type=int, default=10_000_000, help="histories per phantom (training and evaluation)")
     ap.add_argument("--ws-steps", type=int, default=2000, help="Adam steps (one phantom per step)")
     ap.add_argument("--ws-lr", type=float, default=1e-3)
-    ap.add_argument("--ws-variants", type=str, default="2:0:truth,2:0:out",
+    ap.add_argument("--ws-variants", type=str, default="2:0:truth,2:0:out,1:0:truth",
                     help="networks to compare, comma separated: '<input sweeps joined by ->:<coarse-loss weight>"
                          "[:out|truth]' (target: the image after --ws-out sweeps, or the phantom itself)")
     ap.add_argument("--ws-out", type=int, default=20, help="sweeps of the training target")
@@ -833,13 +833,12 @@ def warmstart_experiment(args):
         g = cfg.grid
         b = cfg.phantom.body
         t0 = time.time()
-        h = synth.generate(cfg)
+        H = api.Histories(synth.generate_gpu(cfg, device=dev))
+        torch.cuda.synchronize()
         gen_s = time.time() - t0
         grid = api.make_grid(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.ox, g.oy, g.oz)
         geom = api.make_geom(cfg.beam.u_in, cfg.beam.u_out, b.ax[0], b.ax[1], b.z0, b.z1, min(g.dx, g.dy, g.dz),
                              synth.prior_poly(cfg.beam.E_kin))
-        H = api.Histories.from_numpy(h, device=dev)
-        del h
         order = torch.from_numpy(synth.block_order(cfg.n, cfg.perm_seed)).to(dev)
         mask = torch.from_numpy(synth.hull_mask(cfg)).to(dev)
         params = api.sweep_params("drop", cfg.block, cfg.lam, 1, order=order, hull_mask=mask)
@@ -1030,13 +1029,12 @@ def warmstart_at_scale(args, nets, n_train):
     g = cfg.grid
     b = cfg.phantom.body
     t0 = time.time()
-    h = synth.generate(cfg)
-    log(f"config 3: generated {N} histories in {time.time() - t0:.1f} s")
+    H = api.Histories(synth.generate_gpu(cfg, device=dev))
+    torch.cuda.synchronize()
+    log(f"config 3: generated {N} histories on the device in {time.time() - t0:.1f} s")
     grid = api.make_grid(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.ox, g.oy, g.oz)
     geom = api.make_geom(cfg.beam.u_in, cfg.beam.u_out, b.ax[0], b.ax[1], b.z0, b.z1, min(g.dx, g.dy, g.dz),
                          synth.prior_poly(cfg.beam.E_kin))
-    H = api.Histories.from_numpy(h, device=dev)
-    del h
     order = torch.from_numpy(synth.block_order(N, cfg.perm_seed)).to(dev)
     Hp = H.permuted(order)  # block order made contiguous: stretches of it are plain slices
     del H, order
