@@ -155,21 +155,24 @@ typedef struct {
 } pct_sweep_params;
 
 /* A sweep plan: cached rows regrouped, block by block, into lists per spatial
- * tile of 16 x 16 x 8 voxels (row pieces, for the projections) and into a
- * voxel-major copy per group of 64 voxels of a tile (for the update), so that
- * a DROP block runs without atomics.  `entries` counts the padded list
- * entries, `refs` the reference slots reserved per row (an upper bound on
- * piece ends), `ends` the piece ends (a piece, or its part in one 64-entry
- * chunk, gives one partial dot product).  It describes the same matrix A as the rows it was
- * built from, for one block order and block size, and holds b and ||a_i||^2
- * in block order.  `mem` is caller-owned device memory of `bytes` bytes; the
- * other fields are written by pct_plan_build and describe the layout.  A plan
- * is used by one stream at a time. */
+ * tile of 16 x 16 x 8 voxels (row pieces), which both the projections and the
+ * update read, so that a DROP block runs without global atomics.  The update
+ * adds each tile's contributions in on-chip memory as 64-bit fixed-point
+ * integers (r_i a_ij scaled by 2^(58 - ceil(log2 block_size)) and rounded),
+ * so its sums do not depend on the order of the additions; a contribution of
+ * magnitude 16 or more is added in float32 instead.  `entries` counts the
+ * padded list entries, `refs` the reference slots reserved per row (an upper
+ * bound on piece ends), `ends` the piece ends (a piece, or its part in one
+ * 64-entry chunk, gives one partial dot product).  It describes the same
+ * matrix A as the rows it was built from, for one block order and block size,
+ * and holds b and ||a_i||^2 in block order.  `mem` is caller-owned device
+ * memory of `bytes` bytes; the other fields are written by pct_plan_build and
+ * describe the layout.  A plan is used by one stream at a time. */
 typedef struct {
     void *mem;
     size_t bytes;
     int64_t n, block_size, n_blocks, n_tiles;
-    int64_t entries, chunks, refs, max_chunks, max_ends, entries_vm, ends;
+    int64_t entries, chunks, refs, max_chunks, max_ends, ends;
     int32_t len_dtype, nx, ny, nz;
     const void *order, *rows_idx;
     int32_t ready, reserved;

@@ -58,7 +58,7 @@ class pct_plan(ctypes.Structure):
     _fields_ = [("mem", _fp), ("bytes", ctypes.c_size_t), ("n", ctypes.c_int64), ("block_size", ctypes.c_int64),
                 ("n_blocks", ctypes.c_int64), ("n_tiles", ctypes.c_int64), ("entries", ctypes.c_int64),
                 ("chunks", ctypes.c_int64), ("refs", ctypes.c_int64), ("max_chunks", ctypes.c_int64),
-                ("max_ends", ctypes.c_int64), ("entries_vm", ctypes.c_int64), ("ends", ctypes.c_int64),
+                ("max_ends", ctypes.c_int64), ("ends", ctypes.c_int64),
                 ("len_dtype", ctypes.c_int32),
                 ("nx", ctypes.c_int32),
                 ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("order", _fp), ("rows_idx", _fp),

@@ -471,26 +471,22 @@ PlanDims plan_dims(const pct_grid *g, int64_t n, int64_t B) {
 int64_t plan_scratch_len(const PlanDims &d) { return d.nb * d.T + d.nb + 8; }
 
 enum {
-  L_REFBASE, L_BT_OFF, L_BT_CUR, L_RORD, L_ORDROW, L_RVALS, L_EMASK, L_CFE, L_PACKED, L_LEN, L_REFCNT, L_REFS, L_BPERM, L_N2PERM,
-  L_PARTIAL, L_RESPART, L_SCANTMP, L_ENDSLOT, L_GRPOFF, L_PACKEDB, L_LENB, L_TMPB, L_TMPLENB, L_COUNT
+  L_REFBASE, L_BT_OFF, L_BT_CUR, L_ORDROW, L_RVALS, L_EMASK, L_CFE, L_PACKED, L_LEN, L_REFCNT, L_REFS, L_BPERM, L_N2PERM,
+  L_PARTIAL, L_RESPART, L_SCANTMP, L_ENDSLOT, L_META, L_COUNT
 };
 
 size_t plan_layout(const pct_plan *p, size_t off[L_COUNT]) {
   const int64_t nbT = p->n_blocks * p->n_tiles;
   const size_t lb = p->len_dtype == 0 ? 4 : 2;
   const size_t sz[L_COUNT] = {(size_t)(p->n + 1) * 8,   (size_t)(nbT + 1) * 8,   (size_t)nbT * 8,
-                              (size_t)p->max_ends * 4, (size_t)p->refs * 4, (size_t)p->block_size * 4,
+                              (size_t)p->refs * 4,     (size_t)p->block_size * 4,
                               (size_t)p->chunks * 8,   (size_t)(p->chunks + 1) * 8,
                               (size_t)p->entries * 2,  (size_t)p->entries * lb, (size_t)p->n * 4,
                               (size_t)p->refs * 4,     (size_t)p->n * 4,         (size_t)p->n * 8,
                               (size_t)p->max_ends * 4, (size_t)pct::kResidAllGrid * 8,
                               (size_t)((p->chunks + pct::kScanChunk - 1) / pct::kScanChunk + 2) * 8,
                               (size_t)p->refs * 4,
-                              (size_t)(nbT * pct::kGroups + 1) * 8,
-                              (size_t)p->entries_vm * 4,
-                              (size_t)p->entries_vm * lb,
-                              (size_t)p->entries_vm * 4,
-                              (size_t)p->entries_vm * lb};
+                              (size_t)p->chunks * 16};
   size_t o = 0;
   for (int k = 0; k < L_COUNT; ++k) {
     off[k] = o;
@@ -522,11 +518,9 @@ pct::PlanView plan_view(const pct_plan *p, float len_unit) {
   V.ntz = (p->nz + pct::kTZ - 1) / pct::kTZ;
   V.len_dtype = p->len_dtype;
   V.len_unit = len_unit;
-  V.EB = p->entries_vm;
   if (!m) return V;
   V.bt_off = reinterpret_cast<int64_t *>(m + off[L_BT_OFF]);
   V.bt_cur = reinterpret_cast<unsigned long long *>(m + off[L_BT_CUR]);
-  V.r_ord = reinterpret_cast<float *>(m + off[L_RORD]);
   V.ord_row = reinterpret_cast<uint32_t *>(m + off[L_ORDROW]);
   V.rvals = reinterpret_cast<float *>(m + off[L_RVALS]);
   V.end_mask = reinterpret_cast<uint64_t *>(m + off[L_EMASK]);
@@ -541,11 +535,7 @@ pct::PlanView plan_view(const pct_plan *p, float len_unit) {
   V.partial = reinterpret_cast<float *>(m + off[L_PARTIAL]);
   V.res_part = reinterpret_cast<double *>(m + off[L_RESPART]);
   V.end_slot = reinterpret_cast<uint32_t *>(m + off[L_ENDSLOT]);
-  V.grp_off = reinterpret_cast<int64_t *>(m + off[L_GRPOFF]);
-  V.packedB = reinterpret_cast<uint32_t *>(m + off[L_PACKEDB]);
-  V.lenB = m + off[L_LENB];
-  V.tmpB = reinterpret_cast<uint32_t *>(m + off[L_TMPB]);
-  V.tmp_lenB = m + off[L_TMPLENB];
+  V.meta = m + off[L_META];
   return V;
 }
 
@@ -601,20 +591,14 @@ pct_status do_plan_build(Ctx &c, const pct_grid *g, const pct_rows *rows, const 
   if ((r = read_status(c, &st)) != PCT_OK) return r;
   if (st) return status_to_code(st);
   std::vector<int64_t> bt_off((size_t)(d.nb * d.T + 1), 0);
-  std::vector<int64_t> grp_off((size_t)(d.nb * d.T * pct::kGroups + 1), 0);
-  int64_t E = 0, maxc = 0, P = 1, Rtot = 0, EB = 0;
+  int64_t E = 0, maxc = 0, P = 1, Rtot = 0;
   for (int64_t b = 0; b < d.nb; ++b) {
     int64_t eb = 0;
     for (int64_t t = 0; t < d.T; ++t) {
       const int64_t k = b * d.T + t;
       const int64_t pad = (host[k] + 63) / 64 * 64;
-      if (pad >= (int64_t(1) << 24))
-        return fail(PCT_EINVAL, "block %lld has %lld entries in one tile (limit 2^24): use smaller blocks",
-                    (long long)b, (long long)pad);
       bt_off[k] = E;
-      grp_off[(size_t)k * pct::kGroups] = EB;
       E += pad;
-      EB += host[k];
       eb += pad;
     }
     maxc = std::max(maxc, eb / 64);
@@ -622,9 +606,7 @@ pct_status do_plan_build(Ctx &c, const pct_grid *g, const pct_rows *rows, const 
     Rtot += host[d.nb * d.T + b];
   }
   bt_off[d.nb * d.T] = E;
-  grp_off[(size_t)(d.nb * d.T * pct::kGroups)] = EB;
   tmp.entries = E;
-  tmp.entries_vm = EB;
   tmp.chunks = E / 64;
   tmp.refs = Rtot;
   tmp.max_chunks = std::max<int64_t>(maxc, 1);
@@ -646,7 +628,6 @@ pct_status do_plan_build(Ctx &c, const pct_grid *g, const pct_rows *rows, const 
   tmp.rows_idx = rows->idx;
   V = plan_view(&tmp, unit);
   HIPCHECK(hipMemcpyAsync(V.bt_off, bt_off.data(), bt_off.size() * 8, hipMemcpyHostToDevice, c.s));
-  HIPCHECK(hipMemcpyAsync(V.grp_off, grp_off.data(), grp_off.size() * 8, hipMemcpyHostToDevice, c.s));
   HIPCHECK(pct::launch_copy_i64_to_u64(V.bt_cur, V.bt_off, d.nb * d.T, c.s));
   if (row_cap != V.ref_base) return fail(PCT_EDEVICE, "plan layout: ref_base is not the first region");
   HIPCHECK(pct::launch_scan_rows(V.ref_base, 0, c.n, c.W.scan, c.s));
@@ -656,7 +637,6 @@ pct_status do_plan_build(Ctx &c, const pct_grid *g, const pct_rows *rows, const 
   PROF(PCT_K_PLAN_BUILD, pct::launch_plan_chunks(V, c.s));
   HIPCHECK(pct::launch_scan_rows(V.chunk_first_end, 0, tmp.chunks, plan_scan_tmp(&tmp), c.s));
   PROF(PCT_K_PLAN_BUILD, pct::launch_plan_ref_ordinals(V, c.s));
-  PROF(PCT_K_PLAN_BUILD, pct::launch_plan_build_voxel_major(V, c.s));
   int64_t refs_total = 0, ends = 0;
   HIPCHECK(hipMemcpyAsync(&refs_total, V.ref_base + c.n, 8, hipMemcpyDeviceToHost, c.s));
   HIPCHECK(hipMemcpyAsync(&ends, V.chunk_first_end + tmp.chunks, 8, hipMemcpyDeviceToHost, c.s));

@@ -114,7 +114,6 @@ struct PlanView {
   int64_t *bt_off;          // [nb*T + 1] entry offsets of each (block, tile) list (multiples of 64)
   unsigned long long *bt_cur;  // [nb*T] fill cursors
   uint32_t *ord_row;        // [R] per piece end (global ordinal): its row in the block
-  float *r_ord;             // [P] r of the row of every piece end of one block, in ordinal order
   float *rvals;             // [B] r_i of one block
   uint64_t *end_mask;       // [C] lanes that close a piece (or a chunk)
   int64_t *chunk_first_end; // [C + 1]
@@ -128,18 +127,8 @@ struct PlanView {
   double *n2_perm;          // [n] ||a||^2 in block order
   float *partial;           // [P] per-piece partial dot products of one block, in row order
   double *res_part;         // [kResidAllGrid] residual partial sums (one per workgroup)
-  // voxel-major copy for the scatter: per (block, tile, group of 64 tile-local
-  // voxels) the entries sorted by voxel; packed: bit 0 valid, bit 1 last entry
-  // of its voxel, bits 2..7 voxel in group, bits 8..31 offset of the entry's
-  // piece-end ordinal from the first ordinal of its (block, tile) list
-  int64_t EB;               // entries (= nnz of the rows)
-  int64_t *grp_off;         // [nb*T*kGroups + 1]
-  uint32_t *packedB;        // [EB]
-  void *lenB;               // [EB]
-  uint32_t *tmpB;           // [EB] build only: entries grouped by (list, group), list order
-  void *tmp_lenB;           // [EB]
+  void *meta;               // [C] build only: per chunk, end_mask and chunk_first_end side by side (16 B)
 };
-constexpr int kGroups = kTileVox / 64;  // 64-voxel groups per tile
 constexpr int kResidAllGrid = 1024;     // workgroups of the whole-plan residual rows pass
 
 hipError_t launch_plan_count(const int64_t *row_ptr, const int32_t *idx, const int64_t *order, int64_t n, int64_t B,
@@ -155,7 +144,6 @@ hipError_t launch_copy_i64_to_u64(unsigned long long *dst, const int64_t *src, i
 hipError_t launch_plan_dot(const PlanView &V, int64_t b, const float *x, hipStream_t s);
 hipError_t launch_plan_rows(const PlanView &V, int64_t b, hipStream_t s);
 hipError_t launch_plan_scatter(const PlanView &V, int64_t b, float *x, const uint8_t *mask, float lambda, hipStream_t s);
-hipError_t launch_plan_build_voxel_major(const PlanView &V, hipStream_t s);
 hipError_t launch_plan_dot_all(const PlanView &V, const float *x, hipStream_t s);
 hipError_t launch_plan_resid_all(const PlanView &V, double *partials, hipStream_t s);
 hipError_t launch_sum_partials(const double *partials, int64_t np, double *out, int sqrt_it, hipStream_t s);

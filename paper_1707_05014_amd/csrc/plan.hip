@@ -9,15 +9,16 @@
 //                  next to the other partials of its row;
 //   k_plan_rows    one thread per row of the block: adds the row's partials in
 //                  a fixed order -> r_i = (b_i - a_i.x)/||a_i||^2;
-//   k_plan_scatter workgroups per (block, tile) list, r of the list's piece
-//                  ends staged in LDS: the voxel-sorted copy of the list gives
-//                  each voxel's run, reduced by segmented wave scans into
-//                  num_j and s_j, then x_j += lambda num_j / s_j.
+//   k_plan_scatter one workgroup per (block, tile) list: each entry's
+//                  r_i a_ij and count are added into LDS images of the tile
+//                  (the numerators as exact 64-bit fixed-point integers),
+//                  then x_j += lambda num_j / s_j.
 //
 // Entries are packed in 16 bits (voxel in tile, valid and piece-closing
 // flags) next to their lengths (float32 or float16), so both passes stream the
-// lists with coalesced loads; the scatter reads a voxel-sorted copy whose
-// 32-bit codes also carry the entry's piece-end ordinal.
+// same lists with coalesced loads.
+#include <cmath>
+
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -351,8 +352,6 @@ constexpr int kDotBatch = PCT_DOT_BATCH;
 #ifndef PCT_DOT_WAVES
 #define PCT_DOT_WAVES 8
 #endif
-constexpr int kPlanWaves = 8;
-constexpr int kPlanThreads = kPlanWaves * kWave;
 constexpr int kDotSplit = PCT_DOT_SPLIT;  // workgroups per (block, tile) list, each on an equal share of its chunks
 constexpr int kDotWaves = PCT_DOT_WAVES;  // wavefronts per dot workgroup
 constexpr int kDotThreads = kDotWaves * kWave;
@@ -478,8 +477,8 @@ __global__ void __launch_bounds__(kDotThreads) k_plan_dot(PlanView V, int64_t b0
 
 // Per chunk, its piece-end mask and first ordinal side by side (16 B), so
 // that k_plan_ref_ordinals, which visits chunks in row order (scattered),
-// fetches one cache line per reference instead of two.  Kept in the
-// build-only tmpB area, which is free until the voxel-major copy is built.
+// fetches one cache line per reference instead of two (a build-only area of
+// the plan).
 struct __align__(16) ChunkMeta {
   uint64_t mask;
   int64_t first;
@@ -498,7 +497,7 @@ __global__ void __launch_bounds__(256) k_plan_chunk_meta(PlanView V, ChunkMeta *
 // references hold entry positions after the fill pass; record, for every
 // piece end (global ordinal in chunk order), the row-ordered slot of its
 // reference, so k_plan_dot can store each partial next to the other partials
-// of its row, and its row in the block, so k_plan_expand can give it r
+// of its row, and its row in the block, so k_plan_scatter can give it r
 template <bool META>
 __global__ void __launch_bounds__(256) k_plan_ref_ordinals(PlanView V, const ChunkMeta *__restrict__ meta) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -561,17 +560,6 @@ __global__ void __launch_bounds__(256) k_plan_rows(PlanView V, int64_t b) {
   V.rvals[r] = nref ? (float)(((double)V.b_perm[q] - (double)d) / V.n2_perm[q]) : 0.0f;
 }
 
-// r of every piece end of block b, in ordinal order (coalesced writes; the
-// rows are gathered), so the scatter can stage a tile's r values with
-// contiguous loads
-__global__ void __launch_bounds__(256) k_plan_expand(PlanView V, int64_t b) {
-  const int64_t ob = V.chunk_first_end[V.bt_off[b * V.T] / kWave];
-  const int64_t oe = V.chunk_first_end[V.bt_off[(b + 1) * V.T] / kWave];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t o = ob + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < oe; o += stride)
-    V.r_ord[o - ob] = V.rvals[V.ord_row[o]];
-}
-
 // squared residuals of every row from the partials of a whole-plan dot pass
 // (absolute slots): rows q = blockIdx.x * 256 + threadIdx.x + k * gridDim.x *
 // 256, one FP64 sum per workgroup (fixed grid, so a fixed summation order)
@@ -596,412 +584,137 @@ __global__ void __launch_bounds__(256) k_plan_resid_all(PlanView V, double *part
   if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
-// ---- voxel-major copy of the lists (layout B), built by two stable
-// counting sorts: k_plan_group_bucket moves each (block, tile) list's entries
-// into its 32 groups of 64 voxels (list order kept within a group; writes go
-// out in runs of about a hundred entries), k_plan_voxel_sort orders each
-// group by voxel (order kept within a voxel) and flags the last entry of
-// every voxel's run.  Ranks within a wavefront come from ballots over the key
-// bits (no atomics), so equal keys keep their list order.
-
-// Key ballots of one chunk: bit planes of a key of NB bits over the lanes.
-template <int NB>
-struct KeyBallots {
-  uint64_t valid;
-  uint64_t plane[NB];
-  __device__ __forceinline__ KeyBallots(uint32_t key, bool ok) {
-    valid = __ballot(ok);
-#pragma unroll
-    for (int bit = 0; bit < NB; ++bit) plane[bit] = __ballot((key >> bit) & 1u);
-  }
-  // valid lanes whose key equals k
-  __device__ __forceinline__ uint64_t lanes_with(uint32_t k) const {
-    uint64_t m = valid;
-#pragma unroll
-    for (int bit = 0; bit < NB; ++bit) m &= ((k >> bit) & 1u) ? plane[bit] : ~plane[bit];
-    return m;
-  }
-};
-
-__device__ __forceinline__ uint64_t lanes_below() {
-  const int lane = wave_lane();
-  return (1ull << lane) - 1ull;
-}
-
-constexpr int kBucketChunks = 4;  // chunks per wavefront per round of k_plan_group_bucket
-
-// One workgroup of kPlanWaves wavefronts per (block, tile) list: writes the
-// group offsets of the list (grp_off, from the list start the host put in
-// grp_off[k * kGroups]) and the entries, grouped, to tmpB / tmp_lenB with the
-// B-layout fields except the run flag.  Lane g of a wavefront keeps the count
-// of group g; an entry's rank among equal keys comes from the key ballots.
-__global__ void __launch_bounds__(kPlanThreads) k_plan_group_bucket(PlanView V) {
-  __shared__ uint32_t s_cnt[kPlanWaves][kGroups];
-  __shared__ int64_t s_off[kPlanWaves][kGroups];
-  __shared__ int64_t s_base[kGroups];
-  const int lane = wave_lane();
-  const int wid = uniform((int)(threadIdx.x / kWave));
-  const int64_t k = blockIdx.x;
-  const int64_t a0 = V.bt_off[k], a1 = V.bt_off[k + 1];
-  const int64_t c0 = a0 / kWave, nch = (a1 - a0) / kWave;
-  const int64_t o0 = nch ? V.chunk_first_end[c0] : 0;
-  // sweep A: entries per group (chunks wid, wid + kPlanWaves, ...; loads of
-  // kBucketChunks chunks issued together)
-  uint32_t cnt = 0;
-  for (int64_t cb = wid; cb < nch; cb += (int64_t)kPlanWaves * kBucketChunks) {
-    uint32_t v[kBucketChunks];
-#pragma unroll
-    for (int q = 0; q < kBucketChunks; ++q) {
-      const int64_t c = cb + (int64_t)q * kPlanWaves;
-      v[q] = c < nch ? (uint32_t)V.packed[(c0 + c) * kWave + lane] : 0u;
-    }
-#pragma unroll
-    for (int q = 0; q < kBucketChunks; ++q) {
-      const KeyBallots<5> kb(((v[q] >> 2) & (kTileVox - 1)) >> 6, v[q] & 1u);
-      cnt += (uint32_t)__popcll(kb.lanes_with((uint32_t)lane));
-    }
-  }
-  if (lane < kGroups) s_cnt[wid][lane] = cnt;
-  __syncthreads();
-  if (wid == 0) {
-    uint32_t tot = 0;
-    if (lane < kGroups)
-      for (int w = 0; w < kPlanWaves; ++w) tot += s_cnt[w][lane];
-    const int64_t base = V.grp_off[k * kGroups] + wave_excl_scan((int)tot);
-    if (lane < kGroups) {
-      s_base[lane] = base;
-      if (lane > 0) V.grp_off[k * kGroups + lane] = base;
-    }
-  }
-  __syncthreads();
-  // sweep B: rounds of kPlanWaves x kBucketChunks chunks, wavefront w taking
-  // the w-th run of kBucketChunks consecutive chunks of the round
-  const int64_t per_round = (int64_t)kPlanWaves * kBucketChunks;
-  for (int64_t r0 = 0; r0 < nch; r0 += per_round) {
-    uint32_t pv[kBucketChunks], pl[kBucketChunks], pos[kBucketChunks], grp[kBucketChunks];
-    uint64_t em[kBucketChunks];
-    int64_t fe[kBucketChunks];
-#pragma unroll
-    for (int q = 0; q < kBucketChunks; ++q) {
-      const int64_t c = r0 + (int64_t)wid * kBucketChunks + q;
-      pv[q] = 0u;
-      pl[q] = 0u;
-      em[q] = 0ull;
-      fe[q] = 0;
-      if (c < nch) {
-        const int64_t p = (c0 + c) * kWave + lane;
-        pv[q] = (uint32_t)V.packed[p];
-        pl[q] = V.len_dtype == 0 ? reinterpret_cast<const uint32_t *>(V.len)[p]
-                                 : (uint32_t)reinterpret_cast<const uint16_t *>(V.len)[p];
-        em[q] = V.end_mask[c0 + c];
-        fe[q] = V.chunk_first_end[c0 + c];
-      }
-    }
-    uint32_t wcur = 0;  // lane g: entries of group g met so far in this round
-#pragma unroll
-    for (int q = 0; q < kBucketChunks; ++q) {
-      const bool valid = pv[q] & 1u;
-      const uint32_t vox = (pv[q] >> 2) & (kTileVox - 1);
-      const uint32_t key = vox >> 6;
-      const KeyBallots<5> kb(key, valid);
-      const uint32_t before = (uint32_t)__shfl((int)wcur, (int)key, kWave);
-      pos[q] = before + (uint32_t)__popcll(kb.lanes_with(key) & lanes_below());
-      grp[q] = key;
-      wcur += (uint32_t)__popcll(kb.lanes_with((uint32_t)lane));
-      // the piece end at or after this entry: closes strictly below this
-      // lane belong to earlier pieces of the chunk
-      const int64_t ord = fe[q] + __popcll(em[q] & lanes_below());
-      pv[q] = valid ? (1u | ((vox & 63u) << 2) | ((uint32_t)(ord - o0) << 8)) : 0u;
-    }
-    if (lane < kGroups) s_cnt[wid][lane] = wcur;
-    __syncthreads();
-    if (threadIdx.x < kGroups) {
-      int64_t run = s_base[threadIdx.x];
-      for (int w = 0; w < kPlanWaves; ++w) {
-        s_off[w][threadIdx.x] = run;
-        run += s_cnt[w][threadIdx.x];
-      }
-      s_base[threadIdx.x] = run;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kBucketChunks; ++q) {
-      if (!(pv[q] & 1u)) continue;
-      const int64_t dst = s_off[wid][grp[q]] + pos[q];
-      V.tmpB[dst] = pv[q];
-      if (V.len_dtype == 0)
-        reinterpret_cast<uint32_t *>(V.tmp_lenB)[dst] = pl[q];
-      else
-        reinterpret_cast<uint16_t *>(V.tmp_lenB)[dst] = (uint16_t)pl[q];
-    }
-  }
-}
-
-#ifndef PCT_SORT_CHUNKS
-#define PCT_SORT_CHUNKS 16
-#endif
-#ifndef PCT_SORT_WINDOW
-#define PCT_SORT_WINDOW 4096
-#endif
-#ifndef PCT_SORT_WAVES
-#define PCT_SORT_WAVES 2
-#endif
-constexpr int kSortChunks = PCT_SORT_CHUNKS;  // chunks whose loads k_plan_voxel_sort issues together
-constexpr int kSortWindow = PCT_SORT_WINDOW;  // output entries a wavefront assembles in LDS before writing them out
-constexpr int kSortWaves = PCT_SORT_WAVES;
-// workgroups that one CU holds at once (160 KB of LDS, 8 B per window slot)
-constexpr int kSortWgsPerCu = (160 * 1024) / (8 * kSortWaves * kSortWindow) > 0
-                                  ? (160 * 1024) / (8 * kSortWaves * kSortWindow)
-                                  : 1;
-
-// One (block, tile, group) list: sweep A counts entries per voxel; sweep B
-// places them (stable), through an LDS window of kSortWindow output slots
-// that is written out with contiguous stores (lists longer than the window
-// take one sweep B per window).  Lane v keeps the count, then the cursor, of
-// voxel v of the group.
-__device__ __forceinline__ void voxel_sort_group(const PlanView &V, int64_t gi, int lane, uint32_t *s_v,
-                                                 uint32_t *s_l) {
-  const int64_t e0 = V.grp_off[gi], e1 = V.grp_off[gi + 1];
-  if (e0 == e1) return;
-  const int64_t step = (int64_t)kSortChunks * kWave;
-  // sweep A: entries per voxel of the group
-  uint32_t cnt = 0;
-  for (int64_t w = e0; w < e1; w += step) {
-    uint32_t v[kSortChunks];
-#pragma unroll
-    for (int q = 0; q < kSortChunks; ++q) {
-      const int64_t p = w + (int64_t)q * kWave + lane;
-      v[q] = p < e1 ? V.tmpB[p] : 0u;
-    }
-#pragma unroll
-    for (int q = 0; q < kSortChunks; ++q) {
-      const KeyBallots<6> kb((v[q] >> 2) & 63u, v[q] & 1u);
-      cnt += (uint32_t)__popcll(kb.lanes_with((uint32_t)lane));
-    }
-  }
-  // run starts (exclusive scan over the 64 voxels); a run ends at start + cnt - 1
-  const uint32_t start = (uint32_t)wave_excl_scan((int)cnt);
-  const uint32_t end = start + cnt;
-  const int64_t n = e1 - e0;
-  for (int64_t wlo = 0; wlo < n; wlo += kSortWindow) {
-    const int64_t whi = wlo + kSortWindow < n ? wlo + kSortWindow : n;
-    uint32_t cur = start;
-    // sweep B: stable placement of the slots that fall in [wlo, whi)
-    for (int64_t w = e0; w < e1; w += step) {
-      uint32_t v[kSortChunks], l[kSortChunks];
-#pragma unroll
-      for (int q = 0; q < kSortChunks; ++q) {
-        const int64_t p = w + (int64_t)q * kWave + lane;
-        v[q] = 0u;
-        l[q] = 0u;
-        if (p < e1) {
-          v[q] = V.tmpB[p];
-          l[q] = V.len_dtype == 0 ? reinterpret_cast<const uint32_t *>(V.tmp_lenB)[p]
-                                  : (uint32_t)reinterpret_cast<const uint16_t *>(V.tmp_lenB)[p];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kSortChunks; ++q) {
-        const bool valid = v[q] & 1u;
-        const uint32_t key = (v[q] >> 2) & 63u;
-        const KeyBallots<6> kb(key, valid);
-        const uint32_t slot = (uint32_t)__shfl((int)cur, (int)key, kWave) +
-                              (uint32_t)__popcll(kb.lanes_with(key) & lanes_below());
-        const uint32_t run_end = (uint32_t)__shfl((int)end, (int)key, kWave) - 1u;
-        cur += (uint32_t)__popcll(kb.lanes_with((uint32_t)lane));
-        if (valid && slot >= wlo && slot < whi) {
-          s_v[slot - wlo] = v[q] | (slot == run_end ? 2u : 0u);
-          s_l[slot - wlo] = l[q];
-        }
-      }
-    }
-    wave_lds_sync();
-    // the window, in order
-    for (int64_t o = wlo + lane; o < whi; o += kWave) {
-      const int64_t dst = e0 + o;
-      V.packedB[dst] = s_v[o - wlo];
-      if (V.len_dtype == 0)
-        reinterpret_cast<uint32_t *>(V.lenB)[dst] = s_l[o - wlo];
-      else
-        reinterpret_cast<uint16_t *>(V.lenB)[dst] = (uint16_t)s_l[o - wlo];
-    }
-    wave_lds_sync();
-  }
-}
-
-// Wavefronts walk the (block, tile, group) lists (persistent grid): each
-// orders its group's entries by voxel (stable) from tmpB into packedB / lenB
-// and flags each voxel's last entry.
-__global__ void __launch_bounds__(kSortWaves * kWave) k_plan_voxel_sort(PlanView V) {
-  __shared__ uint32_t s_v[kSortWaves][kSortWindow];
-  __shared__ uint32_t s_l[kSortWaves][kSortWindow];
-  const int lane = wave_lane();
-  const int wid = uniform((int)(threadIdx.x / kWave));
-  const int64_t ng = V.nb * V.T * kGroups;
-  const int64_t nw = (int64_t)gridDim.x * kSortWaves;
-  for (int64_t gi = (int64_t)blockIdx.x * kSortWaves + wid; gi < ng; gi += nw)
-    voxel_sort_group(V, gi, lane, s_v[wid], s_l[wid]);
-}
-
-#ifndef PCT_SCAT_BATCH
-#define PCT_SCAT_BATCH 6
-#endif
-constexpr int kScatBatch = PCT_SCAT_BATCH;
-
-template <int LD>
-__device__ __forceinline__ void scatter_level1(const PlanView &V, int64_t wb, int64_t e1, int lane,
-                                               uint32_t (&v)[kScatBatch], float (&val)[kScatBatch]) {
-  // loads are unconditional (entries past e1 read entry e1 - 1 and are
-  // masked), so wait counts stay static
-#pragma unroll
-  for (int k = 0; k < kScatBatch; ++k) {
-    const int64_t p0 = wb + (int64_t)k * kWave + lane;
-    const bool in = p0 < e1;
-    const int64_t p = in ? p0 : e1 - 1;
-    const uint32_t vv = __builtin_nontemporal_load(V.packedB + p);
-    const float l = LD == 0 ? __builtin_nontemporal_load(reinterpret_cast<const float *>(V.lenB) + p)
-                            : __half2float(__builtin_bit_cast(__half, __builtin_nontemporal_load(
-                                  reinterpret_cast<const uint16_t *>(V.lenB) + p))) * V.len_unit;
-    v[k] = in ? vv : 0u;
-    val[k] = in ? l : 0.0f;
-  }
-}
-
-// Scatter of block b, voxel-major.  kScatSplit workgroups per (block, tile),
-// each on an equal share of the tile's 64-voxel groups: r of every piece end
-// of the tile's list is staged in LDS from r_ord (ordinal order; a list with
-// more than kStageOrd ordinals reads r_ord directly instead), then each
-// wavefront takes groups of the share in turn.
-// A voxel's run is reduced with DPP prefix sums (its length is s_j); the lane
-// closing the run leaves (num_j, s_j) in the wavefront's LDS slots, one per
-// voxel of the group (every voxel has exactly one run per list).  After the
-// group, lane l applies x_j += lambda num_j / s_j to voxel l of the group.
-// No atomics.
-#ifndef PCT_SCAT_SPLIT
-#define PCT_SCAT_SPLIT 2
-#endif
+// ---- scatter and update of one block, from the lists the dot reads.
+//
+// One workgroup per (block, tile) list.  Every entry adds r_i a_ij to the
+// numerator of its voxel and 1 to s_j, in LDS images of the tile: the
+// numerator as a 64-bit fixed-point integer, r_i a_ij x 2^k rounded to the
+// nearest integer, with k set from the block size so that no sum of up to
+// block_size contributions of magnitude below kFixBig can overflow.  Integer
+// additions are exact, so the sums (and the image) do not depend on the order
+// in which the entries arrive; LDS integer atomics also run about fifteen
+// times as fast as LDS float atomics on this chip.  A contribution of
+// magnitude kFixBig or more (or one that is not finite) goes to a float LDS
+// image instead, whose sum does depend on the order (no physical row comes
+// near it: |r_i a_ij| <= |b_i - a_i.x| / ||a_i||).  Then x_j += lambda num_j /
+// s_j for every voxel of the tile that the block touches.
+//
+// A wavefront takes batches of kScatBatch consecutive chunks (batch j, j +
+// kScatWaves, ...) in a three-stage software pipeline: stage A loads a batch's
+// entries, lengths and per-chunk piece-end records and works out each lane's
+// piece-end ordinal; stage B loads the block row of those ordinals; stage C
+// loads r of those rows.  While batch j is added up, stage A of j + 2, stage B
+// of j + 1 and stage C of j are in flight.
+constexpr float kFixBig = 16.0f;
 #ifndef PCT_SCAT_WAVES
 #define PCT_SCAT_WAVES 16
 #endif
-constexpr int kStageOrd = 12288;
-constexpr int kScatSplit = PCT_SCAT_SPLIT;  // workgroups per (block, tile), each on an equal share of its voxel groups
-constexpr int kScatWaves = PCT_SCAT_WAVES;  // wavefronts per scatter workgroup
+#ifndef PCT_SCAT_BATCH
+#define PCT_SCAT_BATCH 4
+#endif
+constexpr int kScatWaves = PCT_SCAT_WAVES;  // wavefronts per scatter workgroup (one workgroup per list)
 constexpr int kScatThreads = kScatWaves * kWave;
+constexpr int kScatBatch = PCT_SCAT_BATCH;  // chunks per pipeline stage of a wavefront
+
+// fixed-point exponent for blocks of B rows: B x kFixBig x 2^k <= 2^62
+__host__ __device__ inline int fix_exponent(int64_t B) {
+  int lg = 0;
+  while ((int64_t(1) << lg) < B) ++lg;
+  return 58 - lg;
+}
+
+struct ScatStage {
+  uint32_t v[kScatBatch];    // entry codes (0 past the list's end)
+  float l[kScatBatch];       // lengths
+  uint32_t ord[kScatBatch];  // global piece-end ordinal of the lane's piece
+};
+
+template <int LD>
+__device__ __forceinline__ void scat_stage_a(const PlanView &V, int64_t ca, int64_t cb, int64_t j, int lane,
+                                             ScatStage &a) {
+#pragma unroll
+  for (int k = 0; k < kScatBatch; ++k) {
+    const int64_t c0 = ca + j * kScatBatch + k;
+    const bool in = c0 < cb;
+    const int64_t c = in ? c0 : cb - 1;
+    const int64_t p = c * kWave + lane;
+    const uint32_t v = (uint32_t)V.packed[p];
+    a.l[k] = plan_len<LD>(V, p);
+    a.v[k] = in ? v : 0u;
+    const uint64_t m = V.end_mask[c];
+    const int64_t fe = V.chunk_first_end[c];
+    // the lane's piece closes at the first closing lane at or above it (a
+    // padding lane reads the chunk's first piece end, never added)
+    a.ord[k] = (uint32_t)(fe + ((v & 1u) ? __popcll(m & ((1ull << lane) - 1ull)) : 0));
+  }
+}
 
 template <int LD>
 __global__ void __launch_bounds__(kScatThreads) k_plan_scatter(PlanView V, int64_t b, float *__restrict__ x,
-                                                               const uint8_t *__restrict__ mask, float lambda) {
-  __shared__ float s_r[kStageOrd];
-  __shared__ float s_num[kScatWaves][kWave];
-  __shared__ uint32_t s_cnt[kScatWaves][kWave];
+                                                               const uint8_t *__restrict__ mask, float lambda,
+                                                               float fix_scale, float fix_unscale) {
+  __shared__ unsigned long long s_num[kTileVox];
+  __shared__ uint32_t s_cnt[kTileVox];
+  __shared__ float s_big[kTileVox];
   const int lane = wave_lane();
-  const int wid = uniform((int)(threadIdx.x / kWave));
-  const int64_t t = blockIdx.x / kScatSplit;
-  const int part = blockIdx.x % kScatSplit;
+  const int64_t t = blockIdx.x;
   const int64_t lk = b * V.T + t;
-  const int64_t a0 = V.bt_off[lk], a1 = V.bt_off[lk + 1];
-  if (a0 == a1) return;  // the whole workgroup leaves
-  // r of the list's piece ends, in ordinal order
-  const float *r_list = V.r_ord + (V.chunk_first_end[a0 / kWave] - V.chunk_first_end[V.bt_off[b * V.T] / kWave]);
-  const int64_t nord = V.chunk_first_end[a1 / kWave] - V.chunk_first_end[a0 / kWave];
-  const bool staged = nord <= kStageOrd;
-  if (staged && nord > 0) {
-    // kStageLoads loads per thread in flight before any store (indices past
-    // the list read its last value and store nothing)
-    constexpr int kStageLoads = 8;
-    for (int64_t i0 = threadIdx.x; i0 < nord; i0 += (int64_t)kScatThreads * kStageLoads) {
-      float rv[kStageLoads];
+  const int64_t ca = V.bt_off[lk] / kWave, cb = V.bt_off[lk + 1] / kWave;
+  if (ca == cb) return;  // the whole workgroup leaves
+  for (int q = threadIdx.x; q < kTileVox; q += kScatThreads) {
+    s_num[q] = 0ull;
+    s_cnt[q] = 0u;
+    s_big[q] = 0.0f;
+  }
+  __syncthreads();
+  const int64_t nbat = (cb - ca + kScatBatch - 1) / kScatBatch;
+  int64_t j = uniform((int)(threadIdx.x / kWave));
+  if (j < nbat) {
+    // batches past the last are loaded as the last one again (never added)
+    const int64_t jlast = j + (nbat - 1 - j) / kScatWaves * kScatWaves;
+    ScatStage a0, a1, a2;
+    uint32_t row0[kScatBatch], row1[kScatBatch];
+    float r0[kScatBatch];
+    scat_stage_a<LD>(V, ca, cb, j, lane, a0);
+    scat_stage_a<LD>(V, ca, cb, j + kScatWaves <= jlast ? j + kScatWaves : jlast, lane, a1);
 #pragma unroll
-      for (int u = 0; u < kStageLoads; ++u) {
-        const int64_t i = i0 + (int64_t)u * kScatThreads;
-        rv[u] = r_list[i < nord ? i : nord - 1];
-      }
+    for (int k = 0; k < kScatBatch; ++k) row0[k] = V.ord_row[a0.ord[k]];
+    for (;;) {
+      const int64_t j1 = j + kScatWaves, j2 = j + 2 * kScatWaves;
 #pragma unroll
-      for (int u = 0; u < kStageLoads; ++u) {
-        const int64_t i = i0 + (int64_t)u * kScatThreads;
-        if (i < nord) s_r[i] = rv[u];
+      for (int k = 0; k < kScatBatch; ++k) r0[k] = V.rvals[row0[k]];
+#pragma unroll
+      for (int k = 0; k < kScatBatch; ++k) row1[k] = V.ord_row[a1.ord[k]];
+      scat_stage_a<LD>(V, ca, cb, j2 <= jlast ? j2 : jlast, lane, a2);
+#pragma unroll
+      for (int k = 0; k < kScatBatch; ++k) {
+        const uint32_t v = a0.v[k];
+        if (!(v & 1u)) continue;
+        const int loc = (int)((v >> 2) & (kTileVox - 1));
+        const float val = r0[k] * a0.l[k];
+        if (fabsf(val) < kFixBig)
+          atomicAdd(&s_num[loc], (unsigned long long)(long long)rintf(val * fix_scale));
+        else
+          atomicAdd(&s_big[loc], val);
+        atomicAdd(&s_cnt[loc], 1u);
       }
+      if (j1 > jlast) break;
+      j = j1;
+      a0 = a1;
+      a1 = a2;
+#pragma unroll
+      for (int k = 0; k < kScatBatch; ++k) row0[k] = row1[k];
     }
   }
   __syncthreads();
-  constexpr int kGroupsPerPart = kGroups / kScatSplit;
-  for (int grp = part * kGroupsPerPart + wid; grp < (part + 1) * kGroupsPerPart; grp += kScatWaves) {
-    const int64_t gi = lk * kGroups + grp;
-    const int64_t e0 = V.grp_off[gi], e1 = V.grp_off[gi + 1];
-    if (e0 == e1) continue;
-    // this lane's voxel of the group: its x and mask are fetched before the loop
+  for (int q = threadIdx.x; q < kTileVox; q += kScatThreads) {
+    const uint32_t c = s_cnt[q];
     bool inside;
-    const int gv = tile_voxel((int)t, grp * kWave + lane, V, inside);
-    float xl = 0.0f;
-    bool keep = true;
-    if (inside) {
-      xl = x[gv];
-      if (mask) keep = mask[gv] != 0;
-    }
-    s_num[wid][lane] = 0.0f;
-    s_cnt[wid][lane] = 0u;
-    float carry = 0.0f;  // sum of the run that continues from the previous chunk
-    int carry_n = 0;
-    // batches of kScatBatch chunks: the entries of the next batch are loaded
-    // while the current batch is reduced
-    uint32_t v[kScatBatch];
-    float val[kScatBatch];
-    scatter_level1<LD>(V, e0, e1, lane, v, val);
-    for (int64_t wb = e0; wb < e1; wb += (int64_t)kScatBatch * kWave) {
-      float r[kScatBatch];
-#pragma unroll
-      for (int k = 0; k < kScatBatch; ++k) {
-        r[k] = 0.0f;
-        if (v[k] & 1u) r[k] = staged ? s_r[v[k] >> 8] : r_list[v[k] >> 8];
-      }
-      const int64_t wn = wb + (int64_t)kScatBatch * kWave;
-      uint32_t vn[kScatBatch];
-      float valn[kScatBatch];
-      if (wn < e1) scatter_level1<LD>(V, wn, e1, lane, vn, valn);
-#pragma unroll
-      for (int k = 0; k < kScatBatch; ++k) {
-        const int64_t w = wb + (int64_t)k * kWave;
-        if (w >= e1) continue;  // wave-uniform
-        const bool close = (v[k] & 1u) && ((v[k] >> 1) & 1u);
-        const uint64_t m = __ballot(close);
-        const float S = wave_incl_scan_dpp(val[k] * r[k]);
-        const uint64_t below = m & ((1ull << lane) - 1);
-        const int prev = below ? 63 - __clzll(below) : -1;
-        const float Sp = __shfl(S, prev < 0 ? 0 : prev, kWave);
-        if (close) {
-          const int vg = (v[k] >> 2) & 63;
-          s_num[wid][vg] = prev >= 0 ? S - Sp : S + carry;
-          s_cnt[wid][vg] = (uint32_t)(prev >= 0 ? lane - prev : lane + 1 + carry_n);
-        }
-        // the run still open at the end of this chunk carries into the next one
-        const int nv = (int)(e1 - w < kWave ? e1 - w : kWave);
-        const int last_close = m ? 63 - __clzll(m) : -1;
-        const float S_end = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, S), nv - 1));
-        const float S_lc = __builtin_bit_cast(
-            float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, S), last_close < 0 ? 0 : last_close));
-        if (last_close == nv - 1) {
-          carry = 0.0f;
-          carry_n = 0;
-        } else if (last_close < 0) {
-          carry += S_end;
-          carry_n += nv;
-        } else {
-          carry = S_end - S_lc;
-          carry_n = nv - 1 - last_close;
-        }
-      }
-      if (wn < e1) {
-#pragma unroll
-        for (int k = 0; k < kScatBatch; ++k) {
-          v[k] = vn[k];
-          val[k] = valn[k];
-        }
-      }
-    }
-    wave_lds_sync();
-    const uint32_t c = s_cnt[wid][lane];
-    if (inside && c) x[gv] = keep ? xl + lambda * s_num[wid][lane] / (float)c : 0.0f;
-    wave_lds_sync();
+    const int gv = tile_voxel((int)t, q, V, inside);
+    if (!c || !inside) continue;
+    const bool keep = !mask || mask[gv] != 0;
+    const float num = (float)((double)(long long)s_num[q] * (double)fix_unscale) + s_big[q];
+    x[gv] = keep ? x[gv] + lambda * num / (float)c : 0.0f;
   }
 }
 
@@ -1066,9 +779,8 @@ hipError_t launch_plan_fill(const int64_t *row_ptr, const int32_t *idx, const vo
 hipError_t launch_plan_ref_ordinals(const PlanView &V, hipStream_t s) {
   if (V.n <= 0) return hipSuccess;
   const dim3 grid(grid_for(V.n, 256, 0x7fffffffu));
-  // the chunk records fit the tmpB area unless padding is most of the plan
-  if (V.C > 0 && (uint64_t)V.C * sizeof(ChunkMeta) <= (uint64_t)V.EB * sizeof(uint32_t)) {
-    ChunkMeta *meta = reinterpret_cast<ChunkMeta *>(V.tmpB);
+  if (V.C > 0 && V.meta) {
+    ChunkMeta *meta = reinterpret_cast<ChunkMeta *>(V.meta);
     hipLaunchKernelGGL(k_plan_chunk_meta, dim3(grid_for(V.C, 256, 8192)), dim3(256), 0, s, V, meta);
     hipLaunchKernelGGL(k_plan_ref_ordinals<true>, grid, dim3(256), 0, s, V, meta);
   } else {
@@ -1111,7 +823,6 @@ hipError_t launch_plan_dot_all(const PlanView &V, const float *x, hipStream_t s)
 
 hipError_t launch_plan_rows(const PlanView &V, int64_t b, hipStream_t s) {
   hipLaunchKernelGGL(k_plan_rows, dim3(grid_for(V.B, 256, 0x7fffffffu)), dim3(256), 0, s, V, b);
-  hipLaunchKernelGGL(k_plan_expand, dim3(grid_for(V.P, 256, 8192)), dim3(256), 0, s, V, b);
   return hipGetLastError();
 }
 
@@ -1124,20 +835,14 @@ hipError_t launch_plan_resid_all(const PlanView &V, double *partials, hipStream_
 hipError_t launch_plan_scatter(const PlanView &V, int64_t b, float *x, const uint8_t *mask, float lambda,
                                hipStream_t s) {
   if (V.T <= 0) return hipSuccess;
+  const int k = fix_exponent(V.B);
+  const float scale = std::ldexp(1.0f, k), unscale = std::ldexp(1.0f, -k);
   if (V.len_dtype == 0)
-    hipLaunchKernelGGL(k_plan_scatter<0>, dim3((unsigned)(V.T * kScatSplit)), dim3(kScatThreads), 0, s, V, b, x,
-                       mask, lambda);
+    hipLaunchKernelGGL(k_plan_scatter<0>, dim3((unsigned)V.T), dim3(kScatThreads), 0, s, V, b, x, mask, lambda,
+                       scale, unscale);
   else
-    hipLaunchKernelGGL(k_plan_scatter<1>, dim3((unsigned)(V.T * kScatSplit)), dim3(kScatThreads), 0, s, V, b, x,
-                       mask, lambda);
-  return hipGetLastError();
-}
-
-hipError_t launch_plan_build_voxel_major(const PlanView &V, hipStream_t s) {
-  if (V.nb * V.T <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_plan_group_bucket, dim3((unsigned)(V.nb * V.T)), dim3(kPlanThreads), 0, s, V);
-  hipLaunchKernelGGL(k_plan_voxel_sort, dim3(grid_for(V.nb * V.T * kGroups, kSortWaves, 256 * kSortWgsPerCu)),
-                     dim3(kSortWaves * kWave), 0, s, V);
+    hipLaunchKernelGGL(k_plan_scatter<1>, dim3((unsigned)V.T), dim3(kScatThreads), 0, s, V, b, x, mask, lambda,
+                       scale, unscale);
   return hipGetLastError();
 }
 

@@ -33,7 +33,7 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(_lib.pct_rows) == 3 * 8 + 3 * 8 + 8 + 8
     assert ctypes.sizeof(_lib.pct_sweep_params) == 4 + 4 + 8 + 4 + 4 + 8 + 8 + 8
     assert ctypes.sizeof(_lib.pct_tvs) == 4 + 4 + 8 + 8 + 8
-    assert ctypes.sizeof(_lib.pct_plan) == 8 + 8 + 11 * 8 + 4 * 4 + 2 * 8 + 2 * 4
+    assert ctypes.sizeof(_lib.pct_plan) == 8 + 8 + 10 * 8 + 4 * 4 + 2 * 8 + 2 * 4
 
 
 def _grid():

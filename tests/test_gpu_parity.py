@@ -445,20 +445,76 @@ def test_plan_ragged_grid_and_blocks():
 
 
 def test_plan_long_lists(cfg1):
-    """One block of all 1e5 rows: every tile list holds far more piece ends
-    than the scatter stages in LDS, so r is read through the ordinal-to-row
-    map instead (checked against the oracle)."""
+    """One block of all 1e5 rows: the longest tile lists (each list is summed
+    by one workgroup) and the smallest fixed-point scale of the update (2^41
+    for a block of 1e5 rows), checked against the oracle."""
     cfg, h, R = cfg1
-    _say("plan with one block of 100000 rows (unstaged scatter lists)")
+    _say("plan with one block of 100000 rows")
     xo, ro, order, mask = _run_oracle(cfg, h, R, "drop", cfg.n, 3)
     xg, rg, plan, _ = _plan_run(cfg, h, cfg.n, 3, order, mask)
     s = plan.struct
     _say(f"  plan: entries {s.entries} piece ends {s.ends} tiles {s.n_tiles}")
-    assert s.ends / s.n_tiles > 12288  # lists longer than the LDS stage, on average
+    assert s.entries / s.n_tiles > 1e5  # long lists, on average
     rel = _rel(xg, xo)
     _say(f"  image rel-L2 {rel:.2e}")
     assert rel <= IMG_TOL
     assert np.allclose(rg, ro, rtol=1e-3)
+
+
+def test_plan_large_contributions(cfg1):
+    """b scaled by 16, so that many contributions r_i a_ij reach the
+    magnitude (16) above which the update adds them in float32 instead of
+    fixed point: both kinds of sum in one image, against the oracle run on the
+    same scaled b."""
+    cfg, h, R = cfg1
+    h2 = dict(h)
+    h2["wepl"] = (h["wepl"] * 16.0).astype(h["wepl"].dtype)
+    _say("plan with b x 16 (contributions beyond the fixed-point range)")
+    order = synth.block_order(cfg.n, cfg.perm_seed)
+    mask = synth.hull_mask(cfg)
+    xo, ro = oracle.drop(R, h2["wepl"], mask.astype(np.float64), order, 5000, cfg.lam, 2, mask=mask)
+    xg, rg, plan, rows = _plan_run(cfg, h2, 5000, 2, order, mask)
+    # share of entries whose first-sweep contribution is 16 or more (from the oracle's rows)
+    rp, idx, ln = R.row_ptr, R.idx, R.len
+    x0 = mask.astype(np.float64)
+    q = order[:5000]
+    big = 0
+    tot = 0
+    for i in q:
+        a, b = rp[i], rp[i + 1]
+        if b == a:
+            continue
+        n2 = float(np.dot(ln[a:b], ln[a:b]))
+        r = (h2["wepl"][i] - float(np.dot(ln[a:b], x0[idx[a:b]]))) / n2
+        big += int(np.count_nonzero(np.abs(r * ln[a:b]) >= 16.0))
+        tot += b - a
+    rel = _rel(xg, xo)
+    _say(f"  first block: {big} of {tot} contributions >= 16; image rel-L2 {rel:.2e}")
+    assert 0.01 * tot < big < 0.99 * tot
+    assert rel <= IMG_TOL
+    assert np.allclose(rg, ro, rtol=1e-3)
+
+
+def test_plan_sweep_reproducible(cfg1):
+    """The update's sums are exact integers, so two sweeps from the same image
+    give the same bits, whatever order the entries' additions took."""
+    cfg, h, R = cfg1
+    grid, geom = pct_args(cfg)
+    H = api.Histories.from_numpy(h)
+    order = torch.from_numpy(synth.block_order(cfg.n, cfg.perm_seed)).cuda()
+    mask = torch.from_numpy(synth.hull_mask(cfg)).cuda()
+    params = api.sweep_params("drop", 5000, cfg.lam, 1, order=order, hull_mask=mask)
+    rows = api.mlp_trace(grid, geom, H)
+    plan = api.plan_build(grid, H, rows, params)
+    outs = []
+    for _ in range(3):
+        x = mask.to(torch.float32)
+        api.plan_sweep(grid, plan, x, params)
+        api.plan_sweep(grid, plan, x, params)
+        outs.append(x.cpu().numpy())
+    torch.cuda.synchronize()
+    assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32))
+    assert np.array_equal(outs[0].view(np.uint32), outs[2].view(np.uint32))
 
 
 def test_plan_f16_rows_match_csr(cfg1):
