@@ -478,7 +478,7 @@ enum {
 size_t plan_layout(const pct_plan *p, size_t off[L_COUNT]) {
   const int64_t nbT = p->n_blocks * p->n_tiles;
   const size_t lb = p->len_dtype == 0 ? 4 : 2;
-  const size_t sz[L_COUNT] = {(size_t)(p->n + 1) * 8,   (size_t)(nbT + 1) * 8,   (size_t)nbT * 8,
+  const size_t sz[] = {(size_t)(p->n + 1) * 8,   (size_t)(nbT + 1) * 8,   (size_t)nbT * 8,
                               (size_t)p->refs * 4,     (size_t)p->block_size * 4,
                               (size_t)p->chunks * 8,   (size_t)(p->chunks + 1) * 8,
                               (size_t)p->entries * 2,  (size_t)p->entries * lb, (size_t)p->n * 4,
@@ -487,6 +487,7 @@ size_t plan_layout(const pct_plan *p, size_t off[L_COUNT]) {
                               (size_t)((p->chunks + pct::kScanChunk - 1) / pct::kScanChunk + 2) * 8,
                               (size_t)p->refs * 4,
                               (size_t)p->chunks * 16};
+  static_assert(sizeof(sz) / sizeof(sz[0]) == L_COUNT, "one size per plan region");
   size_t o = 0;
   for (int k = 0; k < L_COUNT; ++k) {
     off[k] = o;

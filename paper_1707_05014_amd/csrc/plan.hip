@@ -600,17 +600,17 @@ __global__ void __launch_bounds__(256) k_plan_resid_all(PlanView V, double *part
 // s_j for every voxel of the tile that the block touches.
 //
 // A wavefront takes batches of kScatBatch consecutive chunks (batch j, j +
-// kScatWaves, ...) in a three-stage software pipeline: stage A loads a batch's
-// entries, lengths and per-chunk piece-end records and works out each lane's
-// piece-end ordinal; stage B loads the block row of those ordinals; stage C
-// loads r of those rows.  While batch j is added up, stage A of j + 2, stage B
-// of j + 1 and stage C of j are in flight.
+// kScatWaves, ...) in a three-stage software pipeline: the loads of a batch's
+// entries, lengths and per-chunk piece-end records are issued two batches
+// ahead of its additions, the loads of the rows of its lanes' piece ends one
+// batch ahead, and the loads of r of those rows (a small array, cached) just
+// before.
 constexpr float kFixBig = 16.0f;
 #ifndef PCT_SCAT_WAVES
 #define PCT_SCAT_WAVES 16
 #endif
 #ifndef PCT_SCAT_BATCH
-#define PCT_SCAT_BATCH 4
+#define PCT_SCAT_BATCH 2
 #endif
 constexpr int kScatWaves = PCT_SCAT_WAVES;  // wavefronts per scatter workgroup (one workgroup per list)
 constexpr int kScatThreads = kScatWaves * kWave;
@@ -626,33 +626,51 @@ __host__ __device__ inline int fix_exponent(int64_t B) {
 struct ScatStage {
   uint32_t v[kScatBatch];    // entry codes (0 past the list's end)
   float l[kScatBatch];       // lengths
-  uint32_t ord[kScatBatch];  // global piece-end ordinal of the lane's piece
+  uint32_t ord[kScatBatch];  // piece-end ordinal of the lane's piece, from the block's first
 };
 
+// loads of a batch (chunks are wave-uniform, so the addresses are a uniform
+// base plus a 32-bit lane offset)
 template <int LD>
-__device__ __forceinline__ void scat_stage_a(const PlanView &V, int64_t ca, int64_t cb, int64_t j, int lane,
-                                             ScatStage &a) {
+__device__ __forceinline__ void scat_stage_a(const PlanView &V, int64_t ca, int64_t cb, int64_t j, int64_t ob,
+                                             int lane, ScatStage &a) {
 #pragma unroll
   for (int k = 0; k < kScatBatch; ++k) {
     const int64_t c0 = ca + j * kScatBatch + k;
     const bool in = c0 < cb;
     const int64_t c = in ? c0 : cb - 1;
-    const int64_t p = c * kWave + lane;
-    const uint32_t v = (uint32_t)V.packed[p];
-    a.l[k] = plan_len<LD>(V, p);
+    const uint16_t *__restrict__ pk = V.packed + c * kWave;
+    const uint32_t v = (uint32_t)__builtin_nontemporal_load(pk + lane);
+    if constexpr (LD == 0)
+      a.l[k] = __builtin_nontemporal_load(reinterpret_cast<const float *>(V.len) + c * kWave + lane);
+    else
+      a.l[k] = __half2float(__builtin_bit_cast(
+                   __half, __builtin_nontemporal_load(reinterpret_cast<const uint16_t *>(V.len) + c * kWave + lane))) *
+               V.len_unit;
     a.v[k] = in ? v : 0u;
     const uint64_t m = V.end_mask[c];
-    const int64_t fe = V.chunk_first_end[c];
-    // the lane's piece closes at the first closing lane at or above it (a
-    // padding lane reads the chunk's first piece end, never added)
-    a.ord[k] = (uint32_t)(fe + ((v & 1u) ? __popcll(m & ((1ull << lane) - 1ull)) : 0));
+    const uint32_t fe = (uint32_t)(V.chunk_first_end[c] - ob);
+    // the lane's piece closes at the first closing lane at or above it; lanes
+    // past the chunk's last piece end (padding, never added) take that end
+    const int below = __popcll(m & ((1ull << lane) - 1ull)), n = __popcll(m);
+    a.ord[k] = fe + (uint32_t)(below < n ? below : n - 1);
   }
+}
+
+// r a_ij as a 64-bit fixed-point integer: with t = v 2^(k-32) (|t| < 2^30),
+// the high word is floor(t) and the low word the fraction t - floor(t)
+// (exact in float) times 2^32, truncated
+__device__ __forceinline__ unsigned long long fixed_point(float val, float hi_scale) {
+  const float t = val * hi_scale;
+  const float hi = floorf(t);
+  const uint32_t lo = (uint32_t)((t - hi) * 4294967296.0f);
+  return ((unsigned long long)(uint32_t)(int)hi << 32) | lo;
 }
 
 template <int LD>
 __global__ void __launch_bounds__(kScatThreads) k_plan_scatter(PlanView V, int64_t b, float *__restrict__ x,
                                                                const uint8_t *__restrict__ mask, float lambda,
-                                                               float fix_scale, float fix_unscale) {
+                                                               float hi_scale, float fix_unscale) {
   __shared__ unsigned long long s_num[kTileVox];
   __shared__ uint32_t s_cnt[kTileVox];
   __shared__ float s_big[kTileVox];
@@ -667,6 +685,9 @@ __global__ void __launch_bounds__(kScatThreads) k_plan_scatter(PlanView V, int64
     s_big[q] = 0.0f;
   }
   __syncthreads();
+  const int64_t ob = V.chunk_first_end[V.bt_off[b * V.T] / kWave];  // the block's first piece-end ordinal
+  const uint32_t *__restrict__ ord_row = V.ord_row + ob;
+  const float *__restrict__ rvals = V.rvals;
   const int64_t nbat = (cb - ca + kScatBatch - 1) / kScatBatch;
   int64_t j = uniform((int)(threadIdx.x / kWave));
   if (j < nbat) {
@@ -675,17 +696,17 @@ __global__ void __launch_bounds__(kScatThreads) k_plan_scatter(PlanView V, int64
     ScatStage a0, a1, a2;
     uint32_t row0[kScatBatch], row1[kScatBatch];
     float r0[kScatBatch];
-    scat_stage_a<LD>(V, ca, cb, j, lane, a0);
-    scat_stage_a<LD>(V, ca, cb, j + kScatWaves <= jlast ? j + kScatWaves : jlast, lane, a1);
+    scat_stage_a<LD>(V, ca, cb, j, ob, lane, a0);
+    scat_stage_a<LD>(V, ca, cb, j + kScatWaves <= jlast ? j + kScatWaves : jlast, ob, lane, a1);
 #pragma unroll
-    for (int k = 0; k < kScatBatch; ++k) row0[k] = V.ord_row[a0.ord[k]];
+    for (int k = 0; k < kScatBatch; ++k) row0[k] = ord_row[a0.ord[k]];
     for (;;) {
       const int64_t j1 = j + kScatWaves, j2 = j + 2 * kScatWaves;
 #pragma unroll
-      for (int k = 0; k < kScatBatch; ++k) r0[k] = V.rvals[row0[k]];
+      for (int k = 0; k < kScatBatch; ++k) r0[k] = rvals[row0[k]];
 #pragma unroll
-      for (int k = 0; k < kScatBatch; ++k) row1[k] = V.ord_row[a1.ord[k]];
-      scat_stage_a<LD>(V, ca, cb, j2 <= jlast ? j2 : jlast, lane, a2);
+      for (int k = 0; k < kScatBatch; ++k) row1[k] = ord_row[a1.ord[k]];
+      scat_stage_a<LD>(V, ca, cb, j2 <= jlast ? j2 : jlast, ob, lane, a2);
 #pragma unroll
       for (int k = 0; k < kScatBatch; ++k) {
         const uint32_t v = a0.v[k];
@@ -693,7 +714,7 @@ __global__ void __launch_bounds__(kScatThreads) k_plan_scatter(PlanView V, int64
         const int loc = (int)((v >> 2) & (kTileVox - 1));
         const float val = r0[k] * a0.l[k];
         if (fabsf(val) < kFixBig)
-          atomicAdd(&s_num[loc], (unsigned long long)(long long)rintf(val * fix_scale));
+          atomicAdd(&s_num[loc], fixed_point(val, hi_scale));
         else
           atomicAdd(&s_big[loc], val);
         atomicAdd(&s_cnt[loc], 1u);
@@ -836,13 +857,13 @@ hipError_t launch_plan_scatter(const PlanView &V, int64_t b, float *x, const uin
                                hipStream_t s) {
   if (V.T <= 0) return hipSuccess;
   const int k = fix_exponent(V.B);
-  const float scale = std::ldexp(1.0f, k), unscale = std::ldexp(1.0f, -k);
+  const float hi_scale = std::ldexp(1.0f, k - 32), unscale = std::ldexp(1.0f, -k);
   if (V.len_dtype == 0)
     hipLaunchKernelGGL(k_plan_scatter<0>, dim3((unsigned)V.T), dim3(kScatThreads), 0, s, V, b, x, mask, lambda,
-                       scale, unscale);
+                       hi_scale, unscale);
   else
     hipLaunchKernelGGL(k_plan_scatter<1>, dim3((unsigned)V.T), dim3(kScatThreads), 0, s, V, b, x, mask, lambda,
-                       scale, unscale);
+                       hi_scale, unscale);
   return hipGetLastError();
 }
 
