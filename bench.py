@@ -406,15 +406,17 @@ def main():
         ps = plan.struct
         lbp = 4 if ps.len_dtype == 0 else 2
         # algorithmic bytes per launch (one block): the dot streams the block's
-        # layout-A entries (2 B code + length), 8 B per chunk (first piece-end
+        # list entries (2 B code + length), 8 B per chunk (first piece-end
         # ordinal), reads each piece end's row slot and writes its partial
-        # (4 + 4 B) and reads x once (4 B/voxel); the scatter streams the
-        # layout-B entries (4 B code + length), reads r per piece end (4 B)
-        # and reads and writes x (8 B/voxel)
+        # (4 + 4 B) and reads x once (4 B/voxel); the scatter streams the same
+        # entries, 16 B per chunk (piece-end mask + first ordinal), reads the
+        # row of each piece end (4 B) and r of each row (4 B), and reads and
+        # writes x (8 B/voxel)
         ends_pb = ps.ends / n_blocks
         models["plan_dot"] = ("hbm", ((2 + lbp) * ps.entries + 8 * ps.chunks) / n_blocks + 8 * ends_pb + 4 * M,
                               HBM_PEAK_GBS, "GB/s", "pct::k_plan_dot<1, false>" if lbp == 2 else "pct::k_plan_dot<0, false>")
-        models["plan_scatter"] = ("hbm", (4 + lbp) * nnz / n_blocks + 4 * ends_pb + 8 * M, HBM_PEAK_GBS, "GB/s",
+        models["plan_scatter"] = ("hbm", ((2 + lbp) * ps.entries + 16 * ps.chunks) / n_blocks + 4 * ends_pb
+                                  + 4 * cfg.block + 8 * M, HBM_PEAK_GBS, "GB/s",
                                   "pct::k_plan_scatter<1>" if lbp == 2 else "pct::k_plan_scatter<0>")
     if rows is not None and plan is None:
         models["project"] = ("hbm", ((4 + lb) * nnz + (16 + 8 + 8 + 4) * N) / n_blocks + 20 * M, HBM_PEAK_GBS,
@@ -592,6 +594,8 @@ def main():
             "nnz_per_history": round((nnz if nnz else nnz_est) / N, 2),
             "time_to_image_s": round(ms_per_step / 1e3, 3),
             "trace_ms": round(trace_ms, 3), "plan_ms": round(plan_ms, 3), "sweep_ms": round(sweep_ms, 3),
+            "rows_bytes": (int(rows.nnz) * (4 + (4 if rows.len_dtype == 0 else 2)) + 16 * N) if rows is not None else None,
+            "plan_bytes": int(plan.struct.bytes) if plan is not None else None,
             "sweep_only_hist_per_s": round(N / (sweep_ms / 1e3), 1) if sweep_ms > 0 else None,
             "residual_ms": round(residual_ms, 3),
             "kernel_ms": {k: [v[0], round(v[1], 3)] for k, v in prof.items()},
