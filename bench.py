@@ -745,10 +745,11 @@ def tvs_study(args):
 
 def cnn_timing(args):
     """Device time of the warm-start network on one 200 x 200 x 40 volume
-    (channels --ws-channels): inference, one training step, and each
-    convolution shape of the network's first three levels (forward, input
-    gradient, weight gradient) with its FP32 throughput (2 flops per
-    multiply-add of the 3x3x3 contraction).  Prints one JSON line."""
+    (channels --ws-channels): inference and one training step in FP32 and
+    with the bfloat16 matrix-core convolutions, and each convolution shape of
+    the network's first three levels (forward, input gradient, weight
+    gradient; the first two also on the matrix cores) with its throughput (2
+    flops per multiply-add of the 3x3x3 contraction).  Prints one JSON line."""
     import numpy as np
     import torch
 
@@ -763,6 +764,7 @@ def cnn_timing(args):
     D, H, W = 40, 200, 200
     channels = tuple(int(c) for c in args.ws_channels.split(","))
     net = cnn.UNet3D(channels, device=dev, seed=0)
+    net16 = cnn.UNet3D(channels, device=dev, seed=0, precision="bf16")
     rng = np.random.default_rng(0)
     x = torch.from_numpy(rng.uniform(0, 1.8, size=(1, D, H, W)).astype(np.float32)).to(dev)
     t = torch.from_numpy(rng.uniform(0, 1.8, size=(1, D, H, W)).astype(np.float32)).to(dev)
@@ -779,7 +781,9 @@ def cnn_timing(args):
     out = {"metric": "warm-start network device time", "unit": "ms", "n_gpus": 1, "dtype": "f32",
            "config": {"workload": f"one {W}x{H}x{D} volume, channels {list(channels)}"},
            "inference_ms": round(ms(lambda: net.predict(x), args.steps * 3), 3),
-           "train_step_ms": round(ms(lambda: net.train_step(x, t, 1e-4), args.steps * 3), 3), "conv": []}
+           "train_step_ms": round(ms(lambda: net.train_step(x, t, 1e-4), args.steps * 3), 3),
+           "bf16_inference_ms": round(ms(lambda: net16.predict(x), args.steps * 3), 3),
+           "bf16_train_step_ms": round(ms(lambda: net16.train_step(x, t, 1e-4), args.steps * 3), 3), "conv": []}
     dims = (D, H, W)
     for lvl, c in enumerate(channels[:3]):
         a = torch.from_numpy(rng.normal(size=(c,) + dims).astype(np.float32)).to(dev)
@@ -794,10 +798,21 @@ def cnn_timing(args):
         f = ms(lambda: cnn.conv3d(a, w, b, y), args.steps * 5)
         bd = ms(lambda: cnn.conv3d_bwd_data(y, w, dx, wt), args.steps * 5)
         bw = ms(lambda: cnn.conv3d_bwd_weight(a, y, dw, db, sc), args.steps * 5)
-        out["conv"].append({"level": lvl, "shape": f"{c}->{c} on {dims[2]}x{dims[1]}x{dims[0]}",
-                            "fwd_ms": round(f, 4), "bwd_data_ms": round(bd, 4), "bwd_weight_ms": round(bw, 4),
-                            "fwd_tflops": round(flops / f / 1e9, 2), "bwd_data_tflops": round(flops / bd / 1e9, 2),
-                            "bwd_weight_tflops": round(flops / bw / 1e9, 2)})
+        wp = torch.empty(max(cnn.bf16_scratch(c, c), 1), dtype=torch.uint8, device=dev)
+        rec = {"level": lvl, "shape": f"{c}->{c} on {dims[2]}x{dims[1]}x{dims[0]}",
+               "fwd_ms": round(f, 4), "bwd_data_ms": round(bd, 4), "bwd_weight_ms": round(bw, 4),
+               "fwd_tflops": round(flops / f / 1e9, 2), "bwd_data_tflops": round(flops / bd / 1e9, 2),
+               "bwd_weight_tflops": round(flops / bw / 1e9, 2)}
+        if cnn.bf16_scratch(c, c):
+            f16 = ms(lambda: cnn.conv3d(a, w, b, y, wpack=wp), args.steps * 5)
+            bd16 = ms(lambda: cnn.conv3d_bwd_data(y, w, dx, wt, wpack=wp), args.steps * 5)
+            # per launch: x read once (4 B/value) and y written once (4 B/value)
+            hbm = 8.0 * c * dims[0] * dims[1] * dims[2]
+            rec.update({"bf16_fwd_ms": round(f16, 4), "bf16_bwd_data_ms": round(bd16, 4),
+                        "bf16_fwd_tflops": round(flops / f16 / 1e9, 2),
+                        "bf16_fwd_frac_of_mfma_peak": round(flops / f16 / 1e9 / 2500.0, 4),
+                        "bf16_fwd_hbm_GBps": round(hbm / f16 / 1e6, 1)})
+        out["conv"].append(rec)
         dims = tuple(d // 2 for d in dims)
     print(json.dumps(out), flush=True)
 

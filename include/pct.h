@@ -411,6 +411,19 @@ pct_status pct_cnn_conv3d(const float *x, const float *w, const float *b, float 
  * cin * cout * 27 floats */
 pct_status pct_cnn_conv3d_bwd_data(const float *dy, const float *w, float *dx, float *wt, int32_t cin, int32_t cout,
                                    int32_t D, int32_t H, int32_t W, void *stream);
+/* The same two operations on the matrix cores (v_mfma_f32_16x16x32_bf16):
+ * inputs and weights rounded to bfloat16 (nearest, ties to even), products
+ * accumulated in FP32, the result stored as FP32; for networks whose
+ * activations the warm start (Sec. 2.1's x0) may hold at bfloat16 precision.
+ * pct_cnn_conv3d_bf16 needs cin % 8 == 0 and cout % 16 == 0, the input
+ * gradient cout % 8 == 0 and cin % 16 == 0 (else PCT_EINVAL).  wpack: device
+ * scratch of pct_cnn_conv3d_bf16_scratch(cin, cout) bytes (0 for a shape
+ * they do not take) for the packed bfloat16 weights; wt as above. */
+int64_t pct_cnn_conv3d_bf16_scratch(int32_t cin, int32_t cout);
+pct_status pct_cnn_conv3d_bf16(const float *x, const float *w, const float *b, float *y, void *wpack, int32_t cin,
+                               int32_t cout, int32_t D, int32_t H, int32_t W, void *stream);
+pct_status pct_cnn_conv3d_bwd_data_bf16(const float *dy, const float *w, float *dx, float *wt, void *wpack,
+                                        int32_t cin, int32_t cout, int32_t D, int32_t H, int32_t W, void *stream);
 /* floats of scratch that pct_cnn_conv3d_bwd_weight needs */
 int64_t pct_cnn_wgrad_scratch(int32_t cin, int32_t cout, int32_t D, int32_t H, int32_t W);
 /* weight gradient dw [cout][cin][27] and bias gradient db [cout] (or NULL)

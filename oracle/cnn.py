@@ -110,6 +110,37 @@ def adam(w, g, m, v, lr, b1, b2, eps, step):
 
 
 # ---------------------------------------------------------------- network
+def bf16_round(a):
+    """a rounded to float32, then to bfloat16 (round to nearest, ties to even:
+    the high 16 bits of the float32 after adding 0x7fff plus the lowest kept
+    bit), returned as float64.  The matrix-core form of the convolution takes
+    its operands at this precision (finite values only here)."""
+    f = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def mfma_forward_ok(cin, cout):
+    """Shapes the matrix-core convolution takes (input channels in groups of
+    eight, output channels in tiles of sixteen)."""
+    return cin % 8 == 0 and cout % 16 == 0
+
+
+def _conv(x, w, b, bf16):
+    cout, cin = w.shape[0], w.shape[1]
+    if bf16 and mfma_forward_ok(cin, cout):
+        return conv3d(bf16_round(x), bf16_round(w), b)
+    return conv3d(x, w, b)
+
+
+def _conv_bwd_data(g, w, bf16):
+    cout, cin = w.shape[0], w.shape[1]
+    if bf16 and mfma_forward_ok(cout, cin):  # the adjoint is a convolution from cout to cin channels
+        return conv3d_bwd_data(bf16_round(g), bf16_round(w))
+    return conv3d_bwd_data(g, w)
+
+
 def unet_layers(channels, in_ch=1):
     """Convolution shapes (cin, cout) in order: encoder levels 0..L-1 (two
     each; the second one of the deepest level maps back to channels[L-2]),
@@ -139,36 +170,39 @@ def unet_init(channels, seed, in_ch=1):
     return params
 
 
-def unet_forward(params, x, channels):
+def unet_forward(params, x, channels, bf16=False):
     """x [in_ch][D][H][W] -> (output [1][D][H][W], tape).  Encoder level l:
     conv, relu, conv, relu (kept for the skip), pool to the next level.
     Decoder level l (from L-2 down to 0): upsample, add the level's encoder
     output, conv, relu, conv (+ relu except at level 0).  Output = the last
-    input channel + last conv."""
+    input channel + last conv.  bf16: the convolutions that the matrix-core
+    form takes see their operands rounded to bfloat16."""
     L = len(channels)
     tape = {}
     h = x
     skips = []
     k = 0
     for lvl in range(L):
-        a1 = relu(conv3d(h, *params[k])); k += 1
-        a2 = relu(conv3d(a1, *params[k])); k += 1
+        a1 = relu(_conv(h, *params[k], bf16)); k += 1
+        a2 = relu(_conv(a1, *params[k], bf16)); k += 1
         tape[("enc", lvl)] = (h, a1, a2)
         skips.append(a2)
         h = pool(a2) if lvl < L - 1 else a2
     for lvl in range(L - 2, -1, -1):
         u = upsample(h)
         s = u + skips[lvl]
-        a1 = relu(conv3d(s, *params[k])); k += 1
-        z2 = conv3d(a1, *params[k]); k += 1
+        a1 = relu(_conv(s, *params[k], bf16)); k += 1
+        z2 = _conv(a1, *params[k], bf16); k += 1
         a2 = relu(z2) if lvl > 0 else z2
         tape[("dec", lvl)] = (s, a1, a2)
         h = a2
     return x[-1:] + h, tape
 
 
-def unet_backward(params, x, channels, tape, dout):
-    """Gradients of the parameters (list of (dw, db)) given dL/d(output)."""
+def unet_backward(params, x, channels, tape, dout, bf16=False):
+    """Gradients of the parameters (list of (dw, db)) given dL/d(output).
+    bf16: the input gradients that the matrix-core form takes see their
+    operands rounded to bfloat16 (weight gradients stay exact)."""
     L = len(channels)
     grads = [None] * len(params)
     k = len(params)
@@ -179,9 +213,9 @@ def unet_backward(params, x, channels, tape, dout):
         k -= 2
         gz2 = relu_bwd(a2, g) if lvl > 0 else g
         grads[k + 1] = conv3d_bwd_weight(a1, gz2)
-        ga1 = relu_bwd(a1, conv3d_bwd_data(gz2, params[k + 1][0]))
+        ga1 = relu_bwd(a1, _conv_bwd_data(gz2, params[k + 1][0], bf16))
         grads[k] = conv3d_bwd_weight(s, ga1)
-        gs = conv3d_bwd_data(ga1, params[k][0])
+        gs = _conv_bwd_data(ga1, params[k][0], bf16)
         dskips[lvl] += gs
         g = upsample_bwd(gs)  # gradient of the deeper level's output
     # g now is the gradient of the bottleneck output (encoder level L-1's a2)
@@ -192,7 +226,7 @@ def unet_backward(params, x, channels, tape, dout):
         k -= 2
         gz2 = relu_bwd(a2, g)
         grads[k + 1] = conv3d_bwd_weight(a1, gz2)
-        ga1 = relu_bwd(a1, conv3d_bwd_data(gz2, params[k + 1][0]))
+        ga1 = relu_bwd(a1, _conv_bwd_data(gz2, params[k + 1][0], bf16))
         grads[k] = conv3d_bwd_weight(h, ga1)
-        g = conv3d_bwd_data(ga1, params[k][0])  # gradient of this level's input
+        g = _conv_bwd_data(ga1, params[k][0], bf16)  # gradient of this level's input
     return grads

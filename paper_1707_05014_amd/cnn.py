@@ -38,25 +38,51 @@ def _dhw(t: torch.Tensor):
 
 
 # ----------------------------------------------------------- entry points
-def conv3d(x, w, b, y, stream=None):
-    """y = b + w (*) x (3x3x3, zero padding); x [cin][D][H][W], w [cout][cin][3][3][3]."""
+def bf16_scratch(cin, cout) -> int:
+    """Bytes of packed-weight scratch the bfloat16 matrix-core convolution
+    needs for (cin, cout); 0 when it does not take that shape (cin % 8 or
+    cout % 16 not 0)."""
+    return int(_lib.load().pct_cnn_conv3d_bf16_scratch(int(cin), int(cout)))
+
+
+def _scratch(t: torch.Tensor, nbytes: int, name: str) -> int:
+    if not (t.is_cuda and t.is_contiguous()) or t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{name} must be a contiguous device tensor of at least {nbytes} bytes")
+    return int(t.data_ptr())
+
+
+def conv3d(x, w, b, y, stream=None, wpack=None):
+    """y = b + w (*) x (3x3x3, zero padding); x [cin][D][H][W], w [cout][cin][3][3][3].
+    With wpack (device scratch of bf16_scratch(cin, cout) bytes) the matrix
+    cores compute it from bfloat16-rounded x and w, accumulating in FP32."""
     cout, cin = int(w.shape[0]), int(w.shape[1])
     D, H, W = _dhw(x)
     if x.shape != (cin, D, H, W) or y.shape != (cout, D, H, W) or (b is not None and b.numel() != cout):
         raise ValueError("conv3d: shapes do not match")
-    check(_lib.load().pct_cnn_conv3d(_dev(x, "x"), _dev(w, "w"), None if b is None else _dev(b, "b"), _dev(y, "y"),
-                                     cin, cout, D, H, W, _s(stream)))
+    bp = None if b is None else _dev(b, "b")
+    if wpack is not None:
+        check(_lib.load().pct_cnn_conv3d_bf16(_dev(x, "x"), _dev(w, "w"), bp, _dev(y, "y"),
+                                              _scratch(wpack, bf16_scratch(cin, cout), "wpack"), cin, cout, D, H, W,
+                                              _s(stream)))
+    else:
+        check(_lib.load().pct_cnn_conv3d(_dev(x, "x"), _dev(w, "w"), bp, _dev(y, "y"), cin, cout, D, H, W, _s(stream)))
     return y
 
 
-def conv3d_bwd_data(dy, w, dx, wt, stream=None):
-    """dx [cin] = adjoint of the convolution applied to dy [cout]; wt: cin*cout*27 floats of scratch."""
+def conv3d_bwd_data(dy, w, dx, wt, stream=None, wpack=None):
+    """dx [cin] = adjoint of the convolution applied to dy [cout]; wt: cin*cout*27 floats of scratch.
+    With wpack (bf16_scratch(cout, cin) bytes) on the matrix cores, as conv3d."""
     cout, cin = int(w.shape[0]), int(w.shape[1])
     D, H, W = _dhw(dy)
     if dy.shape != (cout, D, H, W) or dx.shape != (cin, D, H, W) or wt.numel() < cin * cout * 27:
         raise ValueError("conv3d_bwd_data: shapes do not match")
-    check(_lib.load().pct_cnn_conv3d_bwd_data(_dev(dy, "dy"), _dev(w, "w"), _dev(dx, "dx"), _dev(wt, "wt"), cin, cout,
-                                              D, H, W, _s(stream)))
+    if wpack is not None:
+        check(_lib.load().pct_cnn_conv3d_bwd_data_bf16(_dev(dy, "dy"), _dev(w, "w"), _dev(dx, "dx"), _dev(wt, "wt"),
+                                                       _scratch(wpack, bf16_scratch(cout, cin), "wpack"), cin, cout,
+                                                       D, H, W, _s(stream)))
+    else:
+        check(_lib.load().pct_cnn_conv3d_bwd_data(_dev(dy, "dy"), _dev(w, "w"), _dev(dx, "dx"), _dev(wt, "wt"), cin,
+                                                  cout, D, H, W, _s(stream)))
     return dx
 
 
@@ -198,9 +224,18 @@ def layer_shapes(channels, in_channels=1):
 
 class UNet3D:
     """Parameters live in one flat float32 device buffer (weights then bias
-    per layer), so gradients and the Adam moments are single buffers too."""
+    per layer), so gradients and the Adam moments are single buffers too.
+    precision "bf16": the convolutions and their input gradients that the
+    matrix-core kernels take (cin % 8 == 0, cout % 16 == 0) run there on
+    bfloat16-rounded operands with FP32 accumulation; weight gradients,
+    activations and parameters stay FP32."""
 
-    def __init__(self, channels=(16, 32, 64, 64), device="cuda", seed: int = 0, in_channels: int = 1):
+    def __init__(self, channels=(16, 32, 64, 64), device="cuda", seed: int = 0, in_channels: int = 1,
+                 precision: str = "f32"):
+        if precision not in ("f32", "bf16"):
+            raise ValueError("precision is 'f32' or 'bf16'")
+        self.precision = precision
+        self._wpack = None
         self.channels = tuple(int(c) for c in channels)
         if len(self.channels) < 2 or min(self.channels) < 1 or in_channels < 1:
             raise ValueError("the network needs at least two levels of positive channel counts")
@@ -283,6 +318,17 @@ class UNet3D:
     def _empty(self, c, dhw):
         return torch.empty((c,) + tuple(dhw), dtype=torch.float32, device=self.device)
 
+    def _pack(self, cin, cout):
+        """Packed-weight scratch for a matrix-core convolution of (cin, cout),
+        or None (FP32 kernels) in FP32 precision or for a shape they do not take."""
+        if self.precision != "bf16" or bf16_scratch(cin, cout) == 0:
+            return None
+        if self._wpack is None:
+            need = max([bf16_scratch(ci, co) for ci, co in self.shapes] +
+                       [bf16_scratch(co, ci) for ci, co in self.shapes])
+            self._wpack = torch.empty(max(need, 1), dtype=torch.uint8, device=self.device)
+        return self._wpack
+
     def forward(self, x: torch.Tensor, keep: bool = False, stream=None) -> torch.Tensor:
         """Output [1][D][H][W] = last input channel + network; with keep=True
         the activations are kept for backward()."""
@@ -294,11 +340,11 @@ class UNet3D:
         for l in range(self.L):
             c1 = self.shapes[k][1]
             z1 = self._empty(c1, dims)
-            conv3d(h, self.w[k], self.b[k], z1, stream)
+            conv3d(h, self.w[k], self.b[k], z1, stream, wpack=self._pack(*self.shapes[k]))
             relu(z1, z1, stream)
             c2 = self.shapes[k + 1][1]
             z2 = self._empty(c2, dims)
-            conv3d(z1, self.w[k + 1], self.b[k + 1], z2, stream)
+            conv3d(z1, self.w[k + 1], self.b[k + 1], z2, stream, wpack=self._pack(*self.shapes[k + 1]))
             relu(z2, z2, stream)
             enc.append((h, z1, z2))
             k += 2
@@ -318,11 +364,11 @@ class UNet3D:
             add(s, skip, s, stream)
             c1 = self.shapes[k][1]
             z1 = self._empty(c1, dims)
-            conv3d(s, self.w[k], self.b[k], z1, stream)
+            conv3d(s, self.w[k], self.b[k], z1, stream, wpack=self._pack(*self.shapes[k]))
             relu(z1, z1, stream)
             c2 = self.shapes[k + 1][1]
             z2 = self._empty(c2, dims)
-            conv3d(z1, self.w[k + 1], self.b[k + 1], z2, stream)
+            conv3d(z1, self.w[k + 1], self.b[k + 1], z2, stream, wpack=self._pack(*self.shapes[k + 1]))
             if l > 0:
                 relu(z2, z2, stream)
             dec.append((s, z1, z2))
@@ -354,7 +400,7 @@ class UNet3D:
             if k == 0:
                 return None
             gi = self._empty(cin, tuple(int(s) for s in inp.shape[1:]))
-            conv3d_bwd_data(g, self.w[k], gi, wt, stream)
+            conv3d_bwd_data(g, self.w[k], gi, wt, stream, wpack=self._pack(cout, cin))
             return gi
 
         k = len(self.shapes)

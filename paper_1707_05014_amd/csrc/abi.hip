@@ -1262,6 +1262,34 @@ pct_status pct_cnn_conv3d_bwd_data(const float *dy, const float *w, float *dx, f
   return PCT_OK;
 }
 
+int64_t pct_cnn_conv3d_bf16_scratch(int32_t cin, int32_t cout) {
+  return pct::cnn::mfma_shape_ok(cin, cout) ? pct::cnn::mfma_pack_bytes(cin, cout) : 0;
+}
+
+pct_status pct_cnn_conv3d_bf16(const float *x, const float *w, const float *b, float *y, void *wpack, int32_t cin,
+                               int32_t cout, int32_t D, int32_t H, int32_t W, void *stream) {
+  g_err.clear();
+  CNN_VOL_CHECK(cin, D, H, W);
+  if (!pct::cnn::mfma_shape_ok(cin, cout))
+    return fail(PCT_EINVAL, "bf16 convolution needs cin %% 8 == 0 and cout %% 16 == 0 (got %d, %d)", cin, cout);
+  if (!x || !w || !y || !wpack) return fail(PCT_EINVAL, "NULL tensor");
+  HIPCHECK(pct::cnn::conv3d_mfma(x, w, b, y, wpack, cin, cout, D, H, W, reinterpret_cast<hipStream_t>(stream)));
+  return PCT_OK;
+}
+
+pct_status pct_cnn_conv3d_bwd_data_bf16(const float *dy, const float *w, float *dx, float *wt, void *wpack,
+                                        int32_t cin, int32_t cout, int32_t D, int32_t H, int32_t W, void *stream) {
+  g_err.clear();
+  CNN_VOL_CHECK(cin, D, H, W);
+  if (!pct::cnn::mfma_shape_ok(cout, cin))
+    return fail(PCT_EINVAL, "bf16 input gradient needs cout %% 8 == 0 and cin %% 16 == 0 (got %d, %d)", cin, cout);
+  if (!dy || !w || !dx || !wt || !wpack) return fail(PCT_EINVAL, "NULL tensor");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIPCHECK(pct::cnn::flip_weights(w, wt, cin, cout, s));
+  HIPCHECK(pct::cnn::conv3d_mfma(dy, wt, nullptr, dx, wpack, cout, cin, D, H, W, s));
+  return PCT_OK;
+}
+
 int64_t pct_cnn_wgrad_scratch(int32_t cin, int32_t cout, int32_t D, int32_t H, int32_t W) {
   if (cin <= 0 || cout <= 0 || D <= 0 || H <= 0 || W <= 0) return 0;
   return pct::cnn::wgrad_chunks(D, H, W) * cout * ((int64_t)cin * 27 + 1);

@@ -356,6 +356,138 @@ __global__ void __launch_bounds__(kThreads) k_adam(float *__restrict__ w, const 
   w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// ---- BF16 matrix-core form of the convolution (cin % 8 == 0, cout % 16 == 0)
+//
+// Implicit GEMM: y[co][p] = b[co] + sum_k A[co][k] B[k][p] with k = (tap,
+// input channel).  One v_mfma_f32_16x16x32_bf16 takes 16 output channels x 16
+// voxels (consecutive along W) x 32 values of k: the four lane groups (lane /
+// 16) take four consecutive entries q of the list of (tap, group of eight
+// input channels) pairs, taps outer, eight channels each.  Lane l supplies
+// row l % 16 of A and column l % 16 of B, and receives rows 4 (l / 16) + i of
+// column l % 16 of the product (fixed by the instruction; the K order only has
+// to be the same in A and B).  Inputs and weights are rounded to bfloat16
+// (nearest, ties to even); products are accumulated in FP32.
+//
+// A workgroup takes a tile of 16 x kMTH x kMTD voxels (W x H x D) and up to
+// NMT x 16 output channels; per pass over kMChunk input channels it stages the
+// tile's halo in LDS as bfloat16, channels fastest, with a voxel stride of
+// 2 * chunk + 16 bytes (so that the 16-byte reads of eight consecutive voxels
+// fall in different banks); a lane's B operand is then one 16-byte LDS read.
+// Voxels of the halo outside the volume hold 0 (zero padding).  Weights are
+// packed beforehand (k_pack_mfma_weights) so that a lane's A operand is one
+// 16-byte load.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMTW = 16, kMTH = 4, kMTD = 2;  // tile (W x H x D): 8 rows of 16 voxels
+constexpr int kMWaves = 4;                    // wavefronts per workgroup, two rows each
+constexpr int kMRowsPerWave = kMTH * kMTD / kMWaves;
+constexpr int kMHW = kMTW + 2, kMHH = kMTH + 2, kMHD = kMTD + 2;
+constexpr int kMHalo = kMHW * kMHH * kMHD;  // 432 voxels
+constexpr int kMChunk = 32;                 // input channels staged per pass
+constexpr int kMStride = 2 * kMChunk + 16;  // bytes per halo voxel in LDS
+
+// float -> bfloat16, round to nearest, ties to even (NaN stays NaN)
+__device__ __forceinline__ uint32_t bf16_rne(float f) {
+  const uint32_t u = __builtin_bit_cast(uint32_t, f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+// wp[(q * cout + co) * 8 + j] = bf16(w[co][8 c8 + j][t]) with q = t * (cin / 8) + c8
+__global__ void __launch_bounds__(kThreads) k_pack_mfma_weights(const float *__restrict__ w, uint16_t *__restrict__ wp,
+                                                                int cin, int cout) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t n = (int64_t)cin * cout * kTaps;
+  if (i >= n) return;
+  const int j = (int)(i % 8);
+  const int64_t r = i / 8;
+  const int co = (int)(r % cout);
+  const int64_t q = r / cout;
+  const int c8n = cin / 8;
+  const int t = (int)(q / c8n), c8 = (int)(q % c8n);
+  wp[i] = (uint16_t)bf16_rne(w[((int64_t)co * cin + 8 * c8 + j) * kTaps + t]);
+}
+
+template <int NMT>
+__global__ void __launch_bounds__(kMWaves * 64) k_conv3d_mfma(const float *__restrict__ x,
+                                                              const uint16_t *__restrict__ wp,
+                                                              const float *__restrict__ b, float *__restrict__ y,
+                                                              int cin, int cout, int D, int H, int W, int tiles_w,
+                                                              int tiles_h) {
+  __shared__ __attribute__((aligned(16))) unsigned char s_x[kMHalo * kMStride];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int g = lane >> 4, n = lane & 15;
+  const int tile = blockIdx.x;
+  const int w0 = (tile % tiles_w) * kMTW, h0 = ((tile / tiles_w) % tiles_h) * kMTH, d0 = tile / (tiles_w * tiles_h) * kMTD;
+  const int co0 = blockIdx.y * NMT * 16;
+  const int64_t V = (int64_t)D * H * W;
+  f32x4 acc[NMT][kMRowsPerWave];
+#pragma unroll
+  for (int m = 0; m < NMT; ++m)
+#pragma unroll
+    for (int r = 0; r < kMRowsPerWave; ++r) acc[m][r] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int c0 = 0; c0 < cin; c0 += kMChunk) {
+    const int c8n = (cin - c0 < kMChunk ? cin - c0 : kMChunk) / 8;
+    // stage the halo: task (c8, hv), hv fastest
+    for (int task = threadIdx.x; task < c8n * kMHalo; task += kMWaves * 64) {
+      const int c8 = task / kMHalo, hv = task % kMHalo;
+      const int hx = hv % kMHW, hy = (hv / kMHW) % kMHH, hz = hv / (kMHW * kMHH);
+      const int xw = w0 + hx - 1, yh = h0 + hy - 1, zd = d0 + hz - 1;
+      const bool in = xw >= 0 && xw < W && yh >= 0 && yh < H && zd >= 0 && zd < D;
+      const float *xc = x + (int64_t)(c0 + 8 * c8) * V + (in ? ((int64_t)zd * H + yh) * W + xw : 0);
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = xc[j * V];
+      u32x4 pk;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) pk[j] = in ? (bf16_rne(v[2 * j]) | (bf16_rne(v[2 * j + 1]) << 16)) : 0u;
+      *reinterpret_cast<u32x4 *>(s_x + hv * kMStride + c8 * 16) = pk;
+    }
+    __syncthreads();
+    const int nq = kTaps * c8n;
+    for (int q0 = 0; q0 < nq; q0 += 4) {
+      const int q = q0 + g;
+      const bool qv = q < nq;
+      const int t = qv ? q / c8n : 0, c8 = qv ? q % c8n : 0;
+      const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+      bf16x8 bfr[kMRowsPerWave];
+#pragma unroll
+      for (int r = 0; r < kMRowsPerWave; ++r) {
+        const int row = wid * kMRowsPerWave + r, rh = row % kMTH, rd = row / kMTH;
+        const int hv = ((rd + 1 + dz) * kMHH + (rh + 1 + dy)) * kMHW + (n + 1 + dx);
+        bfr[r] = *reinterpret_cast<const bf16x8 *>(s_x + hv * kMStride + c8 * 16);
+      }
+      const int64_t kq = (int64_t)t * (cin / 8) + c0 / 8 + c8;  // (tap, channel group) in the packed weights
+#pragma unroll
+      for (int m = 0; m < NMT; ++m) {
+        const int co = co0 + m * 16 + n;
+        bf16x8 afr = {};
+        if (qv && co < cout) afr = *reinterpret_cast<const bf16x8 *>(wp + (kq * cout + co) * 8);
+#pragma unroll
+        for (int r = 0; r < kMRowsPerWave; ++r)
+          acc[m][r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[r], acc[m][r], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < kMRowsPerWave; ++r) {
+    const int row = wid * kMRowsPerWave + r;
+    const int xw = w0 + n, yh = h0 + row % kMTH, zd = d0 + row / kMTH;
+    if (xw >= W || yh >= H || zd >= D) continue;
+    const int64_t p = ((int64_t)zd * H + yh) * W + xw;
+#pragma unroll
+    for (int m = 0; m < NMT; ++m)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int co = co0 + m * 16 + 4 * g + i;
+        if (co < cout) y[(int64_t)co * V + p] = acc[m][r][i] + (b ? b[co] : 0.0f);
+      }
+  }
+}
+
 static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 hipError_t conv3d(const float *x, const float *w, const float *b, float *y, int cin, int cout, int D, int H, int W,
@@ -372,6 +504,32 @@ hipError_t conv3d(const float *x, const float *w, const float *b, float *y, int 
     hipLaunchKernelGGL(k_conv3d<1>, dim3(blocks_for(V), (unsigned)cout), dim3(kThreads), 0, s, x, w, b, y, cin, cout,
                        D, H, W);
   }
+  return hipGetLastError();
+}
+
+bool mfma_shape_ok(int cin, int cout) { return cin > 0 && cout > 0 && cin % 8 == 0 && cout % 16 == 0; }
+
+int64_t mfma_pack_bytes(int cin, int cout) { return (int64_t)cin * cout * kTaps * 2; }
+
+hipError_t conv3d_mfma(const float *x, const float *w, const float *b, float *y, void *wpack, int cin, int cout,
+                       int D, int H, int W, hipStream_t s) {
+  const int64_t V = (int64_t)D * H * W;
+  if (V <= 0) return hipSuccess;
+  uint16_t *wp = static_cast<uint16_t *>(wpack);
+  const int64_t nw = (int64_t)cin * cout * kTaps;
+  hipLaunchKernelGGL(k_pack_mfma_weights, dim3(blocks_for(nw)), dim3(kThreads), 0, s, w, wp, cin, cout);
+  const int tw = (W + kMTW - 1) / kMTW, th = (H + kMTH - 1) / kMTH, td = (D + kMTD - 1) / kMTD;
+  const unsigned tiles = (unsigned)((int64_t)tw * th * td);
+  const int mt = cout / 16;
+  if (mt % 4 == 0)
+    hipLaunchKernelGGL(k_conv3d_mfma<4>, dim3(tiles, (unsigned)(mt / 4)), dim3(kMWaves * 64), 0, s, x, wp, b, y, cin,
+                       cout, D, H, W, tw, th);
+  else if (mt % 2 == 0)
+    hipLaunchKernelGGL(k_conv3d_mfma<2>, dim3(tiles, (unsigned)(mt / 2)), dim3(kMWaves * 64), 0, s, x, wp, b, y, cin,
+                       cout, D, H, W, tw, th);
+  else
+    hipLaunchKernelGGL(k_conv3d_mfma<1>, dim3(tiles, (unsigned)mt), dim3(kMWaves * 64), 0, s, x, wp, b, y, cin, cout,
+                       D, H, W, tw, th);
   return hipGetLastError();
 }
 

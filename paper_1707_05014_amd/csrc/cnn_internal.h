@@ -10,6 +10,12 @@ namespace cnn {
 hipError_t conv3d(const float *x, const float *w, const float *b, float *y, int cin, int cout, int D, int H, int W,
                   hipStream_t s);
 hipError_t flip_weights(const float *w, float *wt, int cin, int cout, hipStream_t s);
+// BF16 matrix-core convolution (cin % 8 == 0, cout % 16 == 0); wpack: scratch
+// of mfma_pack_bytes(cin, cout) bytes for the packed weights
+bool mfma_shape_ok(int cin, int cout);
+int64_t mfma_pack_bytes(int cin, int cout);
+hipError_t conv3d_mfma(const float *x, const float *w, const float *b, float *y, void *wpack, int cin, int cout,
+                       int D, int H, int W, hipStream_t s);
 int64_t wgrad_chunks(int D, int H, int W);
 hipError_t conv3d_wgrad(const float *x, const float *dy, float *dw, float *db, float *part, int cin, int cout, int D,
                         int H, int W, hipStream_t s);

@@ -13,6 +13,23 @@ Shapes are ragged on purpose: voxel counts that are not multiples of the
 256-thread workgroup, extents that leave partial weight-gradient tiles
 (64 voxels along W x 16 rows x 16 planes), output channel counts that leave
 partial channel blocks (1, 6, 17), and a volume one voxel thick.
+
+The matrix-core (bfloat16) convolution is checked against the oracle applied
+to the same operands rounded to bfloat16: products of bfloat16 values are
+exact in FP32, so the same FP32-sum bounds apply.  Its shapes leave partial
+16 x 4 x 2 voxel tiles along every axis, a last pass over fewer than 32
+input channels (40 = 32 + 8), and one, two and four 16-channel output tiles
+per workgroup.  A whole network in bfloat16 cannot follow the oracle's
+bfloat16 network bit for bit: the two round activations that differ in their
+last FP32 bits, a rounding that lands on the other neighbour moves that
+value by 2^-8, and the layers after it then round differently too.  So the
+network is checked by its distance to the exact (FP64, unrounded) oracle
+network: the bfloat16 network on the GPU must be no farther from it than
+twice the oracle's own bfloat16-rounded network (plus 1e-4), output
+correction and every parameter gradient normwise.  (The oracle's own
+bfloat16 network is ~6e-3 from the exact one in its output correction and up
+to ~4e-2 in the gradients of the deepest layers, whose gradients are small;
+a wrong operand or index would put the GPU at O(1).)
 """
 import sys
 
@@ -23,7 +40,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from oracle import cnn as oc  # noqa: E402
-from paper_1707_05014_amd import cnn  # noqa: E402
+from paper_1707_05014_amd import _lib, cnn  # noqa: E402
 
 NORM_TOL = 1e-5
 ELEM_TOL = 3e-5
@@ -226,3 +243,81 @@ def test_coarse_loss_gradient():
     for k, ((dw, db), gw, gb) in enumerate(zip(grads, net.dw, net.db)):
         _check(_host(gw), dw, tol=NET_GRAD_TOL, what=f"layer {k} dw")
         _check(_host(gb), db, tol=NET_GRAD_TOL, what=f"layer {k} db")
+
+
+BF16_SHAPES = [(8, 16, 5, 7, 9), (16, 32, 3, 18, 70), (64, 64, 6, 20, 20), (32, 16, 2, 9, 33), (40, 48, 4, 5, 17)]
+
+
+@pytest.mark.parametrize("shape", BF16_SHAPES)
+def test_conv3d_bf16_forward_and_backward_data(shape):
+    cin, cout, D, H, W = shape
+    _say(f"bf16 conv3d {shape}")
+    r = np.random.default_rng(31)
+    x, w, b = _f32(r.normal(size=(cin, D, H, W))), _f32(r.normal(size=(cout, cin, 3, 3, 3))), _f32(r.normal(size=cout))
+    xq, wq = oc.bf16_round(x), oc.bf16_round(w)
+    y = torch.empty((cout, D, H, W), dtype=torch.float32, device="cuda")
+    wp = torch.empty(cnn.bf16_scratch(cin, cout), dtype=torch.uint8, device="cuda")
+    cnn.conv3d(_dev(x), _dev(w), _dev(b), y, wpack=wp)
+    _check(_host(y), oc.conv3d(xq, wq, b), oc.conv3d(np.abs(xq), np.abs(wq), np.abs(b)), what="bf16 conv3d")
+    cnn.conv3d(_dev(x), _dev(w), None, y, wpack=wp)
+    _check(_host(y), oc.conv3d(xq, wq), oc.conv3d(np.abs(xq), np.abs(wq)), what="bf16 conv3d (no bias)")
+    # it is not the FP32 result: the roundings are there
+    y32 = torch.empty_like(y)
+    cnn.conv3d(_dev(x), _dev(w), None, y32)
+    assert not torch.equal(y, y32)
+    # input gradient (a convolution from cout to cin channels) where that shape is taken
+    if cnn.bf16_scratch(cout, cin):
+        g = _f32(r.normal(size=(cout, D, H, W)))
+        gq = oc.bf16_round(g)
+        dx = torch.empty((cin, D, H, W), dtype=torch.float32, device="cuda")
+        wt = torch.empty(cin * cout * 27, dtype=torch.float32, device="cuda")
+        wp2 = torch.empty(cnn.bf16_scratch(cout, cin), dtype=torch.uint8, device="cuda")
+        cnn.conv3d_bwd_data(_dev(g), _dev(w), dx, wt, wpack=wp2)
+        _check(_host(dx), oc.conv3d_bwd_data(gq, wq), oc.conv3d_bwd_data(np.abs(gq), np.abs(wq)),
+               what="bf16 bwd data")
+
+
+def test_conv3d_bf16_rejects_shapes():
+    _say("bf16 conv3d shape checks")
+    x = torch.zeros((12, 4, 4, 4), dtype=torch.float32, device="cuda")
+    w = torch.zeros((16, 12, 3, 3, 3), dtype=torch.float32, device="cuda")
+    y = torch.empty((16, 4, 4, 4), dtype=torch.float32, device="cuda")
+    wp = torch.empty(1 << 16, dtype=torch.uint8, device="cuda")
+    assert cnn.bf16_scratch(12, 16) == 0 and cnn.bf16_scratch(16, 24) == 0
+    with pytest.raises(_lib.PctError) as ei:
+        cnn.conv3d(x, w, None, y, wpack=wp)
+    assert ei.value.code == _lib.PCT_EINVAL
+
+
+def _rel_err(a, ref):
+    return float(np.linalg.norm(a - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+@pytest.mark.parametrize("channels,dims", [([16, 32, 64, 64], (8, 16, 24)), ([16, 32], (6, 10, 34))])
+def test_network_bf16_forward_backward(channels, dims):
+    _say(f"bf16 network {channels} on {dims}")
+    net = cnn.UNet3D(channels, seed=0, precision="bf16")
+    params = oc.unet_init(channels, seed=41)
+    r = np.random.default_rng(42)
+    params = [(_f32(w), _f32(r.normal(0, 0.05, size=b.shape))) for w, b in params]
+    net.load_params(params)
+    x = _f32(r.uniform(0.0, 1.8, size=(1,) + dims))
+    t = _f32(x + r.normal(0, 0.1, size=(1,) + dims))
+    y64, tape64 = oc.unet_forward(params, x, channels)
+    yq, tapeq = oc.unet_forward(params, x, channels, bf16=True)
+    y = _host(net.forward(_dev(x), keep=True))
+    e_ref, e_gpu = _rel_err(yq - x, y64 - x), _rel_err(y - x, y64 - x)
+    _say(f"  output correction vs exact: oracle bf16 {e_ref:.2e}, GPU bf16 {e_gpu:.2e}, "
+         f"GPU vs oracle bf16 {_rel_err(y - x, yq - x):.2e}")
+    assert e_gpu <= 2 * e_ref + 1e-4
+    _, dy = oc.mse(y64, t)
+    g64 = oc.unet_backward(params, x, channels, tape64, dy)
+    gq = oc.unet_backward(params, x, channels, tapeq, dy, bf16=True)
+    net.backward(_dev(dy))
+    worst = 0.0
+    for k, ((dw, db), (qw, qb), gw, gb) in enumerate(zip(g64, gq, net.dw, net.db)):
+        for got, q, ref, what in ((_host(gw), qw, dw, "dw"), (_host(gb), qb, db, "db")):
+            er, eg = _rel_err(q, ref), _rel_err(got, ref)
+            worst = max(worst, eg)
+            assert eg <= 2 * er + 1e-4, f"layer {k} {what}: GPU {eg:.2e}, oracle bf16 {er:.2e}"
+    _say(f"  worst parameter-gradient error vs exact: {worst:.2e}")

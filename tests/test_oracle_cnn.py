@@ -181,3 +181,26 @@ def test_unet_zero_last_layer_is_identity():
     x = _rng(10).normal(size=(1, 8, 8, 8))
     y, _ = oc.unet_forward(params, x, ch)
     np.testing.assert_array_equal(y, x)
+
+
+def test_bf16_round_known_values_and_nearest():
+    """bfloat16 keeps 8 significant bits: near 1 its spacing is 2^-7.
+    Halfway cases go to the even neighbour; otherwise the nearest neighbour,
+    checked against a direct search over the two candidates."""
+    h = 2.0 ** -8
+    vals = np.array([1.0, 1 + h, 1 + 3 * h, 1 + h + 2.0 ** -20, -(1 + 3 * h), 3.0, 2.0 ** -130, 65504.0])
+    want = np.array([1.0, 1.0, 1 + 2 * 2 * h, 1 + 2 * h, -(1 + 4 * h), 3.0, 2.0 ** -130, 65536.0])
+    assert np.array_equal(oc.bf16_round(vals), want)
+    r = np.random.default_rng(5)
+    x = (r.standard_normal(100_000) * np.exp(r.uniform(-20, 20, 100_000))).astype(np.float32)
+    got = oc.bf16_round(x)
+    u = x.view(np.uint32)
+    lo = (u & np.uint32(0xFFFF0000)).view(np.float32).astype(np.float64)  # truncation toward zero
+    step = np.ldexp(1.0, np.frexp(np.abs(lo))[1] - 8)                    # spacing at |lo| (8 significant bits)
+    hi = lo + np.sign(x) * step                                          # next bfloat16 away from zero
+    d_lo, d_hi = np.abs(x.astype(np.float64) - lo), np.abs(hi - x.astype(np.float64))
+    lo_even = ((u >> 16) & 1) == 0
+    pick_lo = (d_lo < d_hi) | ((d_lo == d_hi) & lo_even)
+    assert np.array_equal(got, np.where(pick_lo, lo, hi))
+    # the rounded values are bfloat16 numbers: low 16 bits of their float32 zero
+    assert not (got.astype(np.float32).view(np.uint32) & 0xFFFF).any()
