@@ -89,6 +89,8 @@ def parse():
                          "[:out|truth]' (target: the image after --ws-out sweeps, or the phantom itself)")
     ap.add_argument("--ws-out", type=int, default=20, help="sweeps of the training target")
     ap.add_argument("--ws-channels", type=str, default="16,32,64,64")
+    ap.add_argument("--ws-precision", choices=("f32", "bf16"), default="bf16",
+                    help="the network's convolutions: FP32, or bfloat16 on the matrix cores where the shape allows")
     ap.add_argument("--ws-eval-2e8", action="store_true",
                     help="also compare the starts on the 2e8-history workload (needs a network on the 1-sweep image)")
     ap.add_argument("--ws-eval-seeds", type=str, default="3,2,5000,5001,5002,5003",
@@ -892,7 +894,7 @@ def warmstart_experiment(args):
     for ins, wc, tg in variants:
         pairs = [(wsm.net_input(sn, ins, grid_t), wsm.volume(sn[args.ws_out if tg == "out" else "truth"], grid_t))
                  for sn in train_snaps]
-        net = cnn.UNet3D(channels, device=dev, seed=7, in_channels=len(ins))
+        net = cnn.UNet3D(channels, device=dev, seed=7, in_channels=len(ins), precision=args.ws_precision)
         loss0 = mean_loss(net, pairs)  # the untrained network is the identity on its last input
         losses, train_s = wsm.train(net, pairs, args.ws_steps, args.ws_lr, seed=11, coarse_weight=wc, log=log)
         loss1 = mean_loss(net, pairs)
@@ -1012,7 +1014,8 @@ def warmstart_experiment(args):
                                f"200x200x40 voxels of 1 mm, DROP blocks of 200000, lambda 0.5, rows cached (f32), "
                                f"tiled sweep plan",
                    "network": {"channels": list(channels), "train_phantoms": args.ws_train,
-                               "train_steps": args.ws_steps, "lr": args.ws_lr, "target_sweeps": args.ws_out}},
+                               "train_steps": args.ws_steps, "lr": args.ws_lr, "target_sweeps": args.ws_out,
+                               "precision": args.ws_precision}},
         "training_data_s": round(data_s, 1),
         "hull_start_sweeps_per_phantom": [p["hull_start"]["sweeps_to_1pct"] for p in per_phantom],
         "hull_start_time_to_1pct_s_total": hull_t,
