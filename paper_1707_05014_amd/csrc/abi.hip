@@ -378,6 +378,13 @@ pct_status do_sweep(Ctx &c, const pct_grid *g, const pct_rows *rows, float *x, c
   const pct::PathParams Pb = brick_params(c.P);
   if (!rows) HIPCHECK(pct::launch_to_bricks(Pb, x, c.W.xb, c.Mw, c.s));
   const int kproj = count_mode == 2 ? PCT_K_PROJECT : PCT_K_PROJECT_COUNTING;
+  // the counting sweep adds numerator and count with one packed 64-bit atomic
+  int pk_bits = 0, pk_k = 0;
+  unsigned long long *pk = nullptr;
+  if (count_mode == 1 && !rows && c.W.pk && pct::packed_counts(p->block_size, pk_bits, pk_k)) {
+    pk = c.W.pk;
+    HIPCHECK(pct::launch_fill_u32(reinterpret_cast<uint32_t *>(pk), 2 * c.Mw, 0u, c.s));
+  }
   for (int64_t first = p0, blk = 0; first < p1; first += p->block_size, ++blk) {
     const int64_t count = std::min<int64_t>(p->block_size, p1 - first);
     if (tv) {
@@ -390,18 +397,19 @@ pct_status do_sweep(Ctx &c, const pct_grid *g, const pct_rows *rows, float *x, c
                                                      c.W.num, c.W.cnt, c.W.status, c.s));
     else if (c.recs_ready)
       PROF(kproj, pct::launch_project_fused(Pb, c.W.recs, p->order, first, c.n, true, count, c.W.xb, c.W.num,
-                                            count_mode == 2 ? nullptr : c.W.cnt, c.W.status, c.s));
+                                            count_mode == 2 ? nullptr : c.W.cnt, c.W.status, c.s, pk, pk_bits, pk_k));
     else
       for (int64_t s0 = 0; s0 < count; s0 += c.W.rec_rows) {
         const int64_t cs = std::min<int64_t>(c.W.rec_rows, count - s0);
         PROF(PCT_K_PATH_SETUP, pct::launch_path_setup(c.P, c.H, p->order, first + s0, cs, c.n, c.W.recs,
                                                       c.W.status, false, c.s));
         PROF(kproj, pct::launch_project_fused(Pb, c.W.recs, nullptr, 0, c.n, false, cs, c.W.xb, c.W.num,
-                                              count_mode == 2 ? nullptr : c.W.cnt, c.W.status, c.s));
+                                              count_mode == 2 ? nullptr : c.W.cnt, c.W.status, c.s, pk, pk_bits,
+                                              pk_k));
       }
     PROF(PCT_K_APPLY, pct::launch_apply_counts(x, c.W.num, c.W.cnt, count_mode ? c.W.blk_cnt + blk * c.Mw : nullptr,
                                                count_mode, p->hull_mask, c.M, p->lambda, c.W.status, c.s, touched,
-                                               rows ? nullptr : &Pb, c.W.xb, c.Mw));
+                                               rows ? nullptr : &Pb, c.W.xb, c.Mw, pk, pk_bits, pk_k));
   }
   return PCT_OK;
 }
@@ -715,6 +723,7 @@ size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage
   const size_t stage_b = 2 * align_up((size_t)(stage_slots > 0 ? stage_slots : 0) * 4);
   b += align_up(std::max(plan_b, stage_b));
   b += align_up((size_t)(blk_cnt_elems > 0 ? blk_cnt_elems : 0) * sizeof(uint16_t));
+  if (blk_cnt_elems > 0) b += align_up((size_t)M * sizeof(unsigned long long));
   return b;
 }
 
@@ -762,6 +771,8 @@ Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt
   const size_t stage_b = 2 * align_up((size_t)(stage_slots > 0 ? stage_slots : 0) * 4);
   p += align_up(std::max(plan_b, stage_b));
   w.blk_cnt = blk_cnt_elems > 0 ? reinterpret_cast<uint16_t *>(p) : nullptr;
+  p += align_up((size_t)(blk_cnt_elems > 0 ? blk_cnt_elems : 0) * sizeof(uint16_t));
+  w.pk = blk_cnt_elems > 0 ? reinterpret_cast<unsigned long long *>(p) : nullptr;
   return w;
 }
 

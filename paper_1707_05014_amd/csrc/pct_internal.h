@@ -71,6 +71,7 @@ struct Workspace {
   int32_t *st_idx;       // [stage_slots] staged row entries of one chunk of rows (trace)
   float *st_len;         // [stage_slots]
   uint16_t *blk_cnt;     // [blk_cnt_elems] per-block voxel counts s_j of the fused sweep (or NULL)
+  unsigned long long *pk; // [M] packed numerators and counts of the fused counting sweep (with blk_cnt)
   void *recs;            // [rec_rows] path set-up records (kPathRecBytes each)
   int64_t rec_rows;      // n (one record per history, fused sweeps) or min(n, kStageRows) (chunks)
   void *tvs;             // [tvs_scratch_bytes(M)] TV superiorization scratch (kWsTvs) or NULL
@@ -176,17 +177,34 @@ hipError_t launch_project_cached(const int64_t *row_ptr, const int32_t *idx, con
                                  uint32_t *cnt, uint32_t *status, hipStream_t s);
 // rows of block positions [first, first + count): records recs[order[first + q]]
 // (global: one record per history) or recs[q] (one chunk's records); cnt
-// NULL: the block counts are not formed
+// NULL: the block counts are not formed; pk (with cnt): numerators and counts
+// added as one packed 64-bit integer per entry (count field of pk_bits bits,
+// numerator in units of 2^-pk_k; see packed_counts)
 hipError_t launch_project_fused(const PathParams &P, const void *recs, const int64_t *order, int64_t first, int64_t n,
                                 bool global, int64_t count, const float *x, float *num, uint32_t *cnt,
-                                uint32_t *status, hipStream_t s);
+                                uint32_t *status, hipStream_t s, unsigned long long *pk = nullptr, int pk_bits = 0,
+                                int pk_k = 0);
 // mode 0: counts from cnt (cleared); 1: also store them as uint16 into blk_cnt;
 // 2: counts read from blk_cnt (cnt unused).  Bp (or NULL): num, cnt and
 // blk_cnt are in brick order over Mb voxels, and xb (x in brick order) is
 // kept equal to x
 hipError_t launch_apply_counts(float *x, float *num, uint32_t *cnt, uint16_t *blk_cnt, int mode, const uint8_t *mask,
                                int64_t M, float lambda, uint32_t *status, hipStream_t s, uint8_t *touched = nullptr,
-                               const PathParams *Bp = nullptr, float *xb = nullptr, int64_t Mb = 0);
+                               const PathParams *Bp = nullptr, float *xb = nullptr, int64_t Mb = 0,
+                               unsigned long long *pk = nullptr, int pk_bits = 0, int pk_k = 0);
+// Packed numerator-and-count atomics for blocks of B rows: a voxel's block
+// count is at most B, so a count field of `bits` bits with 2^bits > B never
+// overflows; with contributions below 4 in magnitude (|fixed| < 2^(k + 2))
+// the numerator field (64 - bits, signed) holds any sum of B of them when
+// k + 2 + 2 bits <= 63, and one fixed value fits 32 bits when k <= 29.  Used
+// when k >= 20 (blocks of up to 2^20 - 1 rows).
+inline bool packed_counts(int64_t B, int &bits, int &k) {
+  bits = 1;
+  while (bits < 62 && (int64_t(1) << bits) <= B) ++bits;
+  k = 61 - 2 * bits;
+  if (k > 29) k = 29;
+  return k >= 20;
+}
 // CARP: xs into the per-voxel sums of the strings touching it (touched
 // cleared), then x = mean where some string touched (acc, tc cleared)
 hipError_t launch_carp_accumulate(const float *xs, uint8_t *touched, float *acc, uint16_t *tc, int64_t M,
