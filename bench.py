@@ -429,7 +429,7 @@ def main():
         # The project class holds the sweeps that read the kept block counts
         # (one atomic per entry), project_counting the first sweep (two).
         models["project"] = ("alu", PATH_FLOPS_PER_POINT * points / n_blocks, FP64_PEAK_TFLOPS, "TFLOP/s",
-                             f"pct::k_project_fused<{kpath}, false>")
+                             f"pct::k_project_fused<{kpath}, 0>")
         # the three resources the rebuilt-row projection can be bound by (per
         # launch, one block): FP64 path arithmetic against the vector peak,
         # x gathered from the last-level cache (4 B per entry) and one global
