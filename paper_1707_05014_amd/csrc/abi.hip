@@ -378,10 +378,11 @@ pct_status do_sweep(Ctx &c, const pct_grid *g, const pct_rows *rows, float *x, c
   const pct::PathParams Pb = brick_params(c.P);
   if (!rows) HIPCHECK(pct::launch_to_bricks(Pb, x, c.W.xb, c.Mw, c.s));
   const int kproj = count_mode == 2 ? PCT_K_PROJECT : PCT_K_PROJECT_COUNTING;
-  // the counting sweep adds numerator and count with one packed 64-bit atomic
+  // rebuilt rows: a sweep that forms the block counts adds numerator and
+  // count with one packed 64-bit atomic
   int pk_bits = 0, pk_k = 0;
   unsigned long long *pk = nullptr;
-  if (count_mode == 1 && !rows && c.W.pk && pct::packed_counts(p->block_size, pk_bits, pk_k)) {
+  if (count_mode != 2 && !rows && c.W.pk && pct::packed_counts(p->block_size, pk_bits, pk_k)) {
     pk = c.W.pk;
     HIPCHECK(pct::launch_fill_u32(reinterpret_cast<uint32_t *>(pk), 2 * c.Mw, 0u, c.s));
   }
@@ -723,7 +724,7 @@ size_t workspace_bytes(int64_t M, int64_t n_hist, int64_t plan_bt, int64_t stage
   const size_t stage_b = 2 * align_up((size_t)(stage_slots > 0 ? stage_slots : 0) * 4);
   b += align_up(std::max(plan_b, stage_b));
   b += align_up((size_t)(blk_cnt_elems > 0 ? blk_cnt_elems : 0) * sizeof(uint16_t));
-  if (blk_cnt_elems > 0) b += align_up((size_t)M * sizeof(unsigned long long));
+  if (blk_cnt_elems > 0 || recs_all) b += align_up((size_t)M * sizeof(unsigned long long));
   return b;
 }
 
@@ -772,7 +773,7 @@ Workspace carve_workspace(void *base, int64_t M, int64_t n_hist, int64_t plan_bt
   p += align_up(std::max(plan_b, stage_b));
   w.blk_cnt = blk_cnt_elems > 0 ? reinterpret_cast<uint16_t *>(p) : nullptr;
   p += align_up((size_t)(blk_cnt_elems > 0 ? blk_cnt_elems : 0) * sizeof(uint16_t));
-  w.pk = blk_cnt_elems > 0 ? reinterpret_cast<unsigned long long *>(p) : nullptr;
+  w.pk = (blk_cnt_elems > 0 || recs_all) ? reinterpret_cast<unsigned long long *>(p) : nullptr;
   return w;
 }
 

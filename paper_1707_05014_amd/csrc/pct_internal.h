@@ -71,7 +71,7 @@ struct Workspace {
   int32_t *st_idx;       // [stage_slots] staged row entries of one chunk of rows (trace)
   float *st_len;         // [stage_slots]
   uint16_t *blk_cnt;     // [blk_cnt_elems] per-block voxel counts s_j of the fused sweep (or NULL)
-  unsigned long long *pk; // [M] packed numerators and counts of the fused counting sweep (with blk_cnt)
+  unsigned long long *pk; // [M] packed numerators and counts of fused counting sweeps (fused workspaces)
   void *recs;            // [rec_rows] path set-up records (kPathRecBytes each)
   int64_t rec_rows;      // n (one record per history, fused sweeps) or min(n, kStageRows) (chunks)
   void *tvs;             // [tvs_scratch_bytes(M)] TV superiorization scratch (kWsTvs) or NULL

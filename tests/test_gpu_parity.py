@@ -324,32 +324,46 @@ def test_fused_kept_counts_match_counting(cfg1):
 
 @pytest.mark.parametrize("block,scale", [(100_000, 1.0), (7000, 16.0)], ids=["one-block", "b-x16"])
 def test_fused_packed_counting_sweep(cfg1, block, scale):
-    """The first sweep of a several-sweep fused reconstruction adds each
-    entry's numerator and count with one packed 64-bit atomic (fixed point,
-    2^-27 for a block of 1e5 rows); contributions of 4 or more take separate
-    FP32 and count atomics instead (b x 16 makes many of them).  Against
-    sweeps that count with separate atomics every time, up to rounding."""
+    """A fused sweep that forms the block counts adds each entry's numerator
+    and count with one packed 64-bit atomic (fixed point, 2^-27 for a block
+    of 1e5 rows) when the workspace holds every history's path record;
+    contributions of 4 or more take separate FP32 and count atomics instead (b
+    x 16 makes many of them).  Against the same sweeps with a workspace too
+    small for the records (then every entry takes the separate atomics), up
+    to rounding, and against the oracle."""
     cfg, h, R = cfg1
     h2 = dict(h)
     h2["wepl"] = (h["wepl"] * scale).astype(h["wepl"].dtype)
-    _say(f"fused: packed counting sweep, blocks of {block}, b x {scale}")
+    _say(f"fused: packed counting sweeps, blocks of {block}, b x {scale}")
     order = synth.block_order(cfg.n, cfg.perm_seed)
     mask = synth.hull_mask(cfg)
-    xa, ra = _run_gpu(cfg, h2, "drop", block, 2, order, mask, fused=True)
     grid, geom = pct_args(cfg)
     H = api.Histories.from_numpy(h2)
-    x = torch.from_numpy(mask.astype(np.float32)).cuda()
     p1 = api.sweep_params("drop", block, cfg.lam, 1, order=torch.from_numpy(order).cuda(),
                           hull_mask=torch.from_numpy(mask).cuda())
+    xa = torch.from_numpy(mask.astype(np.float32)).cuda()
     for _ in range(2):
-        api.project_sweep(grid, geom, H, None, x, p1)
-    xb = x.cpu().numpy().astype(np.float64)
-    rel = _rel(xa, xb)
+        api.project_sweep(grid, geom, H, None, xa, p1)  # workspace sized for the fused form: packed
+    lib = _lib.load()
+    small = lib.pct_workspace_size(ctypes.byref(grid), None, None, cfg.n, 0)
+    ws = torch.empty(small, dtype=torch.uint8, device="cuda")
+    xb = torch.from_numpy(mask.astype(np.float32)).cuda()
+    hs = H.struct()
+    for _ in range(2):
+        code = lib.pct_project_sweep(ctypes.byref(grid), ctypes.byref(geom), ctypes.byref(hs), None, xb.data_ptr(),
+                                     ctypes.byref(p1.struct), None, ws.data_ptr(), small,
+                                     torch.cuda.current_stream().cuda_stream)
+        assert code == _lib.PCT_OK
+    torch.cuda.synchronize()
+    ga, gb = xa.cpu().numpy().astype(np.float64), xb.cpu().numpy().astype(np.float64)
+    rel = _rel(ga, gb)
     _say(f"  image rel-L2 packed vs separate atomics: {rel:.2e}")
     assert rel <= 1e-6
-    # and against the oracle
     xo, ro = oracle.drop(R, h2["wepl"], mask.astype(np.float64), order, block, cfg.lam, 2, mask=mask)
-    assert _rel(xa, xo) <= IMG_TOL
+    assert _rel(ga, xo) <= IMG_TOL
+    # the several-sweep reconstruction (block counts kept after the first sweep) agrees too
+    xc, _ = _run_gpu(cfg, h2, "drop", block, 2, order, mask, fused=True)
+    assert _rel(xc, gb) <= 1e-6
 
 
 def test_fused_chunked_setup_matches(cfg1):
