@@ -127,6 +127,12 @@ def mfma_forward_ok(cin, cout):
     return cin % 8 == 0 and cout % 16 == 0
 
 
+def mfma_wgrad_ok(cin, cout):
+    """Shapes the matrix-core weight gradient takes (input and output
+    channels in tiles of sixteen)."""
+    return cin % 16 == 0 and cout % 16 == 0
+
+
 def _conv(x, w, b, bf16):
     cout, cin = w.shape[0], w.shape[1]
     if bf16 and mfma_forward_ok(cin, cout):
@@ -139,6 +145,16 @@ def _conv_bwd_data(g, w, bf16):
     if bf16 and mfma_forward_ok(cout, cin):  # the adjoint is a convolution from cout to cin channels
         return conv3d_bwd_data(bf16_round(g), bf16_round(w))
     return conv3d_bwd_data(g, w)
+
+
+def _conv_bwd_weight(x, g, bf16):
+    """Weight and bias gradients; bf16: where the matrix-core form takes the
+    shape, the weight gradient sees x and g rounded to bfloat16 (the bias
+    gradient sums g unrounded)."""
+    if bf16 and mfma_wgrad_ok(x.shape[0], g.shape[0]):
+        dw, _ = conv3d_bwd_weight(bf16_round(x), bf16_round(g))
+        return dw, np.asarray(g, np.float64).sum(axis=(1, 2, 3))
+    return conv3d_bwd_weight(x, g)
 
 
 def unet_layers(channels, in_ch=1):
@@ -201,8 +217,8 @@ def unet_forward(params, x, channels, bf16=False):
 
 def unet_backward(params, x, channels, tape, dout, bf16=False):
     """Gradients of the parameters (list of (dw, db)) given dL/d(output).
-    bf16: the input gradients that the matrix-core form takes see their
-    operands rounded to bfloat16 (weight gradients stay exact)."""
+    bf16: the input and weight gradients that the matrix-core forms take see
+    their operands rounded to bfloat16 (bias gradients stay exact)."""
     L = len(channels)
     grads = [None] * len(params)
     k = len(params)
@@ -212,9 +228,9 @@ def unet_backward(params, x, channels, tape, dout, bf16=False):
         s, a1, a2 = tape[("dec", lvl)]
         k -= 2
         gz2 = relu_bwd(a2, g) if lvl > 0 else g
-        grads[k + 1] = conv3d_bwd_weight(a1, gz2)
+        grads[k + 1] = _conv_bwd_weight(a1, gz2, bf16)
         ga1 = relu_bwd(a1, _conv_bwd_data(gz2, params[k + 1][0], bf16))
-        grads[k] = conv3d_bwd_weight(s, ga1)
+        grads[k] = _conv_bwd_weight(s, ga1, bf16)
         gs = _conv_bwd_data(ga1, params[k][0], bf16)
         dskips[lvl] += gs
         g = upsample_bwd(gs)  # gradient of the deeper level's output
@@ -225,8 +241,8 @@ def unet_backward(params, x, channels, tape, dout, bf16=False):
             g = dskips[lvl] + pool_bwd(g)
         k -= 2
         gz2 = relu_bwd(a2, g)
-        grads[k + 1] = conv3d_bwd_weight(a1, gz2)
+        grads[k + 1] = _conv_bwd_weight(a1, gz2, bf16)
         ga1 = relu_bwd(a1, _conv_bwd_data(gz2, params[k + 1][0], bf16))
-        grads[k] = conv3d_bwd_weight(h, ga1)
+        grads[k] = _conv_bwd_weight(h, ga1, bf16)
         g = _conv_bwd_data(ga1, params[k][0], bf16)  # gradient of this level's input
     return grads

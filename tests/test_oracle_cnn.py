@@ -204,3 +204,30 @@ def test_bf16_round_known_values_and_nearest():
     assert np.array_equal(got, np.where(pick_lo, lo, hi))
     # the rounded values are bfloat16 numbers: low 16 bits of their float32 zero
     assert not (got.astype(np.float32).view(np.uint32) & 0xFFFF).any()
+
+
+def test_bf16_weight_gradient_reading():
+    """The matrix-core weight gradient's reading: its operands x and g are
+    rounded to bfloat16 where the shape has channel tiles of sixteen, and
+    only there.  Inputs that are bfloat16 numbers already (small integers)
+    give the exact gradients; a shape the form does not take gives them for
+    any input; otherwise the result moves by about the rounding (2^-9
+    relative per operand), and the bias gradient never moves."""
+    r = _rng(12)
+    ints = lambda *sh: r.integers(-8, 9, size=sh).astype(np.float64)
+    x, g = ints(16, 3, 4, 5), ints(32, 3, 4, 5)
+    exact = oc.conv3d_bwd_weight(x, g)
+    got = oc._conv_bwd_weight(x, g, True)
+    np.testing.assert_array_equal(got[0], exact[0])
+    np.testing.assert_array_equal(got[1], exact[1])
+    x8 = r.normal(size=(8, 3, 4, 5))
+    g16 = r.normal(size=(16, 3, 4, 5))
+    for a, b in zip(oc._conv_bwd_weight(x8, g16, True), oc.conv3d_bwd_weight(x8, g16)):
+        np.testing.assert_array_equal(a, b)
+    xr, gr = r.normal(size=(16, 3, 4, 5)), r.normal(size=(16, 3, 4, 5))
+    (dq, bq), (de, be) = oc._conv_bwd_weight(xr, gr, True), oc.conv3d_bwd_weight(xr, gr)
+    np.testing.assert_array_equal(bq, be)
+    dabs, _ = oc.conv3d_bwd_weight(np.abs(xr), np.abs(gr))
+    err = np.abs(dq - de)
+    assert err.max() > 0
+    assert np.all(err <= 2 * 2.0 ** -8 * dabs + 1e-12)
