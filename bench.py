@@ -772,13 +772,20 @@ def cnn_timing(args):
     t = torch.from_numpy(rng.uniform(0, 1.8, size=(1, D, H, W)).astype(np.float32)).to(dev)
 
     def ms(fn, n):
+        # median over 5 repetitions of n calls, timed with events on the
+        # stream: a host-side stall in one repetition does not count
         fn()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(n):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3 / n
+        reps = []
+        for _ in range(5):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(n):
+                fn()
+            b.record()
+            b.synchronize()
+            reps.append(a.elapsed_time(b) / n)
+        return sorted(reps)[2]
 
     out = {"metric": "warm-start network device time", "unit": "ms", "n_gpus": 1, "dtype": "f32",
            "config": {"workload": f"one {W}x{H}x{D} volume, channels {list(channels)}"},
@@ -814,6 +821,10 @@ def cnn_timing(args):
                         "bf16_fwd_tflops": round(flops / f16 / 1e9, 2),
                         "bf16_fwd_frac_of_mfma_peak": round(flops / f16 / 1e9 / 2500.0, 4),
                         "bf16_fwd_hbm_GBps": round(hbm / f16 / 1e6, 1)})
+        if cnn.bf16_wgrad_ok(c, c):
+            bw16 = ms(lambda: cnn.conv3d_bwd_weight(a, y, dw, db, sc, bf16=True), args.steps * 5)
+            rec.update({"bf16_bwd_weight_ms": round(bw16, 4), "bf16_bwd_weight_tflops": round(flops / bw16 / 1e9, 2),
+                        "bf16_bwd_weight_frac_of_mfma_peak": round(flops / bw16 / 1e9 / 2500.0, 4)})
         out["conv"].append(rec)
         dims = tuple(d // 2 for d in dims)
     print(json.dumps(out), flush=True)

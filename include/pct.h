@@ -424,12 +424,20 @@ pct_status pct_cnn_conv3d_bf16(const float *x, const float *w, const float *b, f
                                int32_t cout, int32_t D, int32_t H, int32_t W, void *stream);
 pct_status pct_cnn_conv3d_bwd_data_bf16(const float *dy, const float *w, float *dx, float *wt, void *wpack,
                                         int32_t cin, int32_t cout, int32_t D, int32_t H, int32_t W, void *stream);
-/* floats of scratch that pct_cnn_conv3d_bwd_weight needs */
+/* floats of scratch that pct_cnn_conv3d_bwd_weight and, for the shapes it
+ * takes, pct_cnn_conv3d_bwd_weight_bf16 need */
 int64_t pct_cnn_wgrad_scratch(int32_t cin, int32_t cout, int32_t D, int32_t H, int32_t W);
 /* weight gradient dw [cout][cin][27] and bias gradient db [cout] (or NULL)
  * from the layer input x [cin] and dy [cout]; fixed summation order */
 pct_status pct_cnn_conv3d_bwd_weight(const float *x, const float *dy, float *dw, float *db, float *scratch,
                                      int32_t cin, int32_t cout, int32_t D, int32_t H, int32_t W, void *stream);
+/* The weight gradient on the matrix cores: x and dy rounded to bfloat16
+ * (nearest, ties to even), products accumulated in FP32 in a fixed order;
+ * the bias gradient sums dy unrounded.  Needs cin % 16 == 0, cout % 16 == 0
+ * and D*H*W < 2^27 (else PCT_EINVAL); scratch as above. */
+pct_status pct_cnn_conv3d_bwd_weight_bf16(const float *x, const float *dy, float *dw, float *db, float *scratch,
+                                          int32_t cin, int32_t cout, int32_t D, int32_t H, int32_t W,
+                                          void *stream);
 /* y = max(x, 0); dx = dy where y > 0 (y = the ReLU output) */
 pct_status pct_cnn_relu(const float *x, float *y, int64_t n, void *stream);
 pct_status pct_cnn_relu_bwd(const float *y, const float *dy, float *dx, int64_t n, void *stream);

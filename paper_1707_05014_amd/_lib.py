@@ -80,7 +80,7 @@ EXPORTS = ("pct_workspace_size", "pct_mlp_trace", "pct_project_sweep", "pct_proj
            "pct_plan_residual", "pct_reconstruct", "pct_residual", "pct_roi_stats", "pct_profile_enable",
            "pct_tvs_apply", "pct_carp", "pct_carp_workspace_size", "pct_carve_hull",
            "pct_profile_read", "pct_last_error", "pct_probe", "pct_probe_bytes",
-           "pct_cnn_conv3d", "pct_cnn_conv3d_bwd_data", "pct_cnn_wgrad_scratch", "pct_cnn_conv3d_bwd_weight",
+           "pct_cnn_conv3d", "pct_cnn_conv3d_bwd_data", "pct_cnn_wgrad_scratch", "pct_cnn_conv3d_bwd_weight", "pct_cnn_conv3d_bwd_weight_bf16",
            "pct_cnn_conv3d_bf16_scratch", "pct_cnn_conv3d_bf16", "pct_cnn_conv3d_bwd_data_bf16",
            "pct_cnn_relu", "pct_cnn_relu_bwd", "pct_cnn_pool", "pct_cnn_pool_bwd", "pct_cnn_upsample",
            "pct_cnn_upsample_bwd", "pct_cnn_add", "pct_cnn_axpy", "pct_cnn_mask", "pct_cnn_mse_scratch", "pct_cnn_mse", "pct_cnn_adam")
@@ -162,6 +162,7 @@ def load(path: str | None = None):
         "pct_cnn_conv3d": [_fp, _fp, _fp, _fp, i32, i32, i32, i32, i32, _fp],
         "pct_cnn_conv3d_bwd_data": [_fp, _fp, _fp, _fp, i32, i32, i32, i32, i32, _fp],
         "pct_cnn_conv3d_bwd_weight": [_fp, _fp, _fp, _fp, _fp, i32, i32, i32, i32, i32, _fp],
+        "pct_cnn_conv3d_bwd_weight_bf16": [_fp, _fp, _fp, _fp, _fp, i32, i32, i32, i32, i32, _fp],
         "pct_cnn_conv3d_bf16": [_fp, _fp, _fp, _fp, _fp, i32, i32, i32, i32, i32, _fp],
         "pct_cnn_conv3d_bwd_data_bf16": [_fp, _fp, _fp, _fp, _fp, i32, i32, i32, i32, i32, _fp],
         "pct_cnn_relu": [_fp, _fp, i64, _fp],

@@ -90,17 +90,24 @@ def wgrad_scratch(cin, cout, D, H, W) -> int:
     return int(_lib.load().pct_cnn_wgrad_scratch(cin, cout, D, H, W))
 
 
-def conv3d_bwd_weight(x, dy, dw, db, scratch, stream=None):
-    """dw [cout][cin][27], db [cout] (or None) from the layer input x [cin] and dy [cout]."""
+def bf16_wgrad_ok(cin, cout) -> bool:
+    """Shapes the matrix-core weight gradient takes."""
+    return cin > 0 and cout > 0 and cin % 16 == 0 and cout % 16 == 0
+
+
+def conv3d_bwd_weight(x, dy, dw, db, scratch, stream=None, bf16=False):
+    """dw [cout][cin][27], db [cout] (or None) from the layer input x [cin] and
+    dy [cout]; bf16=True: on the matrix cores (operands rounded to bfloat16,
+    cin and cout multiples of 16)."""
     cin, cout = int(x.shape[0]), int(dy.shape[0])
     D, H, W = _dhw(x)
     if dy.shape[1:] != x.shape[1:] or dw.numel() != cout * cin * 27 or (db is not None and db.numel() != cout):
         raise ValueError("conv3d_bwd_weight: shapes do not match")
     if scratch.numel() < wgrad_scratch(cin, cout, D, H, W):
         raise ValueError("conv3d_bwd_weight: scratch too small")
-    check(_lib.load().pct_cnn_conv3d_bwd_weight(_dev(x, "x"), _dev(dy, "dy"), _dev(dw, "dw"),
-                                                None if db is None else _dev(db, "db"), _dev(scratch, "scratch"),
-                                                cin, cout, D, H, W, _s(stream)))
+    fn = _lib.load().pct_cnn_conv3d_bwd_weight_bf16 if bf16 else _lib.load().pct_cnn_conv3d_bwd_weight
+    check(fn(_dev(x, "x"), _dev(dy, "dy"), _dev(dw, "dw"), None if db is None else _dev(db, "db"),
+             _dev(scratch, "scratch"), cin, cout, D, H, W, _s(stream)))
     return dw
 
 
@@ -226,8 +233,9 @@ class UNet3D:
     """Parameters live in one flat float32 device buffer (weights then bias
     per layer), so gradients and the Adam moments are single buffers too.
     precision "bf16": the convolutions and their input gradients that the
-    matrix-core kernels take (cin % 8 == 0, cout % 16 == 0) run there on
-    bfloat16-rounded operands with FP32 accumulation; weight gradients,
+    matrix-core kernels take (cin % 8 == 0, cout % 16 == 0), and the weight
+    gradients they take (cin % 16 == 0, cout % 16 == 0), run there on
+    bfloat16-rounded operands with FP32 accumulation; bias gradients,
     activations and parameters stay FP32."""
 
     def __init__(self, channels=(16, 32, 64, 64), device="cuda", seed: int = 0, in_channels: int = 1,
@@ -396,7 +404,8 @@ class UNet3D:
             cin, cout = self.shapes[k]
             if relu_out:
                 relu_bwd(act, g, g, stream)
-            conv3d_bwd_weight(inp, g, self.dw[k], self.db[k], scratch, stream)
+            conv3d_bwd_weight(inp, g, self.dw[k], self.db[k], scratch, stream,
+                              bf16=self.precision == "bf16" and bf16_wgrad_ok(cin, cout))
             if k == 0:
                 return None
             gi = self._empty(cin, tuple(int(s) for s in inp.shape[1:]))

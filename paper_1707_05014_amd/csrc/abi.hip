@@ -1304,7 +1304,9 @@ pct_status pct_cnn_conv3d_bwd_data_bf16(const float *dy, const float *w, float *
 
 int64_t pct_cnn_wgrad_scratch(int32_t cin, int32_t cout, int32_t D, int32_t H, int32_t W) {
   if (cin <= 0 || cout <= 0 || D <= 0 || H <= 0 || W <= 0) return 0;
-  return pct::cnn::wgrad_chunks(D, H, W) * cout * ((int64_t)cin * 27 + 1);
+  int64_t parts = pct::cnn::wgrad_chunks(D, H, W);
+  if (pct::cnn::mfma_wgrad_ok(cin, cout)) parts = std::max(parts, pct::cnn::wgrad_mfma_slabs(cin, cout, D, H, W));
+  return parts * cout * ((int64_t)cin * 27 + 1);
 }
 
 pct_status pct_cnn_conv3d_bwd_weight(const float *x, const float *dy, float *dw, float *db, float *scratch,
@@ -1314,6 +1316,20 @@ pct_status pct_cnn_conv3d_bwd_weight(const float *x, const float *dy, float *dw,
   if (cout <= 0) return fail(PCT_EINVAL, "cout must be positive");
   if (!x || !dy || !dw || !scratch) return fail(PCT_EINVAL, "NULL tensor");
   HIPCHECK(pct::cnn::conv3d_wgrad(x, dy, dw, db, scratch, cin, cout, D, H, W, reinterpret_cast<hipStream_t>(stream)));
+  return PCT_OK;
+}
+
+pct_status pct_cnn_conv3d_bwd_weight_bf16(const float *x, const float *dy, float *dw, float *db, float *scratch,
+                                          int32_t cin, int32_t cout, int32_t D, int32_t H, int32_t W, void *stream) {
+  g_err.clear();
+  CNN_VOL_CHECK(cin, D, H, W);
+  if (!pct::cnn::mfma_wgrad_ok(cin, cout))
+    return fail(PCT_EINVAL, "bf16 weight gradient needs cin %% 16 == 0 and cout %% 16 == 0 (got %d, %d)", cin, cout);
+  if ((int64_t)D * H * W >= (int64_t(1) << 27))
+    return fail(PCT_EINVAL, "bf16 weight gradient needs a volume of fewer than 2^27 voxels");
+  if (!x || !dy || !dw || !scratch) return fail(PCT_EINVAL, "NULL tensor");
+  HIPCHECK(pct::cnn::conv3d_wgrad_mfma(x, dy, dw, db, scratch, cin, cout, D, H, W,
+                                       reinterpret_cast<hipStream_t>(stream)));
   return PCT_OK;
 }
 

@@ -488,6 +488,158 @@ __global__ void __launch_bounds__(kMWaves * 64) k_conv3d_mfma(const float *__res
   }
 }
 
+// ---- BF16 matrix-core form of the weight gradient (cin % 16 == 0, cout % 16 == 0)
+//
+// Per tap t, dw[co][ci][t] = sum_p dy[co][p] x[ci][p + off(t)] is a product
+// over the voxels p: one v_mfma_f32_16x16x32_bf16 takes 16 output channels
+// (rows of A: dy) x 16 input channels (columns of B: x shifted by the tap) x
+// the 32 voxels of one row segment along W, lane group g = lane / 16 taking
+// voxels 8g .. 8g + 7 of the segment in both operands.  dy and x are rounded
+// to bfloat16 (nearest, ties to even); products are accumulated in FP32.
+//
+// A workgroup takes one 16 x 16 channel tile and the voxel tiles s, s +
+// nslab, ... (kGTW x kGTH x kGTD voxels: 8 rows of 32) of its slab s.  Per
+// tile it stages in LDS the tile's dy (16 channels x 8 rows, bfloat16 pairs)
+// and the halo of x (16 channels x 24 rows x 34 voxels), the latter as
+// dwords holding the bfloat16 pair (x[w], x[w + 1]): the eight voxels that a
+// lane needs at any shift along W are then four dwords at even distances
+// (no alignment constraint).  Each wavefront takes every fourth tap for all
+// rows, so its accumulators hold finished sums for the slab: it writes
+// part[s][co][ci * 27 + t], the workgroups of channel tile 0 also the bias
+// partial part[s][co][cin * 27] (FP32 sums of the unrounded dy), and
+// k_wgrad_sum_ranges adds the slabs.
+constexpr int kGTW = 32, kGTH = 4, kGTD = 2;
+constexpr int kGRows = kGTH * kGTD;               // 8 rows of 32 voxels
+constexpr int kGHH = kGTH + 2, kGHD = kGTD + 2;   // halo rows: 6 x 4
+constexpr int kGHRows = kGHH * kGHD;              // 24
+constexpr int kGHW = kGTW + 2;                    // halo voxels per row (34)
+constexpr int kGPairs = kGTW + 1;                 // pair dwords per halo row (33)
+constexpr int kGXCh = kGHRows * kGPairs + 1;      // dwords per channel (odd: channels in different banks)
+constexpr int kGDyRow = kGTW / 2;                 // dwords per dy row (16)
+constexpr int kGDyCh = kGRows * kGDyRow + 4;      // dwords per dy channel (16-byte aligned, banks spread)
+constexpr int kGTapsPerWave = (kTaps + kMWaves - 1) / kMWaves;
+constexpr int kGStageDy = 16 * kGRows * kGDyRow / (kMWaves * 64);  // dy pairs per thread and tile (8)
+static_assert(16 * kGRows * kGDyRow % (kMWaves * 64) == 0, "dy staging must split evenly");
+constexpr int kGStageX = 16 * kGHRows * kGHW / (kMWaves * 64);  // x halo values per thread and tile (51)
+constexpr int kGXBatch = 17;
+static_assert(16 * kGHRows * kGHW % (kMWaves * 64) == 0 && kGStageX % kGXBatch == 0, "x staging must split evenly");
+static_assert(kMWaves * 64 / (kGRows * kGDyRow) * kGStageDy == 16, "dy staging: channels per thread");
+
+__global__ void __launch_bounds__(kMWaves * 64) k_wgrad_mfma(const float *__restrict__ x, const float *__restrict__ dy,
+                                                             float *__restrict__ part, int cin, int cout, int D,
+                                                             int H, int W, int tiles_w, int tiles_h, int64_t ntiles) {
+  __shared__ __attribute__((aligned(16))) uint32_t s_x[16 * kGXCh];
+  __shared__ __attribute__((aligned(16))) uint32_t s_dy[16 * kGDyCh];
+  __shared__ float s_red[kMWaves][kGStageDy];
+  const int lane = threadIdx.x & 63, wid = uniform((int)(threadIdx.x >> 6));
+  const int g = lane >> 4, n = lane & 15;
+  const int64_t slab = blockIdx.x, nslab = gridDim.x;
+  const int co0 = blockIdx.y * 16, ci0 = blockIdx.z * 16;
+  const int64_t V = (int64_t)D * H * W;
+  const bool bias = blockIdx.z == 0;
+  uint16_t *s_x16 = reinterpret_cast<uint16_t *>(s_x);
+  f32x4 acc[kGTapsPerWave];
+#pragma unroll
+  for (int m = 0; m < kGTapsPerWave; ++m) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  float bsum[kGStageDy];
+#pragma unroll
+  for (int k = 0; k < kGStageDy; ++k) bsum[k] = 0.0f;
+  for (int64_t tile = slab; tile < ntiles; tile += nslab) {
+    const int w0 = (int)(tile % tiles_w) * kGTW, h0 = (int)((tile / tiles_w) % tiles_h) * kGTH;
+    const int d0 = (int)(tile / ((int64_t)tiles_w * tiles_h)) * kGTD;
+    // x halo: value (c, halo row, hw) -> low half of pair hw and high half of
+    // pair hw - 1; loads in batches of kGXBatch so that they are in flight
+    // together (every lane loads a voxel of the volume, padding then becomes
+    // 0: no branch between the loads)
+#pragma unroll 1
+    for (int k0 = 0; k0 < kGStageX; k0 += kGXBatch) {
+      float v[kGXBatch];
+#pragma unroll
+      for (int u = 0; u < kGXBatch; ++u) {
+        const int task = threadIdx.x + (k0 + u) * kMWaves * 64;
+        const int c = task / (kGHRows * kGHW), rem = task % (kGHRows * kGHW);
+        const int hr = rem / kGHW, hw = rem % kGHW;
+        const int zd = d0 + hr / kGHH - 1, yh = h0 + hr % kGHH - 1, xw = w0 + hw - 1;
+        const bool in = zd >= 0 && zd < D && yh >= 0 && yh < H && xw >= 0 && xw < W;
+        const int zc = min(max(zd, 0), D - 1), yc = min(max(yh, 0), H - 1), xc = min(max(xw, 0), W - 1);
+        const float lv = x[(int64_t)(ci0 + c) * V + ((int64_t)zc * H + yc) * W + xc];
+        v[u] = in ? lv : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < kGXBatch; ++u) {
+        const int task = threadIdx.x + (k0 + u) * kMWaves * 64;
+        const int c = task / (kGHRows * kGHW), rem = task % (kGHRows * kGHW);
+        const int hr = rem / kGHW, hw = rem % kGHW;
+        const uint16_t b = (uint16_t)bf16_rne(v[u]);
+        const int base = c * kGXCh + hr * kGPairs;
+        if (hw < kGPairs) s_x16[2 * (base + hw)] = b;
+        if (hw > 0) s_x16[2 * (base + hw - 1) + 1] = b;
+      }
+    }
+    // dy: pairs of voxels (c, row, 2j .. 2j + 1); thread k-th task: channel 2k + (tid >= 128)
+    float dv[kGStageDy][2];
+#pragma unroll
+    for (int k = 0; k < kGStageDy; ++k) {
+      const int task = threadIdx.x + k * kMWaves * 64;
+      const int c = task / (kGRows * kGDyRow), rem = task % (kGRows * kGDyRow);
+      const int r = rem / kGDyRow, j = rem % kGDyRow;
+      const int zd = d0 + r / kGTH, yh = h0 + r % kGTH, xw = w0 + 2 * j;
+      const bool row_in = zd < D && yh < H;
+      const int64_t rowp = (int64_t)(co0 + c) * V + ((int64_t)min(zd, D - 1) * H + min(yh, H - 1)) * W;
+      const float l0 = dy[rowp + min(xw, W - 1)], l1 = dy[rowp + min(xw + 1, W - 1)];
+      dv[k][0] = (row_in && xw < W) ? l0 : 0.0f;
+      dv[k][1] = (row_in && xw + 1 < W) ? l1 : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < kGStageDy; ++k) {
+      const int task = threadIdx.x + k * kMWaves * 64;
+      const int c = task / (kGRows * kGDyRow), rem = task % (kGRows * kGDyRow);
+      bsum[k] += dv[k][0] + dv[k][1];
+      s_dy[c * kGDyCh + rem] = bf16_rne(dv[k][0]) | (bf16_rne(dv[k][1]) << 16);
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int r = 0; r < kGRows; ++r) {
+      const bf16x8 afr = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(s_dy + n * kGDyCh + r * kGDyRow + 4 * g));
+      const int rh = r % kGTH, rd = r / kGTH;
+#pragma unroll
+      for (int m = 0; m < kGTapsPerWave; ++m) {
+        // the last wavefront has one tap fewer: it repeats tap 26 into an
+        // accumulator it never writes out (no branch in the loop)
+        const int t = min(wid + kMWaves * m, kTaps - 1);
+        const int dz = t / 9 - 1, dyy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+        const int hr = (rd + 1 + dz) * kGHH + (rh + 1 + dyy);
+        const uint32_t *q = s_x + n * kGXCh + hr * kGPairs + 8 * g + dx + 1;
+        const u32x4 bw = {q[0], q[2], q[4], q[6]};
+        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, __builtin_bit_cast(bf16x8, bw), acc[m], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t stride = (int64_t)cin * kTaps + 1;
+#pragma unroll
+  for (int m = 0; m < kGTapsPerWave; ++m) {
+    const int t = wid + kMWaves * m;
+    if (t >= kTaps) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      part[(slab * cout + co0 + 4 * g + i) * stride + (int64_t)(ci0 + n) * kTaps + t] = acc[m][i];
+  }
+  if (bias) {
+#pragma unroll
+    for (int k = 0; k < kGStageDy; ++k) {
+      const float sw = wave_total(bsum[k]);
+      if (lane == 0) s_red[wid][k] = sw;
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) {
+      // channel c = 2k + h is held by wavefronts 2h and 2h + 1
+      const int c = threadIdx.x, k = c >> 1, h = c & 1;
+      part[(slab * cout + co0 + c) * stride + (int64_t)cin * kTaps] = s_red[2 * h][k] + s_red[2 * h + 1][k];
+    }
+  }
+}
+
 static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 hipError_t conv3d(const float *x, const float *w, const float *b, float *y, int cin, int cout, int D, int H, int W,
@@ -559,6 +711,59 @@ hipError_t conv3d_wgrad(const float *x, const float *dy, float *dw, float *db, f
                      dim3(kThreads), 0, s, x, dy, part, cin, cout, D, H, W, tx, ty, ci_per);
   const int64_t n = (int64_t)cout * ((int64_t)cin * kTaps + 1);
   hipLaunchKernelGGL(k_wgrad_sum, dim3(blocks_for(n)), dim3(kThreads), 0, s, part, dw, db, chunks, cin, cout);
+  return hipGetLastError();
+}
+
+// stage 2 of the matrix-core form: element i of the cout x (cin * 27 + 1)
+// gradient summed over the slabs in kSumWaves contiguous ranges (one
+// wavefront each, slabs in order), the ranges then added in order
+constexpr int kSumWaves = 16;
+__global__ void __launch_bounds__(kSumWaves * 64) k_wgrad_sum_ranges(const float *__restrict__ part,
+                                                                     float *__restrict__ dw, float *__restrict__ db,
+                                                                     int64_t chunks, int cin, int cout) {
+  __shared__ float red[kSumWaves][64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t stride = (int64_t)cin * kTaps + 1, nout = (int64_t)cout * stride;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t g0 = chunks * wid / kSumWaves, g1 = chunks * (wid + 1) / kSumWaves;
+  float s = 0.0f;
+  if (i < nout)
+    for (int64_t g = g0; g < g1; ++g) s += part[g * nout + i];
+  red[wid][lane] = s;
+  __syncthreads();
+  if (wid == 0 && i < nout) {
+    float t = 0.0f;
+    for (int w = 0; w < kSumWaves; ++w) t += red[w][lane];
+    const int64_t co = i / stride, j = i % stride;
+    if (j < (int64_t)cin * kTaps)
+      dw[co * cin * kTaps + j] = t;
+    else if (db)
+      db[co] = t;
+  }
+}
+
+bool mfma_wgrad_ok(int cin, int cout) { return cin > 0 && cout > 0 && cin % 16 == 0 && cout % 16 == 0; }
+
+constexpr int64_t kGTargetWgs = 1024;  // workgroups wanted per matrix-core weight-gradient launch
+
+int64_t wgrad_mfma_slabs(int cin, int cout, int D, int H, int W) {
+  const int64_t tiles = (int64_t)ceil_div(W, kGTW) * ceil_div(H, kGTH) * ceil_div(D, kGTD);
+  const int64_t per = (int64_t)(cout / 16) * (cin / 16);
+  if (tiles <= 0 || per <= 0) return 0;
+  return std::max<int64_t>(1, std::min<int64_t>(tiles, (kGTargetWgs + per - 1) / per));
+}
+
+hipError_t conv3d_wgrad_mfma(const float *x, const float *dy, float *dw, float *db, float *part, int cin, int cout,
+                             int D, int H, int W, hipStream_t s) {
+  const int64_t nslab = wgrad_mfma_slabs(cin, cout, D, H, W);
+  if (nslab <= 0) return hipSuccess;
+  const int tw = ceil_div(W, kGTW), th = ceil_div(H, kGTH);
+  const int64_t ntiles = (int64_t)tw * th * ceil_div(D, kGTD);
+  hipLaunchKernelGGL(k_wgrad_mfma, dim3((unsigned)nslab, (unsigned)(cout / 16), (unsigned)(cin / 16)),
+                     dim3(kMWaves * 64), 0, s, x, dy, part, cin, cout, D, H, W, tw, th, ntiles);
+  const int64_t n = (int64_t)cout * ((int64_t)cin * kTaps + 1);
+  hipLaunchKernelGGL(k_wgrad_sum_ranges, dim3((unsigned)((n + 63) / 64)), dim3(kSumWaves * 64), 0, s, part, dw, db,
+                     nslab, cin, cout);
   return hipGetLastError();
 }
 

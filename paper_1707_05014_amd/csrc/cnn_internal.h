@@ -19,6 +19,12 @@ hipError_t conv3d_mfma(const float *x, const float *w, const float *b, float *y,
 int64_t wgrad_chunks(int D, int H, int W);
 hipError_t conv3d_wgrad(const float *x, const float *dy, float *dw, float *db, float *part, int cin, int cout, int D,
                         int H, int W, hipStream_t s);
+// BF16 matrix-core weight gradient (cin % 16 == 0, cout % 16 == 0): part
+// holds wgrad_mfma_slabs(...) x cout x (cin * 27 + 1) floats
+bool mfma_wgrad_ok(int cin, int cout);
+int64_t wgrad_mfma_slabs(int cin, int cout, int D, int H, int W);
+hipError_t conv3d_wgrad_mfma(const float *x, const float *dy, float *dw, float *db, float *part, int cin, int cout,
+                             int D, int H, int W, hipStream_t s);
 hipError_t relu(const float *x, float *y, int64_t n, hipStream_t s);
 hipError_t relu_bwd(const float *y, const float *dy, float *dx, int64_t n, hipStream_t s);
 hipError_t pool(const float *x, float *y, int C, int D, int H, int W, hipStream_t s);

@@ -132,6 +132,10 @@ def test_cnn_args_rejected_on_host():
     assert lib.pct_cnn_conv3d(p, p, None, p, 1, 1, 0, 4, 4, None) == E
     assert lib.pct_cnn_conv3d_bwd_data(p, p, p, None, 1, 1, 4, 4, 4, None) == E
     assert lib.pct_cnn_conv3d_bwd_weight(p, p, p, None, None, 1, 1, 4, 4, 4, None) == E
+    assert lib.pct_cnn_conv3d_bwd_weight_bf16(p, p, p, None, p, 8, 16, 4, 4, 4, None) == E   # cin % 16 != 0
+    assert lib.pct_cnn_conv3d_bwd_weight_bf16(p, p, p, None, p, 16, 24, 4, 4, 4, None) == E  # cout % 16 != 0
+    assert lib.pct_cnn_conv3d_bwd_weight_bf16(p, p, p, None, None, 16, 16, 4, 4, 4, None) == E
+    assert lib.pct_cnn_conv3d_bwd_weight_bf16(p, p, p, None, p, 16, 16, 512, 512, 512, None) == E  # 2^27 voxels
     assert lib.pct_cnn_pool(p, p, 1, 3, 4, 4, None) == E  # odd depth
     assert lib.pct_cnn_pool_bwd(p, p, 1, 4, 5, 4, None) == E
     assert lib.pct_cnn_upsample(None, p, 1, 2, 2, 2, None) == E
@@ -149,6 +153,9 @@ def test_cnn_args_rejected_on_host():
     # scratch sizes
     assert lib.pct_cnn_wgrad_scratch(2, 3, 5, 18, 70) == 2 * 2 * 1 * 3 * (2 * 27 + 1)  # 2 x 2 x 1 tiles
     assert lib.pct_cnn_wgrad_scratch(0, 3, 5, 18, 70) == 0
+    # shapes the matrix-core form takes: room for its slabs of 32 x 4 x 2 voxel
+    # tiles too (here 3 x 5 x 3 = 45 tiles, one slab each, 2 x 1 channel tiles)
+    assert lib.pct_cnn_wgrad_scratch(16, 32, 5, 18, 70) == 45 * 32 * (16 * 27 + 1)
     assert lib.pct_cnn_mse_scratch(257) == 2
 
 

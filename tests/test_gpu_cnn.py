@@ -19,7 +19,11 @@ to the same operands rounded to bfloat16: products of bfloat16 values are
 exact in FP32, so the same FP32-sum bounds apply.  Its shapes leave partial
 16 x 4 x 2 voxel tiles along every axis, a last pass over fewer than 32
 input channels (40 = 32 + 8), and one, two and four 16-channel output tiles
-per workgroup.  A whole network in bfloat16 cannot follow the oracle's
+per workgroup.  The matrix-core weight gradient (32 x 4 x 2 voxel tiles,
+16 x 16 channel tiles) is checked the same way, on shapes that leave
+partial tiles along every axis, one to four channel tiles each way and a
+volume one voxel thick; its bias gradient sums the unrounded dy.  A whole
+network in bfloat16 cannot follow the oracle's
 bfloat16 network bit for bit: the two round activations that differ in their
 last FP32 bits, a rounding that lands on the other neighbour moves that
 value by 2^-8, and the layers after it then round differently too.  So the
@@ -286,6 +290,47 @@ def test_conv3d_bf16_rejects_shapes():
     assert cnn.bf16_scratch(12, 16) == 0 and cnn.bf16_scratch(16, 24) == 0
     with pytest.raises(_lib.PctError) as ei:
         cnn.conv3d(x, w, None, y, wpack=wp)
+    assert ei.value.code == _lib.PCT_EINVAL
+
+
+BF16_WGRAD_SHAPES = [(16, 16, 5, 7, 9), (16, 32, 3, 18, 70), (64, 64, 6, 20, 20), (32, 16, 2, 9, 33),
+                     (48, 32, 4, 5, 17), (16, 16, 1, 4, 200)]
+
+
+@pytest.mark.parametrize("shape", BF16_WGRAD_SHAPES)
+def test_conv3d_bf16_backward_weight(shape):
+    cin, cout, D, H, W = shape
+    _say(f"bf16 conv3d backward weight {shape}")
+    r = np.random.default_rng(33)
+    x, g = _f32(r.normal(size=(cin, D, H, W))), _f32(r.normal(size=(cout, D, H, W)))
+    xq, gq = oc.bf16_round(x), oc.bf16_round(g)
+    dw = torch.empty((cout, cin, 3, 3, 3), dtype=torch.float32, device="cuda")
+    db = torch.empty(cout, dtype=torch.float32, device="cuda")
+    scratch = torch.empty(cnn.wgrad_scratch(cin, cout, D, H, W), dtype=torch.float32, device="cuda")
+    cnn.conv3d_bwd_weight(_dev(x), _dev(g), dw, db, scratch, bf16=True)
+    rw, _ = oc.conv3d_bwd_weight(xq, gq)
+    aw, _ = oc.conv3d_bwd_weight(np.abs(xq), np.abs(gq))
+    _check(_host(dw), rw, aw, what="bf16 dw")
+    _check(_host(db), g.sum(axis=(1, 2, 3)), np.abs(g).sum(axis=(1, 2, 3)), what="bf16 db")
+    # the roundings are there: not the FP32 result
+    dw32 = torch.empty_like(dw)
+    cnn.conv3d_bwd_weight(_dev(x), _dev(g), dw32, None, scratch)
+    assert not torch.equal(dw, dw32)
+    # a second call gives the same bits (fixed summation order)
+    dw2 = torch.empty_like(dw)
+    cnn.conv3d_bwd_weight(_dev(x), _dev(g), dw2, None, scratch, bf16=True)
+    assert torch.equal(dw, dw2)
+
+
+def test_conv3d_bf16_backward_weight_rejects_shapes():
+    _say("bf16 weight gradient shape checks")
+    x = torch.zeros((8, 4, 4, 4), dtype=torch.float32, device="cuda")
+    g = torch.zeros((16, 4, 4, 4), dtype=torch.float32, device="cuda")
+    dw = torch.empty((16, 8, 3, 3, 3), dtype=torch.float32, device="cuda")
+    scratch = torch.empty(cnn.wgrad_scratch(8, 16, 4, 4, 4), dtype=torch.float32, device="cuda")
+    assert not cnn.bf16_wgrad_ok(8, 16) and not cnn.bf16_wgrad_ok(16, 24) and cnn.bf16_wgrad_ok(32, 48)
+    with pytest.raises(_lib.PctError) as ei:
+        cnn.conv3d_bwd_weight(x, g, dw, None, scratch, bf16=True)
     assert ei.value.code == _lib.PCT_EINVAL
 
 
