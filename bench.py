@@ -26,6 +26,7 @@ bounded sample of the same workload on this job's host threads.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -82,18 +83,21 @@ def parse():
                     help="time the warm-start network's kernels on one 200x200x40 volume and exit")
     ap.add_argument("--ws-train", type=int, default=24, help="training phantoms (seeds 1000, 1001, ...)")
     ap.add_argument("--ws-n", type=int, default=10_000_000, help="histories per phantom (training and evaluation)")
-    ap.add_argument("--ws-steps", type=int, default=2000, help="Adam steps (one phantom per step)")
+    ap.add_argument("--ws-steps", type=int, default=3000, help="Adam steps (one phantom per step)")
     ap.add_argument("--ws-lr", type=float, default=1e-3)
-    ap.add_argument("--ws-variants", type=str, default="2:0:truth,2:0:out,1:0:truth",
+    ap.add_argument("--ws-variants", type=str, default="1:0:truth,1:0:clean,2:0:out",
                     help="networks to compare, comma separated: '<input sweeps joined by ->:<coarse-loss weight>"
-                         "[:out|truth]' (target: the image after --ws-out sweeps, or the phantom itself)")
+                         "[:out|truth|clean]' (target: the image after --ws-out sweeps, the phantom itself, or "
+                         "the image after --ws-out sweeps of the same protons without WEPL noise)")
     ap.add_argument("--ws-out", type=int, default=20, help="sweeps of the training target")
+    ap.add_argument("--ws-ensemble", type=int, default=3,
+                    help="networks per variant, trained from different seeds; the warm start is their mean")
     ap.add_argument("--ws-channels", type=str, default="16,32,64,64")
     ap.add_argument("--ws-precision", choices=("f32", "bf16"), default="bf16",
                     help="the network's convolutions: FP32, or bfloat16 on the matrix cores where the shape allows")
     ap.add_argument("--ws-eval-2e8", action="store_true",
                     help="also compare the starts on the 2e8-history workload (needs a network on the 1-sweep image)")
-    ap.add_argument("--ws-eval-seeds", type=str, default="3,2,5000,5001,5002,5003",
+    ap.add_argument("--ws-eval-seeds", type=str, default="3,2,5000,5001",
                     help="held-out phantoms (3: the 2e8 workload's phantom, 2: the 1e7 workload's)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this benchmark and exit")
@@ -860,6 +864,9 @@ def warmstart_experiment(args):
     snaps_needed = sorted({q for ins, _, _ in variants for q in ins} | {args.ws_out})
     last_in = max(q for ins, _, _ in variants for q in ins)
     want_truth = any(tg == "truth" for _, _, tg in variants)
+    want_clean = any(tg == "clean" for _, _, tg in variants)
+    if any(tg not in ("out", "truth", "clean") for _, _, tg in variants):
+        raise SystemExit("--ws-variants: the target is out, truth or clean")
 
     def setup(cfg):
         g = cfg.grid
@@ -892,6 +899,16 @@ def warmstart_experiment(args):
         train_snaps.append(wsm.sweep_snapshots(S["grid"], S["plan"], x, S["params"], snaps_needed))
         if want_truth:
             train_snaps[-1]["truth"] = torch.from_numpy(synth.truth_image(cfg)).to(dev)
+        if want_clean:
+            # the solver's own image after --ws-out sweeps of the same protons
+            # with the WEPL noise left out: converged, and without noise that
+            # no network could predict from its input
+            cc = dataclasses.replace(cfg, beam=dataclasses.replace(cfg.beam, wepl_sigma=0.0))
+            Sc = setup(cc)
+            xc = Sc["mask"].to(torch.float32)
+            train_snaps[-1]["clean"] = wsm.sweep_snapshots(Sc["grid"], Sc["plan"], xc, Sc["params"],
+                                                           [args.ws_out])[args.ws_out]
+            del Sc, xc
         log(f"training phantom {i + 1}/{args.ws_train} (seed {1000 + i}): generated in {S['gen_s']:.1f} s")
         grid_t = S["grid"]
         del S, x
@@ -903,15 +920,27 @@ def warmstart_experiment(args):
 
     nets = []
     for ins, wc, tg in variants:
-        pairs = [(wsm.net_input(sn, ins, grid_t), wsm.volume(sn[args.ws_out if tg == "out" else "truth"], grid_t))
+        pairs = [(wsm.net_input(sn, ins, grid_t), wsm.volume(sn[args.ws_out if tg == "out" else tg], grid_t))
                  for sn in train_snaps]
-        net = cnn.UNet3D(channels, device=dev, seed=7, in_channels=len(ins), precision=args.ws_precision)
-        loss0 = mean_loss(net, pairs)  # the untrained network is the identity on its last input
-        losses, train_s = wsm.train(net, pairs, args.ws_steps, args.ws_lr, seed=11, coarse_weight=wc, log=log)
-        loss1 = mean_loss(net, pairs)
-        log(f"variant {ins}:{wc}:{tg}: trained {args.ws_steps} steps in {train_s:.1f} s; mean training loss "
-            f"{loss0:.4e} (identity) -> {loss1:.4e}")
-        nets.append((ins, wc, tg, net, (loss0, loss1), train_s))
+        members, train_s = [], 0.0
+        for e in range(max(args.ws_ensemble, 1)):
+            net = cnn.UNet3D(channels, device=dev, seed=7 + e, in_channels=len(ins), precision=args.ws_precision)
+            loss0 = mean_loss(net, pairs)  # the untrained network is the identity on its last input
+            losses, t_e = wsm.train(net, pairs, args.ws_steps, args.ws_lr, seed=11 + e, coarse_weight=wc, log=log)
+            loss1 = mean_loss(net, pairs)
+            train_s += t_e
+            log(f"variant {ins}:{wc}:{tg} (network {e + 1}/{max(args.ws_ensemble, 1)}): trained {args.ws_steps} "
+                f"steps in {t_e:.1f} s; mean training loss {loss0:.4e} (identity) -> {loss1:.4e}")
+            members.append((loss1, net))
+        # a member whose training failed (loss near the identity's) would pull
+        # the mean back toward its input: keep the members within 1.5x of the best
+        best = min(l for l, _ in members)
+        kept = [m for l, m in members if l <= 1.5 * best]
+        if len(kept) < len(members):
+            log(f"variant {ins}:{wc}:{tg}: {len(members) - len(kept)} of {len(members)} networks left out "
+                f"(training loss above 1.5x the best)")
+        loss1 = best
+        nets.append((ins, wc, tg, kept if len(kept) > 1 else kept[0], (loss0, loss1), train_s))
         del pairs
     del train_snaps
 
@@ -1012,8 +1041,9 @@ def warmstart_experiment(args):
                         "speedup_vs_hull_start": round(hull_t / tj, 3) if (hull_t and tj) else None,
                         "rel_l2_of_net_output_per_phantom": [p["warm_start"][j]["rel_l2_of_net_output"]
                                                              for p in per_phantom],
+                        "ensemble_members_kept": len(net) if isinstance(net, list) else 1,
                         "train_s": round(train_s, 1),
-                        "train_ms_per_step": round(train_s * 1e3 / max(args.ws_steps, 1), 2),
+                        "train_ms_per_step": round(train_s * 1e3 / max(args.ws_steps * max(args.ws_ensemble, 1), 1), 2),
                         "train_loss_identity": loss0, "train_loss_trained": loss1})
     out = {
         "metric": "time to <= 1% RSP error (learned warm start vs hull start)",
@@ -1026,6 +1056,7 @@ def warmstart_experiment(args):
                                f"tiled sweep plan",
                    "network": {"channels": list(channels), "train_phantoms": args.ws_train,
                                "train_steps": args.ws_steps, "lr": args.ws_lr, "target_sweeps": args.ws_out,
+                               "ensemble": max(args.ws_ensemble, 1),
                                "precision": args.ws_precision}},
         "training_data_s": round(data_s, 1),
         "hull_start_sweeps_per_phantom": [p["hull_start"]["sweeps_to_1pct"] for p in per_phantom],

@@ -44,13 +44,17 @@ def net_input(snapshots: dict, sweeps, grid) -> torch.Tensor:
 
 
 def train(net: "cnn.UNet3D", pairs, steps: int, lr: float = 1e-3, seed: int = 0, coarse_weight: float = 0.0,
-          log=None, log_every: int = 100):
+          log=None, log_every: int = 100, warmup: int | None = None):
     """Adam on the network's loss (MSE plus coarse_weight times the MSE of
     4x4x4 block means) between net(input) and target over `pairs` (list of
     ([in][D][H][W] input, [1][D][H][W] target) device tensors), one pair per
-    step in a seeded shuffled order, learning rate with cosine decay.
-    Returns the per-step voxel MSEs (host floats) and the wall time (s)."""
+    step in a seeded shuffled order, learning rate ramped up linearly over
+    the first warmup steps, then with cosine decay (without the ramp, Adam's
+    first full-size steps now and then leave a network stuck at its identity
+    start).  Returns the per-step voxel MSEs (host floats) and the wall time
+    (s)."""
     rng = np.random.default_rng(seed)
+    warm = max(1, steps // 20) if warmup is None else max(int(warmup), 1)
     order = []
     losses = []
     t0 = time.perf_counter()
@@ -59,6 +63,8 @@ def train(net: "cnn.UNet3D", pairs, steps: int, lr: float = 1e-3, seed: int = 0,
             order = list(rng.permutation(len(pairs)))
         i = order.pop()
         lr_k = lr * 0.5 * (1.0 + math.cos(math.pi * k / max(steps, 1)))
+        if k < warm:
+            lr_k *= (k + 1) / warm
         losses.append(net.loss_and_grad(pairs[i][0], pairs[i][1], coarse_weight))
         net.adam_step(max(lr_k, 1e-3 * lr))
         if log is not None and (k + 1) % log_every == 0:
@@ -67,9 +73,17 @@ def train(net: "cnn.UNet3D", pairs, steps: int, lr: float = 1e-3, seed: int = 0,
     return [float(v.item()) for v in losses], time.perf_counter() - t0
 
 
-def warm_start(net: "cnn.UNet3D", inp: torch.Tensor, hull_mask: torch.Tensor, stream=None) -> torch.Tensor:
+def warm_start(net, inp: torch.Tensor, hull_mask: torch.Tensor, stream=None) -> torch.Tensor:
     """x0 = net(inp) restricted to the hull (a new [M] tensor); inp is the
-    network input built by net_input()."""
-    y = net.predict(inp, stream=stream).view(-1)
+    network input built by net_input().  net may also be a list of networks
+    (an ensemble trained from different seeds): x0 is then the mean of their
+    outputs."""
+    nets = list(net) if isinstance(net, (list, tuple)) else [net]
+    if len(nets) == 1:
+        y = nets[0].predict(inp, stream=stream).view(-1)
+    else:
+        y = torch.zeros(hull_mask.numel(), dtype=torch.float32, device=inp.device)
+        for k in nets:
+            cnn.axpy(1.0 / len(nets), k.predict(inp, stream=stream).view(-1), y, stream=stream)
     cnn.mask(y, hull_mask, y, stream=stream)
     return y
