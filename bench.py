@@ -84,7 +84,7 @@ def parse():
     ap.add_argument("--ws-train", type=int, default=24, help="training phantoms (seeds 1000, 1001, ...)")
     ap.add_argument("--ws-n", type=int, default=10_000_000, help="histories per phantom (training and evaluation)")
     ap.add_argument("--ws-steps", type=int, default=3000, help="Adam steps (one phantom per step)")
-    ap.add_argument("--ws-lr", type=float, default=1e-3)
+    ap.add_argument("--ws-lr", type=float, default=5e-4)
     ap.add_argument("--ws-variants", type=str, default="1:0:truth,1:0:clean,2:0:out",
                     help="networks to compare, comma separated: '<input sweeps joined by ->:<coarse-loss weight>"
                          "[:out|truth|clean]' (target: the image after --ws-out sweeps, the phantom itself, or "
@@ -933,12 +933,12 @@ def warmstart_experiment(args):
                 f"steps in {t_e:.1f} s; mean training loss {loss0:.4e} (identity) -> {loss1:.4e}")
             members.append((loss1, net))
         # a member whose training failed (loss near the identity's) would pull
-        # the mean back toward its input: keep the members within 1.5x of the best
+        # the mean back toward its input: keep the members within 3x of the best
         best = min(l for l, _ in members)
-        kept = [m for l, m in members if l <= 1.5 * best]
+        kept = [m for l, m in members if l <= 3.0 * best]
         if len(kept) < len(members):
             log(f"variant {ins}:{wc}:{tg}: {len(members) - len(kept)} of {len(members)} networks left out "
-                f"(training loss above 1.5x the best)")
+                f"(training loss above 3x the best)")
         loss1 = best
         nets.append((ins, wc, tg, kept if len(kept) > 1 else kept[0], (loss0, loss1), train_s))
         del pairs
