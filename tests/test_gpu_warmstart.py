@@ -37,6 +37,7 @@ EVAL_SEEDS = (3, 2)
 IN_SWEEPS = 2
 OUT_SWEEPS = 20
 STEPS = 600
+LR = 5e-4
 
 
 def _say(msg):
@@ -94,7 +95,7 @@ def test_warm_start_gain():
     for target in ("truth", "out"):
         net = cnn.UNet3D((16, 32, 64, 64), seed=7)
         pairs = [(a, b if target == "out" else c) for a, b, c in train]
-        losses, train_s = wsm.train(net, pairs, STEPS, 1e-3, seed=11)
+        losses, train_s = wsm.train(net, pairs, STEPS, LR, seed=11)
         _say(f"target {target}: trained {STEPS} steps in {train_s:.1f} s: loss {np.mean(losses[:4]):.3e} -> "
              f"{np.mean(losses[-4:]):.3e}")
         assert np.mean(losses[-4:]) < 0.5 * np.mean(losses[:4])
