@@ -135,3 +135,25 @@ def test_warm_start_gain():
     _say(f"sweeps to <= 1% RSP error: {sweeps}")
     assert None not in sweeps["hull"] and None not in sweeps["truth"]
     assert sum(sweeps["truth"]) <= sum(sweeps["hull"])
+
+
+def test_ensemble_warm_start_is_the_mean():
+    """A list of networks gives the mean of their outputs, restricted to the
+    hull (zero outside), as one network gives its own output."""
+    _say("ensemble warm start")
+    r = np.random.default_rng(3)
+    dims = (8, 16, 24)
+    nets = [cnn.UNet3D((16, 32), seed=s) for s in (1, 2, 3)]
+    for k, net in enumerate(nets):  # nonzero last layers, so that the outputs differ
+        params = [(w + r.normal(0, 0.05, size=w.shape), b) for w, b in net.params_numpy()]
+        net.load_params(params)
+    inp = torch.from_numpy(r.uniform(0, 1.8, size=(1,) + dims).astype(np.float32)).cuda()
+    mask = torch.from_numpy((r.uniform(size=int(np.prod(dims))) < 0.7).astype(np.uint8)).cuda()
+    preds = [n.predict(inp).view(-1).double() for n in nets]
+    want = (sum(preds) / len(preds)) * mask.double()
+    got = wsm.warm_start(nets, inp, mask).double()
+    torch.cuda.synchronize()
+    assert float((got - want).abs().max()) <= 1e-6 * float(want.abs().max())
+    one = wsm.warm_start(nets[0], inp, mask).double()
+    assert torch.equal(one, (preds[0] * mask.double()).to(one.dtype))
+    assert float(got[mask == 0].abs().max()) == 0.0
