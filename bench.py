@@ -67,7 +67,9 @@ def parse():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-accuracy", action="store_true")
     ap.add_argument("--skip-variants", action="store_true", help="rebuilt rows: do not also time the FP32-path form")
-    ap.add_argument("--cpu-sample", type=int, default=1_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="histories the CPU oracle runs on (default: 2e6 with rows rebuilt, 3e6 with cached rows, "
+                         "10-20 s of host time)")
     ap.add_argument("--max-sweeps-acc", type=int, default=30)
     ap.add_argument("--warmstart", action="store_true",
                     help="learned warm start: train the 3D U-Net on solver pairs of seeded phantoms, then compare "
@@ -570,7 +572,8 @@ def main():
 
     cpu = None
     if not args.skip_cpu:
-        cpu = cpu_baseline(cfg, args.cpu_sample, fused)
+        n_cpu = args.cpu_sample if args.cpu_sample else (2_000_000 if fused else 3_000_000)
+        cpu = cpu_baseline(cfg, n_cpu, fused)
         log(f"cpu baseline: {cpu}")
 
     rows_kind = "fused" if fused else cfg.rows
