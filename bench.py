@@ -460,7 +460,7 @@ def main():
     avg_ms = tot_ms / launches
     achieved = work / (avg_ms / 1e3) / (1e9 if unit == "GB/s" else 1e12)
     traffic = None
-    tpath = os.path.join(ROOT, "profiles", "traffic_config3.json" if fused else "traffic_config2.json")
+    tpath = os.path.join(ROOT, "profiles", "traffic_fused_head2e8.json" if fused else "traffic_plan_head10M.json")
     if os.path.exists(tpath):
         tj = json.load(open(tpath))
         kk = tj.get("kernels", {}).get(kname)
