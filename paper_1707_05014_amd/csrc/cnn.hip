@@ -387,6 +387,7 @@ constexpr int kMHW = kMTW + 2, kMHH = kMTH + 2, kMHD = kMTD + 2;
 constexpr int kMHalo = kMHW * kMHH * kMHD;  // 432 voxels
 constexpr int kMChunk = 32;                 // input channels staged per pass
 constexpr int kMStride = 2 * kMChunk + 16;  // bytes per halo voxel in LDS
+constexpr int kMStage = 4;                  // staging tasks per thread with their loads in flight together
 
 // float -> bfloat16, round to nearest, ties to even (NaN stays NaN)
 __device__ __forceinline__ uint32_t bf16_rne(float f) {
@@ -430,20 +431,35 @@ __global__ void __launch_bounds__(kMWaves * 64) k_conv3d_mfma(const float *__res
     for (int r = 0; r < kMRowsPerWave; ++r) acc[m][r] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int c0 = 0; c0 < cin; c0 += kMChunk) {
     const int c8n = (cin - c0 < kMChunk ? cin - c0 : kMChunk) / 8;
-    // stage the halo: task (c8, hv), hv fastest
-    for (int task = threadIdx.x; task < c8n * kMHalo; task += kMWaves * 64) {
-      const int c8 = task / kMHalo, hv = task % kMHalo;
-      const int hx = hv % kMHW, hy = (hv / kMHW) % kMHH, hz = hv / (kMHW * kMHH);
-      const int xw = w0 + hx - 1, yh = h0 + hy - 1, zd = d0 + hz - 1;
-      const bool in = xw >= 0 && xw < W && yh >= 0 && yh < H && zd >= 0 && zd < D;
-      const float *xc = x + (int64_t)(c0 + 8 * c8) * V + (in ? ((int64_t)zd * H + yh) * W + xw : 0);
-      float v[8];
+    // stage the halo: task (c8, hv), hv fastest; kMStage tasks per thread
+    // at a time, all their loads issued before any store (a task past the
+    // end loads task 0's voxels and stores nothing)
+    const int ntask = c8n * kMHalo;
+    for (int t0 = threadIdx.x; t0 < ntask; t0 += kMStage * kMWaves * 64) {
+      float v[kMStage][8];
+      bool in[kMStage];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = xc[j * V];
-      u32x4 pk;
+      for (int u = 0; u < kMStage; ++u) {
+        const int task = t0 + u * kMWaves * 64 < ntask ? t0 + u * kMWaves * 64 : 0;
+        const int c8 = task / kMHalo, hv = task % kMHalo;
+        const int hx = hv % kMHW, hy = (hv / kMHW) % kMHH, hz = hv / (kMHW * kMHH);
+        const int xw = w0 + hx - 1, yh = h0 + hy - 1, zd = d0 + hz - 1;
+        in[u] = xw >= 0 && xw < W && yh >= 0 && yh < H && zd >= 0 && zd < D;
+        const float *xc = x + (int64_t)(c0 + 8 * c8) * V + (in[u] ? ((int64_t)zd * H + yh) * W + xw : 0);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) pk[j] = in ? (bf16_rne(v[2 * j]) | (bf16_rne(v[2 * j + 1]) << 16)) : 0u;
-      *reinterpret_cast<u32x4 *>(s_x + hv * kMStride + c8 * 16) = pk;
+        for (int j = 0; j < 8; ++j) v[u][j] = xc[j * V];
+      }
+#pragma unroll
+      for (int u = 0; u < kMStage; ++u) {
+        const int task = t0 + u * kMWaves * 64;
+        if (task >= ntask) break;
+        const int c8 = task / kMHalo, hv = task % kMHalo;
+        u32x4 pk;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          pk[j] = in[u] ? (bf16_rne(v[u][2 * j]) | (bf16_rne(v[u][2 * j + 1]) << 16)) : 0u;
+        *reinterpret_cast<u32x4 *>(s_x + hv * kMStride + c8 * 16) = pk;
+      }
     }
     __syncthreads();
     const int nq = kTaps * c8n;
