@@ -49,15 +49,21 @@ struct ProfScope {
     std::lock_guard<std::mutex> g(g_prof_mu);
     if (!g_prof_on) return;
     a = prof_event();
-    if (a) hipEventRecord(a, s);
+    if (a && hipEventRecord(a, s) != hipSuccess) {  // no timing for this launch
+      g_prof_pool.push_back(a);
+      a = nullptr;
+    }
   }
   void stop() {
     if (!a) return;
     std::lock_guard<std::mutex> g(g_prof_mu);
     hipEvent_t b = prof_event();
-    if (!b) return;
-    hipEventRecord(b, s);
-    g_prof.push_back({kind, a, b});
+    if (b && hipEventRecord(b, s) == hipSuccess) {
+      g_prof.push_back({kind, a, b});
+    } else {
+      g_prof_pool.push_back(a);
+      if (b) g_prof_pool.push_back(b);
+    }
     a = nullptr;
   }
 };
@@ -1174,7 +1180,9 @@ pct_status pct_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> g(g_prof_mu);
   if (on) {
     for (auto &r : g_prof) {
-      hipEventSynchronize(r.b);
+      // the events are reused: wait for the last recorded ones (a failed
+      // wait leaves nothing to do for a timing record that is discarded)
+      (void)hipEventSynchronize(r.b);
       g_prof_pool.push_back(r.a);
       g_prof_pool.push_back(r.b);
     }
@@ -1204,7 +1212,7 @@ pct_status pct_probe(int32_t kind, void *buf, size_t buf_bytes, int64_t region, 
   hipEvent_t a = nullptr, b = nullptr;
   HIPCHECK(hipEventCreate(&a));
   if (hipEventCreate(&b) != hipSuccess) {
-    hipEventDestroy(a);
+    (void)hipEventDestroy(a);
     return fail(PCT_EDEVICE, "hipEventCreate failed");
   }
   hipError_t e = hipEventRecord(a, s);
@@ -1213,8 +1221,8 @@ pct_status pct_probe(int32_t kind, void *buf, size_t buf_bytes, int64_t region, 
   if (e == hipSuccess) e = hipEventSynchronize(b);
   float ms = 0.f;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-  hipEventDestroy(a);
-  hipEventDestroy(b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
   if (e != hipSuccess) return fail(PCT_EDEVICE, "probe: %s", hipGetErrorString(e));
   *ms_out = (double)ms / reps;
   return PCT_OK;
